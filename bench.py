@@ -1,0 +1,176 @@
+"""Benchmark: charge-force evaluations per second of the DP-SE far+near solve.
+
+One step = one complete solve (all stages, far field + near field + energy)
+of the jump workload: N = 16384 monovalent ions in Lx = Ly = 64, H = 32,
+eps = 1 inside, eps_b = eps_t = 0.05, xi = 1, grid 256 x 256 x 129, near
+cutoff 3. Positions and charges are resident in HBM before the timed region.
+
+The headline path is the mixed-precision one (FP32 grid stages, FP64
+per-mode solves and per-charge sums) when its relative RMS force error
+against the FP64 path is <= 1e-5; otherwise the FP64 path.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def stage_bytes(p, info_band_frac, s):
+    """Algorithmic HBM bytes per launch of each grid stage: every stage-boundary
+    array read once and written once (G grid points, C half-spectrum complexes)."""
+    G = p.Nz * p.Ny * p.Nx
+    Cr = 2 * p.Nz * p.Ny * (p.Nx // 2 + 1)
+    b = info_band_frac
+    return {
+        "spread": (1 + b) * G * s,
+        "fft_forward": (1 + b) * (G + Cr) * s,
+        "column": (3 + b) * Cr * s,
+        "fft_inverse": (2 * Cr + 4 * G) * s,
+        "interp": 4 * G * s,
+    }
+
+
+def band_fraction(p, info):
+    z = [0.5 * (info["z_lo"] + info["z_hi"]) + 0.5 * (info["z_hi"] - info["z_lo"]) * math.cos(math.pi * j / (p.Nz - 1))
+         for j in range(p.Nz)]
+    he = info["H_E"]
+    return sum(1 for zz in z if zz < 3 * he or zz > p.H - 3 * he) / p.Nz
+
+
+def time_path(dp, torch, p, tpos, tq, precision, steps, warmup):
+    plan = dp.Plan(p, max_n=len(tq), precision=precision)
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    PH = torch.empty(len(tq), dtype=torch.float64, device="cuda")
+    F = torch.empty((len(tq), 3), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        plan.solve(tpos, tq, E, PH, F)
+    plan.sync()
+    # per-solve latency with events on the plan's (= current) stream
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        evs[k][0].record()
+        plan.solve(tpos, tq, E, PH, F)
+        evs[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = plan.sync_status()
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    # per-stage times over a separate pass (events between stages)
+    plan.set_timing(True)
+    for _ in range(steps):
+        plan.solve(tpos, tq, E, PH, F)
+    stages, _ = plan.stage_times()
+    plan.set_timing(False)
+    plan.sync()
+    out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]),
+               phi=PH.cpu().numpy(), F=F.cpu().numpy(), far=plan.debug(dp.Stage.FAR)[: len(tq)], info=plan.info)
+    plan.close()
+    return out
+
+
+def cpu_baseline(p, pos, q, near_stride=8):
+    """The FP64 CPU oracle on a bounded sample of the same workload: its whole
+    far field on the full system plus its all-pairs near field for every
+    near_stride-th block of 1024 target charges; the near time is scaled by
+    the inverse of the sampled fraction."""
+    from oracle import dpse_oracle as O
+    threads = os.cpu_count() or 1
+    tm = {}
+    O.solve(p, pos, q, timings=tm, near_rows=near_stride)
+    n = len(q)
+    chunks = (n + 1023) // 1024
+    frac = len(range(0, chunks, near_stride)) / chunks
+    t = tm["far"] + tm["near"] / frac
+    return {"value": n / t, "unit": "charge-force evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle: far field of the full workload ({tm['far']:.1f} s) + all-pairs near "
+                      f"field for {frac:.3f} of the targets ({tm['near']:.1f} s, scaled to all); "
+                      f"estimated full solve {t:.1f} s"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["auto", "fp64", "mixed"], default="auto")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
+              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+    import paper_2101_07088_amd as dp
+    import workloads as W
+
+    p, pos, q = W.config_jump(a.seed)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    n = len(q)
+    res = {}
+    for prec in (["fp64", "mixed"] if a.precision == "auto" else [a.precision]):
+        res[prec] = time_path(dp, torch, p, tpos, tq, dp.DPSE_FP64 if prec == "fp64" else dp.DPSE_MIXED,
+                              a.steps, a.warmup)
+        print(f"[bench] {prec}: {1e3 * res[prec]['wall_s'] / a.steps:.3f} ms/solve, stages "
+              + ", ".join(f"{k}={v:.3f}" for k, v in res[prec]["stages"].items()), file=sys.stderr, flush=True)
+    acc = {}
+    head = "fp64" if "fp64" in res else "mixed"
+    if "fp64" in res and "mixed" in res:
+        F64, Fm = res["fp64"]["F"], res["mixed"]["F"]
+        err = float(np.sqrt(np.sum((Fm - F64) ** 2) / np.sum(F64 ** 2)))
+        ffar64 = q[:, None] * res["fp64"]["far"][:, 1:]
+        ffarm = q[:, None] * res["mixed"]["far"][:, 1:]
+        errfar = float(np.sqrt(np.sum((ffarm - ffar64) ** 2) / np.sum(ffar64 ** 2)))
+        acc = {"mixed_vs_fp64_rel_rms_force": err, "mixed_vs_fp64_rel_rms_far_force": errfar,
+               "mixed_vs_fp64_rel_energy": abs(res["mixed"]["U"] - res["fp64"]["U"]) / abs(res["fp64"]["U"])}
+        head = "mixed" if err <= 1e-5 else "fp64"
+    r = res[head]
+    ms = 1e3 * r["wall_s"] / a.steps
+    value = n / (r["wall_s"] / a.steps)
+    s_bytes = 4 if head == "mixed" else 8
+    bfrac = band_fraction(p, r["info"])
+    sb = stage_bytes(p, bfrac, s_bytes)
+    dom = max(sb, key=lambda k: r["stages"][k])
+    t_dom = r["stages"][dom] * 1e-3
+    achieved = sb[dom] / t_dom / 1e9
+    line = {
+        "metric": "charge-force evals/s at <=1e-5 rel RMS force err vs FP64; p50/p99 solve ms",
+        "value": value, "unit": "charge-force evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": "jump: N=16384 +-1 ions, Lx=Ly=64, H=32, eps=1, eps_b=eps_t=0.05, xi=1.0, "
+                               "grid 256x256x129, r_cut=3.0, seed %d" % a.seed,
+                   "precision": head, "parallelism": "single GPU"},
+        "p50_ms": float(np.percentile(r["lat_ms"], 50)), "p99_ms": float(np.percentile(r["lat_ms"], 99)),
+        "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
+        "accuracy": acc,
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    for prec, rr in res.items():
+        line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / a.steps)
+        line[f"{prec}_p50_ms"] = float(np.percentile(rr["lat_ms"], 50))
+        line[f"{prec}_p99_ms"] = float(np.percentile(rr["lat_ms"], 99))
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(p, pos, q)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

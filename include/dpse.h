@@ -1,0 +1,188 @@
+/*
+ * dpse.h -- C ABI of the doubly-periodic spectral Ewald (DP-SE) solver for
+ * MI355X (gfx950).
+ *
+ * The library computes, for N charges q_k at positions z_k in a slab
+ * 0 < z < H that is periodic in x (period Lx) and y (period Ly), with
+ * permittivity eps inside, eps_bottom below z = 0 and eps_top above z = H:
+ *   - the energy U = 1/2 sum_k q_k phibar_k            (paper Sec. 2, eq. Ufinal),
+ *   - the averaged potential phibar_k at each charge     (eq. pbar), and
+ *   - the force F_k = q_k Ebar(z_k)                      (eq. fqE),
+ * with the Poisson equation eps*Lap(phi) = -rho (eq. poiss) and the jump
+ * conditions of eqs. cbc1-cbc4 (no wall charges). The method is the paper's
+ * Ewald split (Sec. 3.2) into a localized near field summed over pairs
+ * (Sec. 4.2) and a smooth far field solved on a grid that is Fourier in x,y
+ * and Chebyshev in z, with images of charges near the walls and a harmonic
+ * correction for the rest of the image series (Sec. 4.3, algorithm of
+ * Sec. 5.2.2 steps 1-7, per-mode boundary value solver of App. A).
+ *
+ * Units: a point charge q at distance r in a uniform medium has potential
+ * q/(4 pi eps r). The set of charges must be exactly neutral (Sec. 7).
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - g_w = 0 gives point charges; the self potential of each charge is
+ *     removed as in Sec. 6.3, so phibar and U are finite;
+ *   - support n_g = 2*ceil(4.3*g_t/h) grid cells unless given (Sec. 5.1);
+ *   - z grid: Gauss-Lobatto Chebyshev nodes on [-3 H_E, H + 3 H_E] (Sec. 5.2.2);
+ *   - gauge phi(0) = 0 (eq. phi00, Sec. 5.2.2) unless DPSE_GAUGE_NONE;
+ *   - near field: pairs with minimal-image distance r < r_cut, one image of
+ *     every charge per wall (Sec. 4.2, 5.2.2).
+ *
+ * Streams and ownership. All position, charge and output pointers are DEVICE
+ * pointers owned by the caller (e.g. torch.Tensor.data_ptr() of float64 HIP
+ * tensors). The plan owns its workspace. dpse_solve only enqueues work on
+ * the plan's HIP stream and returns; the caller's buffers must stay valid
+ * until that stream has passed the solve. A plan is not thread safe and must
+ * not run two solves concurrently. Data-dependent errors (charge outside the
+ * slab, non-neutral set, constraint violated) are detected on the device and
+ * returned by the next dpse_sync; outputs of such a solve are undefined.
+ */
+#ifndef DPSE_H
+#define DPSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (every entry point returns one; 0 is success). */
+enum {
+  DPSE_OK = 0,
+  DPSE_EINVAL = 1,      /* invalid argument or parameters                        */
+  DPSE_ENOMEM = 2,      /* device allocation failed                              */
+  DPSE_EHIP = 3,        /* a HIP runtime call failed                             */
+  DPSE_ENONNEUTRAL = 4, /* |sum q| > 1e-12 sum |q|  (device-detected)            */
+  DPSE_EOUTSIDE = 5,    /* a charge with z outside (n_sigma g_w, H - n_sigma g_w), or a non-finite coordinate (device-detected) */
+  DPSE_ECONSTRAINT = 6, /* r_cut >= H + h_min or 2 H_E >= H + h_min, h_min the smallest distance of a charge to a wall (Sec. 4.2, 5.3; device-detected) */
+  DPSE_ETOOMANY = 7     /* n larger than the plan's max_n                        */
+};
+
+/* Precision of the grid stages. */
+enum {
+  DPSE_FP64 = 0,  /* every stage in FP64                                          */
+  DPSE_MIXED = 1  /* spreading, x,y FFTs, interpolation, near field in FP32 with FP32
+                     accumulation; z transforms, per-mode solves, harmonic
+                     correction, k = 0 mode and all per-charge sums in FP64    */
+};
+
+/* Flags (bitwise or). */
+enum {
+  DPSE_GAUGE_NONE = 1, /* skip the phi(0) = 0 gauge constant (U and F unaffected for neutral sets) */
+  DPSE_KMAX_GT = 2     /* cap the harmonic correction at |k| <= min(pi/h, 4.2/g_t) instead of pi/h */
+};
+
+/* Parameters of one slab system. Lengths share one unit. */
+typedef struct {
+  double Lx, Ly, H;                 /* periods in x,y; slab height; > 0                      */
+  double eps, eps_bottom, eps_top;  /* permittivities; > 0                                   */
+  double xi;                        /* Ewald splitting parameter (eq. gamreal); > 0          */
+  double g_w;                       /* Gaussian charge width (eq. gcharge); >= 0             */
+  int32_t Nx, Ny, Nz;               /* grid; Nx, Ny powers of two in [8, 1024]; Nz - 1 a power of two in [4, 1024]; Lx/Nx == Ly/Ny */
+  int32_t support;                  /* n_g, even, 0 = 2*ceil(4.3*g_t/h); n_g <= min(Nx, Ny)  */
+  double r_cut;                     /* near cutoff, 0 < r_cut < min(Lx, Ly)/2; 0 = derive from delta (eq. rnf) */
+  double delta;                     /* tolerance used when r_cut == 0 (default 1e-4 if 0)    */
+  int32_t precision;                /* DPSE_FP64 or DPSE_MIXED                               */
+  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT                        */
+} dpse_params;
+
+/* Derived quantities of a plan (Sec. 3.2 eq. gt, Sec. 5.1 eq. He, Sec. 5.2.2). */
+typedef struct {
+  double h;            /* grid spacing in x and y                                 */
+  double g_t;          /* std of the spreading Gaussian S-bar                     */
+  double H_E;          /* support radius n_g h / 2                                */
+  double n_sigma;      /* H_E / g_t                                               */
+  double z_lo, z_hi;   /* Chebyshev domain [-3 H_E, H + 3 H_E]                    */
+  double r_cut;        /* near cutoff actually used                              */
+  double xi_e;         /* (4 g_w^2 + xi^-2)^(-1/2)                                */
+  int32_t support;     /* n_g                                                      */
+  int32_t n_modes;     /* Ny (Nx/2 + 1) transverse modes                          */
+  int64_t workspace_bytes; /* device memory owned by the plan (0 from dpse_derive) */
+  int64_t max_n;       /* charges per solve the plan accepts (0 from dpse_derive)  */
+} dpse_info;
+
+typedef struct dpse_plan dpse_plan;
+
+/* Validates params and fills info without touching the GPU (host only).
+ * Returns DPSE_EINVAL (with info untouched) for invalid parameters. */
+int dpse_derive(const dpse_params* params, dpse_info* info);
+
+/* Creates a plan for up to max_n charges per solve on the HIP stream `stream`
+ * (a hipStream_t; NULL = the null stream) of the current device. Allocates the
+ * workspace and uploads the plan tables (nodes, quadrature weights, wave
+ * numbers). *out receives the plan. */
+int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out);
+
+/* Copies the derived quantities of a plan into *info. */
+int dpse_plan_info(const dpse_plan* plan, dpse_info* info);
+
+/* Enqueues one solve (Sec. 5.2.2 steps 1-7 plus the near field).
+ *   n      number of charges, 1 <= n <= max_n;
+ *   pos    device, n x 3 row-major float64 (x, y, z); x, y are taken modulo Lx, Ly;
+ *   q      device, n float64 charges;
+ *   energy device, 1 float64, or NULL;
+ *   phi    device, n float64 averaged potentials, or NULL;
+ *   force  device, n x 3 row-major float64 forces, or NULL.
+ * Outputs are in the caller's charge order. Host-detectable errors return
+ * immediately (DPSE_EINVAL, DPSE_ETOOMANY); data errors appear at dpse_sync. */
+int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
+               double* energy, double* phi, double* force);
+
+/* Enqueues n_sys independent solves (one per plan, each with its own sizes and
+ * parameters) as one batch. Array arguments have n_sys entries with the
+ * meaning of dpse_solve's. Plans may share a stream; the batch is ordered on
+ * the stream of plans[0], and every other plan's stream waits for it. */
+int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
+                     const double* const* pos, const double* const* q,
+                     double* const* energy, double* const* phi, double* const* force);
+
+/* Waits for the plan's stream and returns the device-side status of the
+ * solves enqueued since the previous dpse_sync (DPSE_OK, DPSE_ENONNEUTRAL,
+ * DPSE_EOUTSIDE or DPSE_ECONSTRAINT), clearing it. */
+int dpse_sync(dpse_plan* plan);
+
+/* Frees the plan and its workspace (waits for its stream first). */
+int dpse_plan_destroy(dpse_plan* plan);
+
+/* Static description of a status code. */
+const char* dpse_status_string(int status);
+
+/* Stage outputs kept in the workspace after a solve, for per-stage checks.
+ * dpse_debug_copy waits for the plan's stream and copies stage `which` into
+ * host memory `dst` (at most `bytes` bytes); *elem_bytes receives the size of
+ * one real (8 or 4) and *count the number of reals copied. Layouts:
+ *   DPSE_STAGE_F_I    spread grid of all charges and images, [Nz][Ny][Nx]
+ *   DPSE_STAGE_F_O    spread grid of the wall-band charges, [Nz][Ny][Nx] (zero outside the bands)
+ *   DPSE_STAGE_FH_I   x,y transform of F_I, complex [Nz][Ny][Nx/2+1] (re, im interleaved)
+ *   DPSE_STAGE_PSI    potential at the nodes per mode, complex [Nz][Ny][Nx/2+1]
+ *   DPSE_STAGE_PSIZ   z-derivative of it, complex [Nz][Ny][Nx/2+1]
+ *   DPSE_STAGE_GRIDS  phi, Ex, Ey, Ez on the grid, [Nz][Ny][Nx][4]
+ *   DPSE_STAGE_FAR    far-field averages at the charges (phi, Ex, Ey, Ez), [n][4], caller order
+ *   DPSE_STAGE_NEAR   near-field sums at the charges (phi, Ex, Ey, Ez), [n][4], caller order
+ *   DPSE_STAGE_SCALARS (B_i, A_i, far part at the origin, near part at the origin), FP64 */
+enum {
+  DPSE_STAGE_F_I = 0, DPSE_STAGE_F_O = 1, DPSE_STAGE_FH_I = 2, DPSE_STAGE_PSI = 3,
+  DPSE_STAGE_PSIZ = 4, DPSE_STAGE_GRIDS = 5, DPSE_STAGE_FAR = 6, DPSE_STAGE_NEAR = 7,
+  DPSE_STAGE_SCALARS = 8
+};
+int dpse_debug_copy(dpse_plan* plan, int which, void* dst, int64_t bytes,
+                    int32_t* elem_bytes, int64_t* count);
+
+/* Per-stage device timing. The paper reports the time of each stage of a
+ * solve (Sec. 7.4: correction, spreading, near field, interpolation,
+ * transforms, boundary value solves). With timing on, every solve records HIP
+ * events between its stages on the plan's stream (no synchronization is
+ * added). dpse_stage_times waits for the stream, writes the mean duration in
+ * milliseconds of each stage over the solves recorded since the previous call
+ * into ms[0 .. min(max_stages, DPSE_NUM_STAGES)), sets *n_solves, and clears
+ * the record. Stage names come from dpse_stage_name. */
+enum { DPSE_NUM_STAGES = 10 };
+int dpse_set_timing(dpse_plan* plan, int enable);
+int dpse_stage_times(dpse_plan* plan, double* ms, int max_stages, int* n_solves);
+const char* dpse_stage_name(int stage);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPSE_H */

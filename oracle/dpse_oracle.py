@@ -361,10 +361,12 @@ def near_kernel(r, p, xi_e):
     return G, -dG / r
 
 
-def near_field(p, d, pos, q, chunk=1024):
+def near_field(p, d, pos, q, chunk=1024, rows=None):
     """For each charge k: sum over charges j != k and over the bottom/top
     images of all j (strengths gamma_b q_j, gamma_t q_j, at (x,y,-z) and
-    (x,y,2H-z)) with minimal-image distance r < r_cut. Returns [n, 4]."""
+    (x,y,2H-z)) with minimal-image distance r < r_cut. Returns [n, 4].
+    ``rows`` (a slice step) restricts the targets to every rows-th chunk of
+    ``chunk`` charges (the others stay 0); used only to time a sample."""
     n = len(q)
     out = np.zeros((n, 4))
     srcs = [(pos, q, True)]
@@ -372,7 +374,7 @@ def near_field(p, d, pos, q, chunk=1024):
         srcs.append((np.stack([pos[:, 0], pos[:, 1], -pos[:, 2]], 1), d["gamma_b"] * q, False))
     if d["gamma_t"] != 0.0:
         srcs.append((np.stack([pos[:, 0], pos[:, 1], 2 * p.H - pos[:, 2]], 1), d["gamma_t"] * q, False))
-    for t0 in range(0, n, chunk):
+    for t0 in range(0, n, chunk * (rows or 1)):
         ts = slice(t0, min(n, t0 + chunk))
         tp = pos[ts]
         for sp, sq, exclude_self in srcs:
@@ -426,7 +428,11 @@ def near_at_origin(p, d, pos, q):
 # The whole solve (Sec. 5.2.2 steps 1-7, field paragraph, gauge paragraph)
 # ---------------------------------------------------------------------------
 
-def solve(p, pos, q) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarray]]:
+def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarray]]:
+    """The whole solve. ``timings`` (a dict) receives wall seconds of the far
+    and near parts; ``near_rows`` is passed to near_field (timing samples only)."""
+    import time
+    t_start = time.perf_counter()
     pos = np.asarray(pos, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     d = derive(p)
@@ -496,7 +502,9 @@ def solve(p, pos, q) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarra
     grids = np.stack([ifft_xy(Psi, p), ifft_xy(Ex_h, p), ifft_xy(Ey_h, p), ifft_xy(Ez_h, p)])
     # step 7: interpolate (average) at the charges
     far = interp(p, d, grids, pos)
-    near = near_field(p, d, pos, q)
+    t_near = time.perf_counter()
+    near = near_field(p, d, pos, q, rows=near_rows)
+    t_near = time.perf_counter() - t_near
     # gauge phi(0) = 0 (Sec. 5.2.2): pointwise near + gamma^{1/2}-averaged far at the origin
     if p.gauge:
         xi = p.xi
@@ -514,6 +522,9 @@ def solve(p, pos, q) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarra
     E = far[:, 1:] + near[:, 1:]
     F = q[:, None] * E
     U = 0.5 * float(np.sum(q * phi))
+    if timings is not None:
+        timings["near"] = t_near
+        timings["far"] = time.perf_counter() - t_start - t_near
     inter = dict(f_o=f_o, f_i=f_i, F_o=F_o, F_i=F_i, fh_o=fh_o, fh_i=fh_i,
                  y_o=y_o, y_i=y_i, mphi_b=mphi_b, mE_b=mE_b, mphi_t=mphi_t, mE_t=mE_t,
                  alpha=alpha, beta=beta, A_i=A_i, A_i1=A_i1, A_i2=A_i2, Psi=Psi,

@@ -1,0 +1,147 @@
+// Internal declarations of the DP-SE library: plan constants passed to every
+// kernel, the plan/workspace layout, and the launch wrappers of each stage.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "dpse.h"
+
+namespace dpse {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Plan constants, passed by value as a kernel argument.
+struct Geom {
+  double Lx, Ly, H, eps, eps_b, eps_t, xi, g_w;
+  double h, inv_h, g_t, H_E, za, zb, zc, zR;
+  double gamma_b, gamma_t, tau_b, tau_t, xi_e, r_cut;
+  double sbar_norm;  // (2 pi g_t^2)^(-3/2)
+  double inv2g2;     // 1/(2 g_t^2)
+  double zmin_ok, zmax_ok;  // admissible charge heights (exclusive bounds)
+  int Nx, Ny, Nz, nkx, ng, flags;
+  // particle bins used by spreading and interpolation
+  int B;                 // bin width in grid cells (x and y)
+  int nbx, nby, nzb;     // bins in x, y; z buckets
+  double zb_lo, zb_w;    // z bucket origin and width
+  // near-field cell list
+  int ncx, ncy, ncz;
+  double cwx, cwy, cwz;
+  // wall bands of the psi_o* solve: nodes [0, top_end) and [bot_begin, Nz)
+  int top_end, bot_begin;
+};
+
+// One particle record: position and strength.
+struct Part {
+  double x, y, z, q;
+};
+
+// Group of an extended particle (charge or image), stored in meta & 3.
+enum { GRP_WALL = 0, GRP_INNER = 1, GRP_IMAGE = 2 };
+
+// Launch shapes.
+constexpr int kSpreadT = 32;  // spreading tile (grid cells per side)
+constexpr int kInterpT = 16;  // interpolation tile
+constexpr int kBin = 16;      // particle bin width (grid cells)
+
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<double> { using T = double2; };
+template <>
+struct Cplx<float> { using T = float2; };
+
+struct Workspace {
+  // particles
+  Part* ext = nullptr;        // [3 max_n] charges then images
+  int* ext_meta = nullptr;    // group | (original index << 2)
+  Part* srt = nullptr;        // sorted by (bin, z bucket)
+  int* srt_meta = nullptr;
+  int* bin_cnt = nullptr;     // [nkeys + 1]
+  int* bin_off = nullptr;     // [nkeys + 1]
+  int* bin_cur = nullptr;     // [nkeys]
+  int* n_img = nullptr;       // [1]
+  // near-field cell list over the charges
+  Part* nsrt = nullptr;       // [max_n]
+  int* nsrt_idx = nullptr;    // original index
+  int* cell_cnt = nullptr;
+  int* cell_off = nullptr;
+  int* cell_cur = nullptr;
+  // grids (R = double or float, C = complex of R)
+  void* f_i = nullptr;   // R [Nz][Ny][Nx]
+  void* f_o = nullptr;   // R [Nz][Ny][Nx], band planes only
+  void* fx_i = nullptr;  // C [Nz][Ny][nkx]
+  void* fx_o = nullptr;  // C [Nz][Ny][nkx], band planes only
+  void* psi = nullptr;   // C [Nz][Ny][nkx]
+  void* psiz = nullptr;  // C
+  void* p0 = nullptr;    // C inverse y-pass outputs
+  void* py = nullptr;    // C
+  void* pz = nullptr;    // C
+  void* u4 = nullptr;    // R [Nz][Ny][Nx][4]
+  // per-charge accumulators (caller order)
+  double4* far4 = nullptr;
+  double4* near4 = nullptr;
+  // scalars: 0 sum q, 1 sum |q|, 2 B_i, 3 A_i, 4 far0, 5 near0, 6 energy scratch
+  double* scal = nullptr;
+  double* partials = nullptr;  // block partial sums
+  int* status = nullptr;
+};
+
+struct Tables {
+  double* z = nullptr;      // nodes [Nz]
+  double* wq = nullptr;     // h^2 * Clenshaw-Curtis weight [Nz]
+  double* T0 = nullptr;     // T_n(s(0)) [Nz]
+  double* TH = nullptr;     // T_n(s(H))
+  double* dT0 = nullptr;    // T_n'(s(0)) / R
+  double* dTH = nullptr;    // T_n'(s(H)) / R
+  double2* twx = nullptr;   // exp(-2 pi i k/Nx), k < Nx/2
+  double2* twy = nullptr;   // exp(-2 pi i k/Ny)
+  double2* twz = nullptr;   // exp(-2 pi i k/(2(Nz-1)))
+  float2* twx_f = nullptr;
+  float2* twy_f = nullptr;
+};
+
+}  // namespace dpse
+
+struct dpse_plan {
+  dpse_params prm;
+  dpse_info info;
+  dpse::Geom g;
+  dpse::Tables t;
+  dpse::Workspace w;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int64_t max_n = 0;
+  int64_t last_n = 0;
+  int nkeys = 0;
+  int ncells = 0;
+  int npartials = 0;
+  std::vector<void*> allocs;
+  // per-stage timing: one row of DPSE_NUM_STAGES + 1 events per recorded solve
+  bool timing = false;
+  std::vector<hipEvent_t> events;
+  int timed_solves = 0;
+};
+
+namespace dpse {
+
+// Stage launchers (each enqueues on plan->stream). R = double or float.
+hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double* q);
+hipError_t launch_bin(dpse_plan* p, int64_t n);
+template <typename R> hipError_t launch_spread(dpse_plan* p);
+template <typename R> hipError_t launch_fft_forward(dpse_plan* p);
+template <typename R> hipError_t launch_column(dpse_plan* p);
+template <typename R> hipError_t launch_fft_inverse(dpse_plan* p);
+template <typename R> hipError_t launch_interp(dpse_plan* p, int64_t n);
+template <typename R> hipError_t launch_near(dpse_plan* p, int64_t n);
+template <typename R> hipError_t launch_gauge(dpse_plan* p, int64_t n);
+hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
+                           double* phi, double* force);
+
+// Small helpers.
+hipError_t fill_int(int* ptr, int value, int64_t count, hipStream_t s);
+hipError_t fill_double(double* ptr, double value, int64_t count, hipStream_t s);
+
+}  // namespace dpse

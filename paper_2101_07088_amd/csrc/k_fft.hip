@@ -1,0 +1,282 @@
+// x,y Fourier transforms of the grids (Sec. 5.2.1 steps 2 and 5).
+// Forward: F(k, z_c) = (1/(Nx Ny)) sum_ij f e^{-i(kx x_i + ky y_j)} as an R2C
+// pass along x (two real rows packed in one complex FFT) and a C2C pass along
+// y. Inverse: from Psi and Psi_z per mode, the y pass forms Psi, -i k_y Psi
+// and Psi_z; the x pass forms -i k_x Psi and returns phi, Ex, Ey, Ez = -Psi_z
+// on the grid (E = -grad psi, Sec. 5.2.1 step 4), interleaved per point.
+// Derivative multipliers vanish on Nyquist indices; the imaginary parts of the
+// x-DC and x-Nyquist bins are dropped by the C2R pass.
+#include <hip/hip_runtime.h>
+
+#include "dpse_internal.h"
+#include "fft_lds.h"
+
+namespace dpse {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kElems = 2048;  // complex elements per LDS FFT buffer
+
+template <typename R>
+struct CT;
+template <>
+struct CT<double> { using T = double2; };
+template <>
+struct CT<float> { using T = float2; };
+
+__host__ __device__ inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// R2C along x of rows [row0, row0 + nrows_total) of `in` (rows of length Nx).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const R* __restrict__ in,
+                                                        typename CT<R>::T* __restrict__ out, int64_t row0,
+                                                        int64_t nrows, const typename CT<R>::T* __restrict__ twg) {
+  using C = typename CT<R>::T;
+  __shared__ C buf[kElems];
+  __shared__ C tw[512];
+  const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
+  const int nseq = kElems / Nx;              // row pairs per block
+  const int64_t r_base = row0 + (int64_t)blockIdx.x * 2 * nseq;
+  const int nr = (int)min((int64_t)2 * nseq, row0 + nrows - r_base);
+  for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < 2 * nseq * Nx; i += kThreads) {
+    int rl = i / Nx, x = i % Nx;
+    R v = rl < nr ? in[(r_base + rl) * Nx + x] : (R)0;
+    C* d = &buf[(rl >> 1) * Nx + bitrev(x, logN)];
+    if (rl & 1) d->y = v; else d->x = v;
+  }
+  __syncthreads();
+  fft_lds<C, false>(buf, logN, nseq, Nx, 1, tw, false, threadIdx.x, kThreads);
+  const R scale = (R)(1.0 / ((double)g.Nx * (double)g.Ny));
+  for (int i = threadIdx.x; i < nseq * nkx; i += kThreads) {
+    int s = i / nkx, k = i % nkx;
+    C z = buf[s * Nx + k], zc = buf[s * Nx + ((Nx - k) & (Nx - 1))];
+    zc.y = -zc.y;
+    C a, b;
+    a.x = (R)0.5 * (z.x + zc.x) * scale;
+    a.y = (R)0.5 * (z.y + zc.y) * scale;
+    b.x = (R)0.5 * (z.y - zc.y) * scale;
+    b.y = (R)-0.5 * (z.x - zc.x) * scale;
+    int rl = 2 * s;
+    if (rl < nr) out[(r_base + rl) * nkx + k] = a;
+    if (rl + 1 < nr) out[(r_base + rl + 1) * nkx + k] = b;
+  }
+}
+
+// Forward C2C along y, in place, for planes [p0, p0 + np).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* data, int p0,
+                                                    const typename CT<R>::T* __restrict__ twg) {
+  using C = typename CT<R>::T;
+  __shared__ C buf[kElems];
+  __shared__ C tw[512];
+  const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
+  const int KB = kElems / Ny;
+  const int nblk = (nkx + KB - 1) / KB;
+  const int plane = p0 + blockIdx.x / nblk;
+  const int kb = (blockIdx.x % nblk) * KB;
+  for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
+  C* base = data + (size_t)plane * Ny * nkx;
+  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
+    int ky = i / KB, kl = i % KB;
+    C v;
+    v.x = 0; v.y = 0;
+    if (kb + kl < nkx) v = base[(size_t)ky * nkx + kb + kl];
+    buf[bitrev(ky, logN) * KB + kl] = v;
+  }
+  __syncthreads();
+  fft_lds<C, true>(buf, logN, KB, 1, KB, tw, false, threadIdx.x, kThreads);
+  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
+    int ky = i / KB, kl = i % KB;
+    if (kb + kl < nkx) base[(size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
+  }
+}
+
+// Inverse C2C along y: (Psi, Psi_z) -> (P0 = Psi, PY = -i ky Psi, PZ = Psi_z), y-transformed.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R>::T* __restrict__ psi,
+                                                     const typename CT<R>::T* __restrict__ psiz,
+                                                     typename CT<R>::T* p0, typename CT<R>::T* py,
+                                                     typename CT<R>::T* pz,
+                                                     const typename CT<R>::T* __restrict__ twg) {
+  using C = typename CT<R>::T;
+  constexpr int E3 = kElems / 2;  // per field
+  __shared__ C buf[3 * E3];
+  __shared__ C tw[512];
+  const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
+  const int KB = max(1, E3 / Ny);
+  const int nblk = (nkx + KB - 1) / KB;
+  const int plane = blockIdx.x / nblk;
+  const int kb = (blockIdx.x % nblk) * KB;
+  for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
+  const size_t off = (size_t)plane * Ny * nkx;
+  const double kyf = 2.0 * kPi / g.Ly;
+  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
+    int ky = i / KB, kl = i % KB;
+    C a, c;
+    a.x = 0; a.y = 0; c.x = 0; c.y = 0;
+    if (kb + kl < nkx) {
+      a = psi[off + (size_t)ky * nkx + kb + kl];
+      c = psiz[off + (size_t)ky * nkx + kb + kl];
+    }
+    int ny = ky < Ny / 2 ? ky : ky - Ny;
+    R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
+    C b;  // -i ky a
+    b.x = kyv * a.y;
+    b.y = -kyv * a.x;
+    int pos = bitrev(ky, logN) * KB + kl;
+    buf[pos] = a;
+    buf[E3 + pos] = b;
+    buf[2 * E3 + pos] = c;
+  }
+  __syncthreads();
+  // the three fields are 3 KB sequences laid out with the same element stride
+  fft_lds<C, true>(buf, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
+  fft_lds<C, true>(buf + E3, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
+  fft_lds<C, true>(buf + 2 * E3, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
+  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
+    int ky = i / KB, kl = i % KB;
+    if (kb + kl < nkx) {
+      size_t o = off + (size_t)ky * nkx + kb + kl;
+      int pos = ky * KB + kl;
+      p0[o] = buf[pos];
+      py[o] = buf[E3 + pos];
+      pz[o] = buf[2 * E3 + pos];
+    }
+  }
+}
+
+// Inverse C2R along x: rows of (P0, PY, PZ) -> u4[row][x] = (phi, Ex, Ey, Ez).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename CT<R>::T* __restrict__ p0,
+                                                         const typename CT<R>::T* __restrict__ py,
+                                                         const typename CT<R>::T* __restrict__ pz, R* __restrict__ u4,
+                                                         int64_t nrows, const typename CT<R>::T* __restrict__ twg) {
+  using C = typename CT<R>::T;
+  __shared__ C buf[kElems];
+  __shared__ C tw[512];
+  const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
+  const int nrow_blk = kElems / (2 * Nx);  // rows per block (2 sequences per row)
+  const int64_t r_base = (int64_t)blockIdx.x * nrow_blk;
+  const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
+  for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
+  const double kxf = 2.0 * kPi / g.Lx;
+  for (int i = threadIdx.x; i < nrow_blk * Nx; i += kThreads) {
+    int rl = i / Nx, k = i % Nx;
+    C z1, z2;
+    z1.x = 0; z1.y = 0; z2.x = 0; z2.y = 0;
+    if (rl < nr) {
+      int kk = k <= Nx / 2 ? k : Nx - k;
+      bool cj = k > Nx / 2;
+      size_t o = (size_t)(r_base + rl) * nkx + kk;
+      C a = p0[o], b = py[o], c = pz[o];
+      if (kk == 0 || kk == Nx / 2) { a.y = 0; b.y = 0; c.y = 0; }
+      R kxv = (kk == Nx / 2) ? (R)0 : (R)(kxf * kk);
+      C ex;  // -i kx a
+      ex.x = kxv * a.y;
+      ex.y = -kxv * a.x;
+      C ez;  // -Psi_z
+      ez.x = -c.x;
+      ez.y = -c.y;
+      if (cj) { a.y = -a.y; ex.y = -ex.y; b.y = -b.y; ez.y = -ez.y; }
+      // z1 = phi_hat + i Ex_hat, z2 = Ey_hat + i Ez_hat
+      z1.x = a.x - ex.y; z1.y = a.y + ex.x;
+      z2.x = b.x - ez.y; z2.y = b.y + ez.x;
+    }
+    int pos = bitrev(k, logN);
+    buf[(2 * rl) * Nx + pos] = z1;
+    buf[(2 * rl + 1) * Nx + pos] = z2;
+  }
+  __syncthreads();
+  fft_lds<C, false>(buf, logN, 2 * nrow_blk, Nx, 1, tw, true, threadIdx.x, kThreads);
+  using V = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
+  V* out = reinterpret_cast<V*>(u4);
+  for (int i = threadIdx.x; i < nr * Nx; i += kThreads) {
+    int rl = i / Nx, x = i % Nx;
+    C z1 = buf[(2 * rl) * Nx + x], z2 = buf[(2 * rl + 1) * Nx + x];
+    V v;
+    v.x = z1.x; v.y = z1.y; v.z = z2.x; v.w = z2.y;
+    out[(size_t)(r_base + rl) * Nx + x] = v;
+  }
+}
+
+template <typename R>
+const typename CT<R>::T* twx(dpse_plan* p);
+template <>
+const double2* twx<double>(dpse_plan* p) { return p->t.twx; }
+template <>
+const float2* twx<float>(dpse_plan* p) { return p->t.twx_f; }
+template <typename R>
+const typename CT<R>::T* twy(dpse_plan* p);
+template <>
+const double2* twy<double>(dpse_plan* p) { return p->t.twy; }
+template <>
+const float2* twy<float>(dpse_plan* p) { return p->t.twy_f; }
+
+template <typename R>
+void launch_x_rows(dpse_plan* p, const R* in, typename CT<R>::T* out, int plane_a, int plane_b) {
+  const Geom& g = p->g;
+  if (plane_b <= plane_a) return;
+  int64_t row0 = (int64_t)plane_a * g.Ny, nrows = (int64_t)(plane_b - plane_a) * g.Ny;
+  int rows_per = 2 * (kElems / g.Nx);
+  int nb = (int)((nrows + rows_per - 1) / rows_per);
+  hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3(nb), dim3(kThreads), 0, p->stream, g, in, out, row0, nrows, twx<R>(p));
+}
+
+template <typename R>
+void launch_y_planes(dpse_plan* p, typename CT<R>::T* data, int plane_a, int plane_b) {
+  const Geom& g = p->g;
+  if (plane_b <= plane_a) return;
+  int KB = kElems / g.Ny;
+  int nblk = (g.nkx + KB - 1) / KB;
+  hipLaunchKernelGGL(k_fft_y<R>, dim3(nblk * (plane_b - plane_a)), dim3(kThreads), 0, p->stream, g, data,
+                     plane_a, twy<R>(p));
+}
+
+}  // namespace
+
+template <typename R>
+hipError_t launch_fft_forward(dpse_plan* p) {
+  using C = typename CT<R>::T;
+  const Geom& g = p->g;
+  launch_x_rows<R>(p, (const R*)p->w.f_i, (C*)p->w.fx_i, 0, g.Nz);
+  launch_y_planes<R>(p, (C*)p->w.fx_i, 0, g.Nz);
+  if (g.top_end >= g.bot_begin) {
+    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.Nz);
+    launch_y_planes<R>(p, (C*)p->w.fx_o, 0, g.Nz);
+  } else {
+    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.top_end);
+    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, g.bot_begin, g.Nz);
+    launch_y_planes<R>(p, (C*)p->w.fx_o, 0, g.top_end);
+    launch_y_planes<R>(p, (C*)p->w.fx_o, g.bot_begin, g.Nz);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fft_inverse(dpse_plan* p) {
+  using C = typename CT<R>::T;
+  const Geom& g = p->g;
+  int KB = std::max(1, (kElems / 2) / g.Ny);
+  int nblk = (g.nkx + KB - 1) / KB;
+  hipLaunchKernelGGL(k_ifft_y<R>, dim3(nblk * g.Nz), dim3(kThreads), 0, p->stream, g, (const C*)p->w.psi,
+                     (const C*)p->w.psiz, (C*)p->w.p0, (C*)p->w.py, (C*)p->w.pz, twy<R>(p));
+  int64_t nrows = (int64_t)g.Nz * g.Ny;
+  int rows_per = kElems / (2 * g.Nx);
+  int nb = (int)((nrows + rows_per - 1) / rows_per);
+  hipLaunchKernelGGL(k_ifft_x_c2r<R>, dim3(nb), dim3(kThreads), 0, p->stream, g, (const C*)p->w.p0,
+                     (const C*)p->w.py, (const C*)p->w.pz, (R*)p->w.u4, nrows, twx<R>(p));
+  return hipGetLastError();
+}
+
+template hipError_t launch_fft_forward<double>(dpse_plan*);
+template hipError_t launch_fft_forward<float>(dpse_plan*);
+template hipError_t launch_fft_inverse<double>(dpse_plan*);
+template hipError_t launch_fft_inverse<float>(dpse_plan*);
+
+}  // namespace dpse

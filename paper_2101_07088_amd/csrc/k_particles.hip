@@ -1,0 +1,414 @@
+// Particle-side kernels: validation and charge groups with their images
+// (Sec. 5.2.2 step 1, eq. ims), counting sorts into spreading bins and the
+// near-field cell list, the near-field pair sums (Sec. 3.2 eqs. GnearK,
+// EnearK; Sec. 4.2), the gauge constant (Sec. 5.2.2, last paragraph) and the
+// combination of far and near parts into potentials, forces and energy
+// (eqs. Ufinal, fqE, self term of Sec. 6.3).
+#include <hip/hip_runtime.h>
+
+#include "dpse_internal.h"
+
+namespace dpse {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__global__ void k_fill_int(int* p, int v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_double(double* p, double v, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__device__ inline double block_sum(double v, double* sh) {
+  // wavefront reduction, then across the block's waves
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+  }
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+__device__ inline int spread_key(const Geom& g, double x, double y, double z) {
+  int ix = (int)floor(x / g.h);
+  int iy = (int)floor(y / g.h);
+  ix %= g.Nx; if (ix < 0) ix += g.Nx;
+  iy %= g.Ny; if (iy < 0) iy += g.Ny;
+  int bx = ix / g.B, by = iy / g.B;
+  int zb = (int)floor((z - g.zb_lo) / g.zb_w);
+  zb = zb < 0 ? 0 : (zb >= g.nzb ? g.nzb - 1 : zb);
+  return (by * g.nbx + bx) * g.nzb + zb;
+}
+
+__device__ inline int cell_of(const Geom& g, double x, double y, double z) {
+  int cx = (int)floor(x / g.cwx), cy = (int)floor(y / g.cwy), cz = (int)floor(z / g.cwz);
+  cx = cx < 0 ? 0 : (cx >= g.ncx ? g.ncx - 1 : cx);
+  cy = cy < 0 ? 0 : (cy >= g.ncy ? g.ncy - 1 : cy);
+  cz = cz < 0 ? 0 : (cz >= g.ncz ? g.ncz - 1 : cz);
+  return (cz * g.ncy + cy) * g.ncx + cx;
+}
+
+// Validation, periodic wrap, groups C_o / C_>, images of C_o charges.
+__global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const double* __restrict__ pos,
+                                                   const double* __restrict__ q, Part* ext, int* meta,
+                                                   int* n_img, double* scal, int* status) {
+  __shared__ double sh[kThreads / 64];
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double qq = 0.0;
+  if (i < n) {
+    double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    qq = q[i];
+    int st = 0;
+    bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qq);
+    if (!fin || !(z > g.zmin_ok && z < g.zmax_ok)) st |= 1;
+    if (!fin) {
+      x = 0.0; y = 0.0; z = 0.5 * g.H; qq = 0.0;
+    }
+    z = fmin(fmax(z, 0.0), g.H);
+    x -= g.Lx * floor(x / g.Lx);
+    if (!(x < g.Lx)) x = 0.0;
+    y -= g.Ly * floor(y / g.Ly);
+    if (!(y < g.Ly)) y = 0.0;
+    double hmin = fmin(z, g.H - z);
+    if (g.r_cut >= g.H + hmin || 2.0 * g.H_E >= g.H + hmin) st |= 2;
+    bool low = z < 2.0 * g.H_E, high = z > g.H - 2.0 * g.H_E;
+    ext[i] = Part{x, y, z, qq};
+    meta[i] = ((low || high) ? GRP_WALL : GRP_INNER) | (int)(i << 2);
+    if (low && g.gamma_b != 0.0) {
+      int s = atomicAdd(n_img, 1);
+      ext[n + s] = Part{x, y, -z, g.gamma_b * qq};
+      meta[n + s] = GRP_IMAGE | (int)(i << 2);
+    }
+    if (high && g.gamma_t != 0.0) {
+      int s = atomicAdd(n_img, 1);
+      ext[n + s] = Part{x, y, 2.0 * g.H - z, g.gamma_t * qq};
+      meta[n + s] = GRP_IMAGE | (int)(i << 2);
+    }
+    if (st) atomicOr(status, st);
+  }
+  double s1 = block_sum(qq, sh);
+  double s2 = block_sum(fabs(qq), sh);
+  if (threadIdx.x == 0) {
+    atomicAdd(&scal[0], s1);
+    atomicAdd(&scal[1], s2);
+  }
+}
+
+__global__ void k_check_neutral(const double* scal, int* status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (!(fabs(scal[0]) <= 1e-12 * scal[1])) atomicOr(status, 4);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_count_ext(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                        const int* __restrict__ n_img, int* cnt) {
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n + *n_img) return;
+  Part p = ext[i];
+  atomicAdd(&cnt[spread_key(g, p.x, p.y, p.z)], 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_scatter_ext(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                          const int* __restrict__ meta,
+                                                          const int* __restrict__ n_img, int* cur,
+                                                          Part* srt, int* srt_meta) {
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n + *n_img) return;
+  Part p = ext[i];
+  int s = atomicAdd(&cur[spread_key(g, p.x, p.y, p.z)], 1);
+  srt[s] = p;
+  srt_meta[s] = meta[i];
+}
+
+__global__ void __launch_bounds__(kThreads) k_count_cells(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                          int* cnt) {
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n) return;
+  Part p = ext[i];
+  atomicAdd(&cnt[cell_of(g, p.x, p.y, p.z)], 1);
+}
+
+__global__ void __launch_bounds__(kThreads) k_scatter_cells(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                            int* cur, Part* srt, int* idx) {
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n) return;
+  Part p = ext[i];
+  int s = atomicAdd(&cur[cell_of(g, p.x, p.y, p.z)], 1);
+  srt[s] = p;
+  idx[s] = (int)i;
+}
+
+// Exclusive scan of cnt[0..m) into off[0..m] and cur[0..m) by one block.
+__global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int* off, int* cur, int m) {
+  __shared__ int sh[1024];
+  const int T = 1024;
+  int per = (m + T - 1) / T;
+  int b = threadIdx.x * per, e = min(m, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += cnt[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < T; o <<= 1) {
+    int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = sh[threadIdx.x] - s;
+  for (int i = b; i < e; ++i) {
+    off[i] = run;
+    cur[i] = run;
+    run += cnt[i];
+  }
+  if (threadIdx.x == T - 1) off[m] = sh[T - 1];
+}
+
+// --- near field -------------------------------------------------------------
+
+template <typename R>
+__device__ inline void near_pair(const Geom& g, double dx, double dy, double dz, double qs,
+                                 R& ph, R& ex, R& ey, R& ez) {
+  double r2 = dx * dx + dy * dy + dz * dz;
+  if (!(r2 < g.r_cut * g.r_cut)) return;
+  R r = (R)sqrt(r2);
+  R G, e;
+  if (g.g_w > 0.0) {
+    R a1 = (R)(1.0 / (2.0 * g.g_w)), b1 = (R)g.xi_e;
+    if (r < (R)(1e-3 * g.g_w)) {
+      const R c = (R)(2.0 / sqrt(kPi));
+      R c0 = c * (a1 - b1);
+      R c2 = -c * (a1 * a1 * a1 - b1 * b1 * b1) / (R)3;
+      R c4 = c * (a1 * a1 * a1 * a1 * a1 - b1 * b1 * b1 * b1 * b1) / (R)10;
+      G = c0 + c2 * r * r + c4 * r * r * r * r;
+      e = -(2 * c2 + 4 * c4 * r * r);
+    } else {
+      G = (erf(a1 * r) - erf(b1 * r)) / r;
+      R dG = (R)(2.0 / sqrt(kPi)) * (a1 * exp(-(a1 * r) * (a1 * r)) - b1 * exp(-(b1 * r) * (b1 * r))) / r - G / r;
+      e = -dG / r;
+    }
+  } else {
+    R xr = (R)g.xi_e * r;
+    G = erfc(xr) / r;
+    e = (G + (R)(2.0 / sqrt(kPi)) * (R)g.xi_e * exp(-xr * xr)) / (r * r);
+  }
+  R qr = (R)qs;
+  ph += qr * G;
+  ex += qr * e * (R)dx;
+  ey += qr * e * (R)dy;
+  ez += qr * e * (R)dz;
+}
+
+// One thread per target charge (cell-sorted order). Sources: other charges in
+// the 27 neighbouring cells (minimal image), and the bottom/top images of all
+// charges, found through the mirror points (x, y, -z) and (x, y, 2H - z).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part* __restrict__ srt,
+                                                   const int* __restrict__ idx, const int* __restrict__ off,
+                                                   double4* near4) {
+  int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (t >= n) return;
+  Part me = srt[t];
+  R ph = 0, ex = 0, ey = 0, ez = 0;
+  int cx = (int)floor(me.x / g.cwx), cy = (int)floor(me.y / g.cwy);
+  cx = min(max(cx, 0), g.ncx - 1);
+  cy = min(max(cy, 0), g.ncy - 1);
+  int xlo = -1, xhi = 1, ylo = -1, yhi = 1;
+  bool xall = g.ncx < 3, yall = g.ncy < 3;
+  if (xall) { xlo = 0; xhi = g.ncx - 1; }
+  if (yall) { ylo = 0; yhi = g.ncy - 1; }
+  // three source families: direct (mirror sign +1), bottom images, top images
+  for (int fam = 0; fam < 3; ++fam) {
+    double zt, qf;  // z of the point whose neighbours are searched; strength factor
+    if (fam == 0) { zt = me.z; qf = 1.0; }
+    else if (fam == 1) { if (g.gamma_b == 0.0 || me.z >= g.r_cut) continue; zt = -me.z; qf = g.gamma_b; }
+    else { if (g.gamma_t == 0.0 || g.H - me.z >= g.r_cut) continue; zt = 2.0 * g.H - me.z; qf = g.gamma_t; }
+    int zlo = (int)floor((zt - g.r_cut) / g.cwz), zhi = (int)floor((zt + g.r_cut) / g.cwz);
+    zlo = max(zlo, 0);
+    zhi = min(zhi, g.ncz - 1);
+    for (int cz = zlo; cz <= zhi; ++cz) {
+      for (int oy = ylo; oy <= yhi; ++oy) {
+        int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
+        for (int ox = xlo; ox <= xhi; ++ox) {
+          int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
+          int c = (cz * g.ncy + yy) * g.ncx + xx;
+          for (int s = off[c]; s < off[c + 1]; ++s) {
+            if (fam == 0 && s == t) continue;
+            Part o = srt[s];
+            double dx = me.x - o.x, dy = me.y - o.y;
+            dx -= g.Lx * rint(dx / g.Lx);
+            dy -= g.Ly * rint(dy / g.Ly);
+            double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
+            near_pair<R>(g, dx, dy, me.z - zs, qf * o.q, ph, ex, ey, ez);
+          }
+        }
+      }
+    }
+  }
+  const double c = 1.0 / (4.0 * kPi * g.eps);
+  near4[idx[t]] = make_double4(c * (double)ph, c * (double)ex, c * (double)ey, c * (double)ez);
+}
+
+// Pointwise near-field potential at the origin (gauge of Sec. 5.2.2): kernel
+// G^(n)(r; g_w, xi) of eq. Gnear over the charges and their first images.
+__global__ void __launch_bounds__(kThreads) k_near_origin(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                          double* partials) {
+  __shared__ double sh[kThreads / 64];
+  double acc = 0.0;
+  const double xp = 1.0 / sqrt(2.0 * g.g_w * g.g_w + 1.0 / (g.xi * g.xi));
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    Part p = ext[i];
+    double dx = -p.x - g.Lx * rint(-p.x / g.Lx);
+    double dy = -p.y - g.Ly * rint(-p.y / g.Ly);
+    double zs[3] = {p.z, -p.z, 2.0 * g.H - p.z};
+    double qs[3] = {p.q, g.gamma_b * p.q, g.gamma_t * p.q};
+    for (int f = 0; f < 3; ++f) {
+      if (qs[f] == 0.0) continue;
+      double r = sqrt(dx * dx + dy * dy + zs[f] * zs[f]);
+      if (!(r < g.r_cut)) continue;
+      double G = g.g_w > 0.0 ? (erf(r / (sqrt(2.0) * g.g_w)) - erf(xp * r)) / r : erfc(xp * r) / r;
+      acc += qs[f] * G;
+    }
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_gauge_final(Geom g, int nb, const double* partials, double* scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += partials[i];
+  double near0 = s / (4.0 * kPi * g.eps);
+  scal[5] = near0;
+  scal[2] = (g.flags & DPSE_GAUGE_NONE) ? 0.0 : -(scal[4] + near0);
+}
+
+// phibar = far + near + B_i - q * 2 xi_e / (4 pi eps sqrt(pi)); F = q (E_far + E_near).
+__global__ void __launch_bounds__(kThreads) k_finalize(Geom g, int64_t n, const double* __restrict__ q,
+                                                       const double4* __restrict__ far4,
+                                                       const double4* __restrict__ near4,
+                                                       const double* __restrict__ scal, double* phi,
+                                                       double* force, double* partials) {
+  __shared__ double sh[kThreads / 64];
+  const double selfc = 2.0 * g.xi_e / (4.0 * kPi * g.eps * sqrt(kPi));
+  const double Bi = scal[2];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kThreads) {
+    double qi = q[i];
+    double4 f = far4[i], r = near4[i];
+    double ph = f.x + r.x + Bi - qi * selfc;
+    if (phi) phi[i] = ph;
+    if (force) {
+      force[3 * i] = qi * (f.y + r.y);
+      force[3 * i + 1] = qi * (f.z + r.z);
+      force[3 * i + 2] = qi * (f.w + r.w);
+    }
+    acc += qi * ph;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_energy_final(int nb, const double* partials, double* energy, double* scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += partials[i];
+  scal[6] = 0.5 * s;
+  if (energy) *energy = 0.5 * s;
+}
+
+inline int blocks_for(int64_t n, int cap) {
+  int64_t b = (n + kThreads - 1) / kThreads;
+  if (b < 1) b = 1;
+  return (int)(b < cap ? b : cap);
+}
+
+}  // namespace
+
+hipError_t fill_int(int* ptr, int value, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_int, dim3(blocks_for(count, 4096)), dim3(kThreads), 0, s, ptr, value, count);
+  return hipGetLastError();
+}
+
+hipError_t fill_double(double* ptr, double value, int64_t count, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_double, dim3(blocks_for(count, 4096)), dim3(kThreads), 0, s, ptr, value, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double* q) {
+  hipStream_t s = p->stream;
+  Workspace& w = p->w;
+  hipError_t e = fill_int(w.n_img, 0, 1, s);
+  if (e == hipSuccess) e = fill_double(w.scal, 0.0, 16, s);
+  if (e != hipSuccess) return e;
+  int nb = (int)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
+                     w.n_img, w.scal, w.status);
+  hipLaunchKernelGGL(k_check_neutral, dim3(1), dim3(64), 0, s, (const double*)w.scal, w.status);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin(dpse_plan* p, int64_t n) {
+  hipStream_t s = p->stream;
+  Workspace& w = p->w;
+  hipError_t e = fill_int(w.bin_cnt, 0, p->nkeys + 1, s);
+  if (e == hipSuccess) e = fill_int(w.cell_cnt, 0, p->ncells + 1, s);
+  if (e != hipSuccess) return e;
+  int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
+  int nb = (int)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_count_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
+                     (const int*)w.n_img, w.bin_cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
+  hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
+                     (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta);
+  hipLaunchKernelGGL(k_count_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext, w.cell_cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.cell_cnt, w.cell_off, w.cell_cur,
+                     p->ncells);
+  hipLaunchKernelGGL(k_scatter_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
+                     w.cell_cur, w.nsrt, w.nsrt_idx);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_near(dpse_plan* p, int64_t n) {
+  int nb = (int)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_near<R>, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.nsrt,
+                     (const int*)p->w.nsrt_idx, (const int*)p->w.cell_off, p->w.near4);
+  return hipGetLastError();
+}
+
+// near part of the gauge; the far part (scal[4]) is written by the grid kernels
+hipError_t launch_gauge_near(dpse_plan* p, int64_t n) {
+  int nb = blocks_for(n, p->npartials);
+  hipLaunchKernelGGL(k_near_origin, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.ext,
+                     p->w.partials);
+  hipLaunchKernelGGL(k_gauge_final, dim3(1), dim3(64), 0, p->stream, p->g, nb, (const double*)p->w.partials,
+                     p->w.scal);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy, double* phi,
+                           double* force) {
+  int nb = blocks_for(n, p->npartials);
+  hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, q,
+                     (const double4*)p->w.far4, (const double4*)p->w.near4, (const double*)p->w.scal, phi,
+                     force, p->w.partials + p->npartials);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nb,
+                     (const double*)(p->w.partials + p->npartials), energy, p->w.scal);
+  return hipGetLastError();
+}
+
+template hipError_t launch_near<double>(dpse_plan*, int64_t);
+template hipError_t launch_near<float>(dpse_plan*, int64_t);
+
+}  // namespace dpse

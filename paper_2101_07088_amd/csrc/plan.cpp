@@ -1,0 +1,507 @@
+// Host side of the DP-SE library: parameter derivation and validation,
+// plan tables and workspace, and the stage sequence of one solve
+// (Sec. 5.2.2 steps 1-7 of the paper plus the near field of Sec. 4.2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "dpse_internal.h"
+
+using dpse::Geom;
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// d/dr of [erf(r/a) - erf(r/b)]/r with a = sqrt2 g_w (a = 0: the term is 1/r)
+// and b = sqrt(2 g_w^2 + xi^-2) (b absent when xi = 0): eq. Gnear without the
+// 1/(4 pi eps) factor.
+double dgnear(double r, double g_w, double xi) {
+  auto term = [](double rr, double s) {
+    if (s == 0.0) return -1.0 / (rr * rr);
+    double u = rr / s;
+    return 2.0 / std::sqrt(dpse::kPi) * std::exp(-u * u) / (s * rr) - std::erf(u) / (rr * rr);
+  };
+  double t1 = term(r, std::sqrt(2.0) * g_w);
+  if (xi == 0.0) return t1;
+  return t1 - term(r, std::sqrt(2.0 * g_w * g_w + 1.0 / (xi * xi)));
+}
+
+// Smallest r with |dG(r; g_w, xi) / dG(r; g_w, 0)| < delta (eq. rnf).
+double derive_rnf(double g_w, double xi, double delta) {
+  auto ratio = [&](double r) { return std::fabs(dgnear(r, g_w, xi) / dgnear(r, g_w, 0.0)); };
+  double step = 0.01 / xi, r = 1e-6 / xi;
+  while (ratio(r) >= delta) {
+    r += step;
+    if (r > 100.0 / xi) return -1.0;
+  }
+  double lo = r - step, hi = r;
+  for (int it = 0; it < 100; ++it) {
+    double mid = 0.5 * (lo + hi);
+    if (ratio(mid) < delta) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
+  if (!p || !info) return DPSE_EINVAL;
+  auto pos_finite = [](double v) { return std::isfinite(v) && v > 0.0; };
+  if (!pos_finite(p->Lx) || !pos_finite(p->Ly) || !pos_finite(p->H) || !pos_finite(p->eps) ||
+      !pos_finite(p->eps_bottom) || !pos_finite(p->eps_top) || !pos_finite(p->xi))
+    return DPSE_EINVAL;
+  if (!std::isfinite(p->g_w) || p->g_w < 0.0) return DPSE_EINVAL;
+  if (!is_pow2(p->Nx) || !is_pow2(p->Ny) || p->Nx < 8 || p->Ny < 8 || p->Nx > 1024 || p->Ny > 1024)
+    return DPSE_EINVAL;
+  if (p->Nz < 5 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
+  if (p->precision != DPSE_FP64 && p->precision != DPSE_MIXED) return DPSE_EINVAL;
+  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT)) return DPSE_EINVAL;
+  double h = p->Lx / p->Nx, hy = p->Ly / p->Ny;
+  if (std::fabs(h - hy) > 1e-12 * h) return DPSE_EINVAL;
+  double g_t = std::sqrt(1.0 / (4.0 * p->xi * p->xi) + p->g_w * p->g_w);
+  int ng = p->support;
+  if (ng == 0) ng = 2 * (int)std::ceil(4.3 * g_t / h);
+  if (ng < 2 || (ng & 1) || ng > p->Nx || ng > p->Ny) return DPSE_EINVAL;
+  double H_E = ng * h / 2.0;
+  double rc = p->r_cut;
+  if (rc == 0.0) {
+    double delta = p->delta > 0.0 ? p->delta : 1e-4;
+    rc = derive_rnf(p->g_w, p->xi, delta);
+    if (rc <= 0.0) return DPSE_EINVAL;
+    rc += 4.0 * p->g_w;  // r_cut = r_nf + n_sigma g_w (Sec. 5.1)
+  }
+  if (!(rc > 0.0) || rc >= 0.5 * std::fmin(p->Lx, p->Ly)) return DPSE_EINVAL;
+  // position-independent necessary conditions of Sec. 4.2 / 5.3 (h_min <= H/2)
+  if (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H) return DPSE_EINVAL;
+
+  std::memset(info, 0, sizeof(*info));
+  info->h = h;
+  info->g_t = g_t;
+  info->H_E = H_E;
+  info->n_sigma = H_E / g_t;
+  info->z_lo = -3.0 * H_E;
+  info->z_hi = p->H + 3.0 * H_E;
+  info->r_cut = rc;
+  info->xi_e = 1.0 / std::sqrt(4.0 * p->g_w * p->g_w + 1.0 / (p->xi * p->xi));
+  info->support = ng;
+  info->n_modes = p->Ny * (p->Nx / 2 + 1);
+
+  if (g) {
+    std::memset(g, 0, sizeof(*g));
+    g->Lx = p->Lx; g->Ly = p->Ly; g->H = p->H;
+    g->eps = p->eps; g->eps_b = p->eps_bottom; g->eps_t = p->eps_top;
+    g->xi = p->xi; g->g_w = p->g_w;
+    g->h = h; g->inv_h = 1.0 / h; g->g_t = g_t; g->H_E = H_E;
+    g->za = -3.0 * H_E; g->zb = p->H + 3.0 * H_E;
+    g->zc = 0.5 * (g->za + g->zb); g->zR = 0.5 * (g->zb - g->za);
+    g->gamma_b = (p->eps - p->eps_bottom) / (p->eps + p->eps_bottom);
+    g->gamma_t = (p->eps - p->eps_top) / (p->eps + p->eps_top);
+    g->tau_b = 2.0 * p->eps / (p->eps_bottom + p->eps);
+    g->tau_t = 2.0 * p->eps / (p->eps_top + p->eps);
+    g->xi_e = info->xi_e;
+    g->r_cut = rc;
+    g->sbar_norm = std::pow(2.0 * dpse::kPi * g_t * g_t, -1.5);
+    g->inv2g2 = 1.0 / (2.0 * g_t * g_t);
+    g->zmin_ok = 4.0 * p->g_w;
+    g->zmax_ok = p->H - 4.0 * p->g_w;
+    g->Nx = p->Nx; g->Ny = p->Ny; g->Nz = p->Nz; g->nkx = p->Nx / 2 + 1;
+    g->ng = ng; g->flags = p->flags;
+    g->B = std::min(dpse::kBin, std::min(p->Nx, p->Ny));
+    g->nbx = p->Nx / g->B; g->nby = p->Ny / g->B;
+    g->zb_lo = -2.0 * H_E;
+    g->zb_w = 0.5 * H_E;
+    g->nzb = (int)std::ceil((p->H + 4.0 * H_E) / g->zb_w) + 1;
+    g->ncx = std::max(1, std::min(1024, (int)std::floor(p->Lx / rc)));
+    g->ncy = std::max(1, std::min(1024, (int)std::floor(p->Ly / rc)));
+    g->ncz = std::max(1, std::min(1024, (int)std::floor(p->H / rc)));
+    g->cwx = p->Lx / g->ncx; g->cwy = p->Ly / g->ncy; g->cwz = p->H / g->ncz;
+    // wall bands of psi_o*: nodes with z_j > H - 3 H_E (top) or z_j < 3 H_E (bottom)
+    int N = p->Nz;
+    int top_end = 0, bot_begin = N;
+    for (int j = 0; j < N; ++j) {
+      double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
+      if (z > p->H - 3.0 * H_E) top_end = j + 1;
+    }
+    for (int j = N - 1; j >= 0; --j) {
+      double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
+      if (z < 3.0 * H_E) bot_begin = j;
+    }
+    g->top_end = top_end;
+    g->bot_begin = bot_begin;
+  }
+  return DPSE_OK;
+}
+
+template <typename T>
+hipError_t dalloc(dpse_plan* p, T** ptr, size_t count, int64_t* bytes) {
+  size_t b = std::max<size_t>(count, 1) * sizeof(T);
+  b = (b + 255) & ~size_t(255);
+  hipError_t e = hipMalloc((void**)ptr, b);
+  if (e == hipSuccess) {
+    p->allocs.push_back((void*)*ptr);
+    *bytes += (int64_t)b;
+  }
+  return e;
+}
+
+void free_all(dpse_plan* p) {
+  for (void* a : p->allocs) (void)hipFree(a);
+  p->allocs.clear();
+}
+
+// Chebyshev T_n(s) and T_n'(s) for n < N by the three-term recurrences.
+void cheb_table(int N, long double s, std::vector<double>& T, std::vector<double>& dT) {
+  T.assign(N, 0.0);
+  dT.assign(N, 0.0);
+  long double t0 = 1.0L, t1 = s, u0 = 1.0L, u1 = 2.0L * s;  // U_{n-1} for T_n' = n U_{n-1}
+  for (int n = 0; n < N; ++n) {
+    long double tn = (n == 0) ? 1.0L : (n == 1 ? s : 0.0L);
+    if (n >= 2) {
+      tn = 2.0L * s * t1 - t0;
+      t0 = t1;
+      t1 = tn;
+    }
+    T[n] = (double)((n == 0) ? 1.0L : (n == 1 ? s : tn));
+    long double un1;  // U_{n-1}
+    if (n == 0) un1 = 0.0L;
+    else if (n == 1) un1 = 1.0L;
+    else if (n == 2) un1 = u1;
+    else {
+      long double un = 2.0L * s * u1 - u0;
+      u0 = u1;
+      u1 = un;
+      un1 = un;
+    }
+    dT[n] = (double)(n * un1);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dpse_status_string(int s) {
+  switch (s) {
+    case DPSE_OK: return "ok";
+    case DPSE_EINVAL: return "invalid argument or parameters";
+    case DPSE_ENOMEM: return "device allocation failed";
+    case DPSE_EHIP: return "HIP runtime error";
+    case DPSE_ENONNEUTRAL: return "charges are not neutral";
+    case DPSE_EOUTSIDE: return "charge outside the slab or non-finite coordinate";
+    case DPSE_ECONSTRAINT: return "near-field or far-field image constraint violated (Sec. 5.3)";
+    case DPSE_ETOOMANY: return "more charges than the plan's max_n";
+    default: return "unknown status";
+  }
+}
+
+int dpse_derive(const dpse_params* params, dpse_info* info) {
+  dpse_info tmp;
+  int s = derive_all(params, &tmp, nullptr);
+  if (s == DPSE_OK) *info = tmp;
+  return s;
+}
+
+int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out) {
+  if (!out || max_n <= 0 || max_n > (int64_t(1) << 28)) return DPSE_EINVAL;
+  dpse_plan* p = new (std::nothrow) dpse_plan();
+  if (!p) return DPSE_ENOMEM;
+  int s = derive_all(params, &p->info, &p->g);
+  if (s != DPSE_OK) {
+    delete p;
+    return s;
+  }
+  p->prm = *params;
+  p->stream = (hipStream_t)stream;
+  p->max_n = max_n;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return DPSE_EHIP;
+  }
+  const Geom& g = p->g;
+  const bool mixed = params->precision == DPSE_MIXED;
+  const size_t rs = mixed ? 4 : 8;
+  const size_t G = (size_t)g.Nz * g.Ny * g.Nx;
+  const size_t C = (size_t)g.Nz * g.Ny * g.nkx;
+  p->nkeys = g.nbx * g.nby * g.nzb;
+  p->ncells = g.ncx * g.ncy * g.ncz;
+  p->npartials = 1024;
+  int64_t bytes = 0;
+  hipError_t e = hipSuccess;
+  auto A = [&](auto** ptr, size_t count) {
+    if (e == hipSuccess) e = dalloc(p, ptr, count, &bytes);
+  };
+  dpse::Workspace& w = p->w;
+  size_t next = 3 * (size_t)max_n;
+  A(&w.ext, next); A(&w.ext_meta, next); A(&w.srt, next); A(&w.srt_meta, next);
+  A(&w.bin_cnt, p->nkeys + 1); A(&w.bin_off, p->nkeys + 1); A(&w.bin_cur, p->nkeys + 1);
+  A(&w.n_img, 4);
+  A(&w.nsrt, max_n); A(&w.nsrt_idx, max_n);
+  A(&w.cell_cnt, p->ncells + 1); A(&w.cell_off, p->ncells + 1); A(&w.cell_cur, p->ncells + 1);
+  char** grids[] = {(char**)&w.f_i, (char**)&w.f_o};
+  for (char** gp : grids) A(gp, G * rs);
+  char** cgrids[] = {(char**)&w.fx_i, (char**)&w.fx_o, (char**)&w.psi, (char**)&w.psiz,
+                     (char**)&w.p0, (char**)&w.py, (char**)&w.pz};
+  for (char** gp : cgrids) A(gp, C * 2 * rs);
+  A((char**)&w.u4, 4 * G * rs);
+  A(&w.far4, max_n); A(&w.near4, max_n);
+  A(&w.scal, 16); A(&w.partials, 4 * p->npartials); A(&w.status, 4);
+  dpse::Tables& t = p->t;
+  A(&t.z, g.Nz); A(&t.wq, g.Nz); A(&t.T0, g.Nz); A(&t.TH, g.Nz); A(&t.dT0, g.Nz); A(&t.dTH, g.Nz);
+  A(&t.twx, g.Nx / 2); A(&t.twy, g.Ny / 2); A(&t.twz, g.Nz - 1);
+  A(&t.twx_f, g.Nx / 2); A(&t.twy_f, g.Ny / 2);
+  if (e != hipSuccess) {
+    free_all(p);
+    delete p;
+    return DPSE_ENOMEM;
+  }
+  p->info.workspace_bytes = bytes;
+  p->info.max_n = max_n;
+
+  // plan tables
+  const int N = g.Nz;
+  std::vector<double> z(N), wq(N);
+  const int nint = N - 1;
+  for (int j = 0; j < N; ++j) {
+    long double th = (long double)dpse::kPi * j / nint;
+    z[j] = (double)(g.zc + g.zR * std::cos(th));
+    // Clenshaw-Curtis weight on [-1,1] (cosine-series form), scaled by R and h^2
+    long double acc = 1.0L;
+    for (int k = 1; k <= nint / 2; ++k) {
+      long double b = (2 * k == nint) ? 1.0L : 2.0L;
+      acc -= b / (4.0L * k * k - 1.0L) * std::cos(2.0L * (long double)dpse::kPi * j * k / nint);
+    }
+    long double c = (j == 0 || j == nint) ? 1.0L : 2.0L;
+    wq[j] = (double)(c / nint * acc * g.zR * g.h * g.h);
+  }
+  std::vector<double> T0, dT0, TH, dTH;
+  cheb_table(N, ((long double)0.0 - g.zc) / g.zR, T0, dT0);
+  cheb_table(N, ((long double)g.H - g.zc) / g.zR, TH, dTH);
+  for (int n = 0; n < N; ++n) {
+    dT0[n] /= g.zR;
+    dTH[n] /= g.zR;
+  }
+  auto twid = [](int L) {
+    std::vector<double2> tw(std::max(L / 2, 1));
+    for (int k = 0; k < L / 2; ++k) {
+      long double a = -2.0L * (long double)dpse::kPi * k / L;
+      tw[k] = make_double2((double)std::cos(a), (double)std::sin(a));
+    }
+    return tw;
+  };
+  auto tox = twid(g.Nx), toy = twid(g.Ny), toz = twid(2 * (N - 1));
+  std::vector<float2> txf(tox.size()), tyf(toy.size());
+  for (size_t i = 0; i < tox.size(); ++i) txf[i] = make_float2((float)tox[i].x, (float)tox[i].y);
+  for (size_t i = 0; i < toy.size(); ++i) tyf[i] = make_float2((float)toy[i].x, (float)toy[i].y);
+  auto H2D = [&](void* dst, const void* src, size_t b) {
+    if (e == hipSuccess) e = hipMemcpy(dst, src, b, hipMemcpyHostToDevice);
+  };
+  H2D(t.z, z.data(), N * 8); H2D(t.wq, wq.data(), N * 8);
+  H2D(t.T0, T0.data(), N * 8); H2D(t.TH, TH.data(), N * 8);
+  H2D(t.dT0, dT0.data(), N * 8); H2D(t.dTH, dTH.data(), N * 8);
+  H2D(t.twx, tox.data(), tox.size() * sizeof(double2));
+  H2D(t.twy, toy.data(), toy.size() * sizeof(double2));
+  H2D(t.twz, toz.data(), toz.size() * sizeof(double2));
+  H2D(t.twx_f, txf.data(), txf.size() * sizeof(float2));
+  H2D(t.twy_f, tyf.data(), tyf.size() * sizeof(float2));
+  int zero4[4] = {0, 0, 0, 0};
+  H2D(w.status, zero4, sizeof(zero4));
+  if (e != hipSuccess) {
+    free_all(p);
+    delete p;
+    return DPSE_EHIP;
+  }
+  *out = p;
+  return DPSE_OK;
+}
+
+int dpse_plan_info(const dpse_plan* plan, dpse_info* info) {
+  if (!plan || !info) return DPSE_EINVAL;
+  *info = plan->info;
+  return DPSE_OK;
+}
+
+static const char* kStageNames[DPSE_NUM_STAGES] = {
+    "prep", "bin", "spread", "fft_forward", "column", "fft_inverse", "interp", "near", "gauge", "finalize"};
+
+static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* q,
+                      double* energy, double* phi, double* force) {
+  if (!p || !pos || !q || n <= 0) return DPSE_EINVAL;
+  if (n > p->max_n) return DPSE_ETOOMANY;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+    if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  }
+  p->last_n = n;
+  const bool mixed = p->prm.precision == DPSE_MIXED;
+  hipEvent_t* ev = nullptr;
+  if (p->timing) {
+    size_t need = (size_t)(p->timed_solves + 1) * (DPSE_NUM_STAGES + 1);
+    while (p->events.size() < need) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return DPSE_EHIP;
+      p->events.push_back(e);
+    }
+    ev = p->events.data() + (size_t)p->timed_solves * (DPSE_NUM_STAGES + 1);
+    p->timed_solves++;
+  }
+  int stage = 0;
+  hipError_t e = hipSuccess;
+  auto mark = [&]() {
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[stage], p->stream);
+    ++stage;
+  };
+  mark();
+  e = e == hipSuccess ? dpse::launch_prep(p, n, pos, q) : e; mark();
+  e = e == hipSuccess ? dpse::launch_bin(p, n) : e; mark();
+  if (mixed) {
+    e = e == hipSuccess ? dpse::launch_spread<float>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_fft_forward<float>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_column<float>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_fft_inverse<float>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_interp<float>(p, n) : e; mark();
+    e = e == hipSuccess ? dpse::launch_near<float>(p, n) : e; mark();
+    e = e == hipSuccess ? dpse::launch_gauge<float>(p, n) : e; mark();
+  } else {
+    e = e == hipSuccess ? dpse::launch_spread<double>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_fft_forward<double>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_column<double>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_fft_inverse<double>(p) : e; mark();
+    e = e == hipSuccess ? dpse::launch_interp<double>(p, n) : e; mark();
+    e = e == hipSuccess ? dpse::launch_near<double>(p, n) : e; mark();
+    e = e == hipSuccess ? dpse::launch_gauge<double>(p, n) : e; mark();
+  }
+  e = e == hipSuccess ? dpse::launch_finalize(p, n, q, energy, phi, force) : e; mark();
+  return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
+}
+
+int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q, double* energy,
+               double* phi, double* force) {
+  return solve_impl(plan, n, pos, q, energy, phi, force);
+}
+
+int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
+                     const double* const* pos, const double* const* q, double* const* energy,
+                     double* const* phi, double* const* force) {
+  if (n_sys <= 0 || !plans || !n || !pos || !q) return DPSE_EINVAL;
+  for (int i = 0; i < n_sys; ++i) {
+    if (!plans[i]) return DPSE_EINVAL;
+    if (n[i] <= 0) return DPSE_EINVAL;
+    if (n[i] > plans[i]->max_n) return DPSE_ETOOMANY;
+  }
+  hipStream_t s0 = plans[0]->stream;
+  hipEvent_t ev = nullptr;
+  // every plan's stream first waits for the work already queued on stream 0's
+  // timeline is not required: each solve is independent. Solves of plans that
+  // share s0 run in order; the others run on their own streams and s0 waits.
+  std::vector<hipEvent_t> done;
+  for (int i = 0; i < n_sys; ++i) {
+    int st = solve_impl(plans[i], n[i], pos[i], q[i], energy ? energy[i] : nullptr,
+                        phi ? phi[i] : nullptr, force ? force[i] : nullptr);
+    if (st != DPSE_OK) return st;
+    if (plans[i]->stream != s0) {
+      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return DPSE_EHIP;
+      if (hipEventRecord(ev, plans[i]->stream) != hipSuccess) return DPSE_EHIP;
+      if (hipStreamWaitEvent(s0, ev, 0) != hipSuccess) return DPSE_EHIP;
+      done.push_back(ev);
+    }
+  }
+  for (hipEvent_t d : done) (void)hipEventDestroy(d);
+  return DPSE_OK;
+}
+
+int dpse_sync(dpse_plan* p) {
+  if (!p) return DPSE_EINVAL;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;
+  int st[4] = {0, 0, 0, 0};
+  if (hipMemcpy(st, p->w.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return DPSE_EHIP;
+  int zero4[4] = {0, 0, 0, 0};
+  if (hipMemcpy(p->w.status, zero4, sizeof(zero4), hipMemcpyHostToDevice) != hipSuccess)
+    return DPSE_EHIP;
+  // priority: outside > constraint > non-neutral
+  if (st[0] & 1) return DPSE_EOUTSIDE;
+  if (st[0] & 2) return DPSE_ECONSTRAINT;
+  if (st[0] & 4) return DPSE_ENONNEUTRAL;
+  return DPSE_OK;
+}
+
+int dpse_set_timing(dpse_plan* p, int enable) {
+  if (!p) return DPSE_EINVAL;
+  p->timing = enable != 0;
+  return DPSE_OK;
+}
+
+int dpse_stage_times(dpse_plan* p, double* ms, int max_stages, int* n_solves) {
+  if (!p || (!ms && max_stages > 0)) return DPSE_EINVAL;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;
+  const int ns = DPSE_NUM_STAGES;
+  std::vector<double> acc(ns, 0.0);
+  for (int s = 0; s < p->timed_solves; ++s) {
+    hipEvent_t* ev = p->events.data() + (size_t)s * (ns + 1);
+    for (int k = 0; k < ns; ++k) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) return DPSE_EHIP;
+      acc[k] += t;
+    }
+  }
+  int m = max_stages < ns ? max_stages : ns;
+  for (int k = 0; k < m; ++k) ms[k] = p->timed_solves ? acc[k] / p->timed_solves : 0.0;
+  if (n_solves) *n_solves = p->timed_solves;
+  p->timed_solves = 0;
+  return DPSE_OK;
+}
+
+const char* dpse_stage_name(int stage) {
+  return (stage >= 0 && stage < DPSE_NUM_STAGES) ? kStageNames[stage] : "unknown";
+}
+
+int dpse_plan_destroy(dpse_plan* p) {
+  if (!p) return DPSE_EINVAL;
+  (void)hipStreamSynchronize(p->stream);
+  for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
+  p->events.clear();
+  free_all(p);
+  delete p;
+  return DPSE_OK;
+}
+
+int dpse_debug_copy(dpse_plan* p, int which, void* dst, int64_t bytes, int32_t* elem_bytes,
+                    int64_t* count) {
+  if (!p || !dst || bytes < 0) return DPSE_EINVAL;
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;
+  const dpse::Geom& g = p->g;
+  const bool mixed = p->prm.precision == DPSE_MIXED;
+  const int rs = mixed ? 4 : 8;
+  const int64_t G = (int64_t)g.Nz * g.Ny * g.Nx;
+  const int64_t C = (int64_t)g.Nz * g.Ny * g.nkx * 2;
+  const void* src = nullptr;
+  int64_t cnt = 0;
+  int eb = rs;
+  switch (which) {
+    case DPSE_STAGE_F_I: src = p->w.f_i; cnt = G; break;
+    case DPSE_STAGE_F_O: src = p->w.f_o; cnt = G; break;
+    case DPSE_STAGE_FH_I: src = p->w.fx_i; cnt = C; break;
+    case DPSE_STAGE_PSI: src = p->w.psi; cnt = C; break;
+    case DPSE_STAGE_PSIZ: src = p->w.psiz; cnt = C; break;
+    case DPSE_STAGE_GRIDS: src = p->w.u4; cnt = 4 * G; break;
+    case DPSE_STAGE_FAR: src = p->w.far4; cnt = 4 * p->last_n; eb = 8; break;
+    case DPSE_STAGE_NEAR: src = p->w.near4; cnt = 4 * p->last_n; eb = 8; break;
+    case DPSE_STAGE_SCALARS: src = p->w.scal; cnt = 8; eb = 8; break;
+    default: return DPSE_EINVAL;
+  }
+  if (cnt * eb > bytes) return DPSE_EINVAL;
+  if (hipMemcpy(dst, src, cnt * eb, hipMemcpyDeviceToHost) != hipSuccess) return DPSE_EHIP;
+  if (which == DPSE_STAGE_F_O) {
+    // only the wall-band planes are computed; report zeros elsewhere
+    int64_t plane = (int64_t)g.Ny * g.Nx * eb;
+    for (int j = g.top_end; j < g.bot_begin; ++j) std::memset((char*)dst + j * plane, 0, plane);
+  }
+  if (elem_bytes) *elem_bytes = eb;
+  if (count) *count = cnt;
+  return DPSE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+"""ctypes binding of libdpse.so; names follow include/dpse.h."""
+from __future__ import annotations
+
+import ctypes
+import enum
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libdpse.so")
+
+DPSE_FP64 = 0
+DPSE_MIXED = 1
+DPSE_GAUGE_NONE = 1
+DPSE_KMAX_GT = 2
+
+_STATUS = {
+    0: "DPSE_OK", 1: "DPSE_EINVAL", 2: "DPSE_ENOMEM", 3: "DPSE_EHIP", 4: "DPSE_ENONNEUTRAL",
+    5: "DPSE_EOUTSIDE", 6: "DPSE_ECONSTRAINT", 7: "DPSE_ETOOMANY",
+}
+
+
+class Stage(enum.IntEnum):
+    F_I = 0
+    F_O = 1
+    FH_I = 2
+    PSI = 3
+    PSIZ = 4
+    GRIDS = 5
+    FAR = 6
+    NEAR = 7
+    SCALARS = 8
+
+
+class DpseError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {_STATUS.get(status, status)} ({_lib().dpse_status_string(status).decode()})")
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("H", ctypes.c_double),
+                ("eps", ctypes.c_double), ("eps_bottom", ctypes.c_double), ("eps_top", ctypes.c_double),
+                ("xi", ctypes.c_double), ("g_w", ctypes.c_double),
+                ("Nx", ctypes.c_int32), ("Ny", ctypes.c_int32), ("Nz", ctypes.c_int32),
+                ("support", ctypes.c_int32), ("r_cut", ctypes.c_double), ("delta", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("h", ctypes.c_double), ("g_t", ctypes.c_double), ("H_E", ctypes.c_double),
+                ("n_sigma", ctypes.c_double), ("z_lo", ctypes.c_double), ("z_hi", ctypes.c_double),
+                ("r_cut", ctypes.c_double), ("xi_e", ctypes.c_double), ("support", ctypes.c_int32),
+                ("n_modes", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
+                ("max_n", ctypes.c_int64)]
+
+
+_LIB = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2101_07088_amd.build` "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(_LIB_PATH)
+        vp, i64, i32, pd = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+        L.dpse_status_string.restype = ctypes.c_char_p
+        L.dpse_status_string.argtypes = [ctypes.c_int]
+        L.dpse_derive.argtypes = [ctypes.POINTER(_Params), ctypes.POINTER(_Info)]
+        L.dpse_plan_create.argtypes = [ctypes.POINTER(_Params), i64, vp, ctypes.POINTER(vp)]
+        L.dpse_plan_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.dpse_solve.argtypes = [vp, i64, pd, pd, pd, pd, pd]
+        L.dpse_solve_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.dpse_sync.argtypes = [vp]
+        L.dpse_plan_destroy.argtypes = [vp]
+        L.dpse_debug_copy.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+        L.dpse_set_timing.argtypes = [vp, ctypes.c_int]
+        L.dpse_stage_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_int)]
+        L.dpse_stage_name.restype = ctypes.c_char_p
+        L.dpse_stage_name.argtypes = [ctypes.c_int]
+        for name in ("dpse_derive", "dpse_plan_create", "dpse_plan_info", "dpse_solve", "dpse_solve_batch",
+                     "dpse_sync", "dpse_plan_destroy", "dpse_debug_copy", "dpse_set_timing",
+                     "dpse_stage_times"):
+            getattr(L, name).restype = ctypes.c_int
+        _LIB = L
+    return _LIB
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise DpseError(status, where)
+
+
+def _params(p, precision: int = DPSE_FP64, delta: float = 0.0) -> _Params:
+    """Accepts any object with the SlabParams attribute names."""
+    flags = 0
+    if not getattr(p, "gauge", True):
+        flags |= DPSE_GAUGE_NONE
+    if getattr(p, "kmax_gt", False):
+        flags |= DPSE_KMAX_GT
+    return _Params(Lx=p.Lx, Ly=p.Ly, H=p.H, eps=p.eps, eps_bottom=p.eps_b, eps_top=p.eps_t, xi=p.xi,
+                   g_w=getattr(p, "g_w", 0.0), Nx=p.Nx, Ny=p.Ny, Nz=p.Nz, support=getattr(p, "n_g", 0),
+                   r_cut=p.r_cut, delta=delta, precision=precision, flags=flags)
+
+
+def _info_dict(info: _Info) -> dict:
+    return {name: getattr(info, name) for name, _ in _Info._fields_}
+
+
+def derive(params, precision: int = DPSE_FP64) -> dict:
+    """Host-only parameter derivation and validation (no GPU needed)."""
+    prm = _params(params, precision)
+    info = _Info()
+    _check(_lib().dpse_derive(ctypes.byref(prm), ctypes.byref(info)), "dpse_derive")
+    return _info_dict(info)
+
+
+class Plan:
+    """A plan for one slab system on the current HIP device and stream."""
+
+    def __init__(self, params, max_n: int, precision: int = DPSE_FP64, stream=None):
+        import torch
+        self._torch = torch
+        self.params = params
+        self.precision = precision
+        self.max_n = int(max_n)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        prm = _params(params, precision)
+        h = ctypes.c_void_p()
+        _check(_lib().dpse_plan_create(ctypes.byref(prm), self.max_n, ctypes.c_void_p(stream.cuda_stream),
+                                       ctypes.byref(h)), "dpse_plan_create")
+        self._h = h
+        info = _Info()
+        _check(_lib().dpse_plan_info(h, ctypes.byref(info)), "dpse_plan_info")
+        self.info = _info_dict(info)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def solve(self, pos, q, energy=None, phi=None, force=None):
+        """Enqueues a solve. pos: float64 [n,3], q: float64 [n] HIP tensors.
+        Returns (energy[1], phi[n], force[n,3]) device tensors (allocated if
+        not given)."""
+        torch = self._torch
+        n = int(q.shape[0])
+        assert pos.dtype == torch.float64 and q.dtype == torch.float64 and pos.is_cuda and q.is_cuda
+        assert pos.is_contiguous() and q.is_contiguous() and tuple(pos.shape) == (n, 3)
+        dev = pos.device
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=dev)
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=dev)
+        if force is None:
+            force = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        _check(_lib().dpse_solve(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
+                                 force.data_ptr()), "dpse_solve")
+        return energy, phi, force
+
+    def sync(self) -> int:
+        """Waits for the stream; raises DpseError for a device-detected error."""
+        st = _lib().dpse_sync(self._h)
+        _check(st, "dpse_sync")
+        return st
+
+    def sync_status(self) -> int:
+        return _lib().dpse_sync(self._h)
+
+    def debug(self, stage: Stage) -> np.ndarray:
+        """Copies a stage output of the last solve (layouts in include/dpse.h)."""
+        p = self.params
+        nkx = p.Nx // 2 + 1
+        G = p.Nz * p.Ny * p.Nx
+        sizes = {Stage.F_I: G, Stage.F_O: G, Stage.FH_I: 2 * p.Nz * p.Ny * nkx, Stage.PSI: 2 * p.Nz * p.Ny * nkx,
+                 Stage.PSIZ: 2 * p.Nz * p.Ny * nkx, Stage.GRIDS: 4 * G, Stage.FAR: 4 * self.max_n,
+                 Stage.NEAR: 4 * self.max_n, Stage.SCALARS: 8}
+        buf = np.empty(sizes[stage] * 8, dtype=np.uint8)
+        eb = ctypes.c_int32()
+        cnt = ctypes.c_int64()
+        _check(_lib().dpse_debug_copy(self._h, int(stage), buf.ctypes.data, buf.nbytes, ctypes.byref(eb),
+                                      ctypes.byref(cnt)), "dpse_debug_copy")
+        dt = np.float64 if eb.value == 8 else np.float32
+        a = buf[: cnt.value * eb.value].view(dt).astype(np.float64)
+        if stage in (Stage.F_I, Stage.F_O):
+            return a.reshape(p.Nz, p.Ny, p.Nx)
+        if stage in (Stage.FH_I, Stage.PSI, Stage.PSIZ):
+            c = a.reshape(p.Nz, p.Ny, nkx, 2)
+            return c[..., 0] + 1j * c[..., 1]
+        if stage == Stage.GRIDS:
+            return np.moveaxis(a.reshape(p.Nz, p.Ny, p.Nx, 4), -1, 0)
+        if stage in (Stage.FAR, Stage.NEAR):
+            return a.reshape(-1, 4)
+        return a
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib().dpse_set_timing(self._h, int(bool(enable))), "dpse_set_timing")
+
+    def stage_times(self) -> tuple:
+        """Mean per-stage milliseconds over the solves recorded since the last
+        call: (dict name -> ms, number of solves)."""
+        ns = 10
+        ms = (ctypes.c_double * ns)()
+        cnt = ctypes.c_int()
+        _check(_lib().dpse_stage_times(self._h, ms, ns, ctypes.byref(cnt)), "dpse_stage_times")
+        return {_lib().dpse_stage_name(i).decode(): ms[i] for i in range(ns)}, cnt.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().dpse_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Optional[Sequence] = None,
+                phi: Optional[Sequence] = None, force: Optional[Sequence] = None):
+    """Enqueues one solve per plan through dpse_solve_batch; outputs are
+    allocated when not given. Returns lists (energy, phi, force)."""
+    import torch
+    k = len(plans)
+    if energy is None:
+        energy = [torch.empty(1, dtype=torch.float64, device=p_.device) for p_ in pos]
+    if phi is None:
+        phi = [torch.empty(q_.shape[0], dtype=torch.float64, device=q_.device) for q_ in q]
+    if force is None:
+        force = [torch.empty((q_.shape[0], 3), dtype=torch.float64, device=q_.device) for q_ in q]
+    VP = ctypes.c_void_p * k
+    hs = VP(*[p_.handle.value for p_ in plans])
+    ns = (ctypes.c_int64 * k)(*[int(q_.shape[0]) for q_ in q])
+    ptr = lambda ts: VP(*[t.data_ptr() for t in ts])
+    _check(_lib().dpse_solve_batch(k, hs, ns, ptr(pos), ptr(q), ptr(energy), ptr(phi), ptr(force)),
+           "dpse_solve_batch")
+    return energy, phi, force

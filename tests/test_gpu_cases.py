@@ -1,0 +1,142 @@
+"""GPU tests beyond the stage parity: the full jump workload, the mixed
+precision path, edge cases, plan reuse and the device-side validation."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dpse_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def run(p, pos, q, precision=0, plan=None, max_n=None):
+    import paper_2101_07088_amd as dp
+    if plan is None:
+        plan = dp.Plan(p, max_n=max_n or len(q), precision=precision)
+    tp = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    U, phi, F = plan.solve(tp, tq)
+    st = plan.sync_status()
+    return plan, st, float(U.cpu()[0]), phi.cpu().numpy(), F.cpu().numpy()
+
+
+def check(p, pos, q, tol, precision=0, label=""):
+    U0, phi0, F0, _ = O.solve(p, pos, q)
+    _, st, U, phi, F = run(p, pos, q, precision)
+    assert st == 0
+    eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
+    print(f"[case] {label} prec={precision} relRMS F {eF:.2e} phi {ep:.2e}", flush=True)
+    assert eF < tol and ep < tol
+    assert abs(U - U0) < tol * 0.5 * np.sum(np.abs(q * phi0))
+
+
+def small_jump(seed, n_pairs, L=16.0, H=8.0, eb=0.05, et=20.0, z_lo=0.5, z_hi=None):
+    p = W.SlabParams(Lx=L, Ly=L, H=H, eps=1.0, eps_b=eb, eps_t=et, xi=1.0, Nx=int(L / 0.25), Ny=int(L / 0.25),
+                     Nz=33, r_cut=3.0)
+    pos, q = W.charges(seed, n_pairs, n_pairs, L, L, z_lo, z_hi if z_hi is not None else H - 0.5)
+    return p, pos, q
+
+
+def test_jump_workload_full_size_fp64_and_mixed():
+    """N = 16384, 256 x 256 x 129: FP64 at 1e-9 and mixed at 1e-5 against the oracle."""
+    _need_gpu()
+    p, pos, q = W.config_jump(0)
+    print("[case] jump full size: oracle solve ...", flush=True)
+    U0, phi0, F0, inter = O.solve(p, pos, q)
+    for prec, tol in ((0, 1e-9), (1, 1e-5)):
+        _, st, U, phi, F = run(p, pos, q, prec)
+        assert st == 0
+        eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
+        fo = q[:, None] * inter["far"][:, 1:]
+        print(f"[case] jump full prec={prec} relRMS F {eF:.2e} phi {ep:.2e} U {U:.10e} / {U0:.10e}", flush=True)
+        assert eF < tol and ep < tol
+        assert abs(U - U0) < tol * 0.5 * np.sum(np.abs(q * phi0))
+
+
+@pytest.mark.parametrize("eb,et", [(1.0, 1.0), (0.05, 0.05), (0.05, 20.0), (20.0, 1.0)])
+def test_mixed_precision_against_oracle(eb, et):
+    _need_gpu()
+    p, pos, q = small_jump(3, 150, eb=eb, et=et)
+    check(p, pos, q, 1e-5, precision=1, label=f"mixed eb={eb} et={et}")
+
+
+def test_smallest_system_and_boundary_positions():
+    _need_gpu()
+    p = W.SlabParams(Lx=16.0, Ly=16.0, H=8.0, eps=1.0, eps_b=0.2, eps_t=3.0, xi=1.0, Nx=64, Ny=64, Nz=33,
+                     r_cut=3.0)
+    pos = np.array([[0.0, 15.999999999999, 0.5000001], [15.999999999999, 0.0, 7.4999999]])
+    q = np.array([1.0, -1.0])
+    check(p, pos, q, 1e-9, label="two charges at the periodic boundary")
+
+
+def test_only_inner_charges_and_only_wall_charges():
+    _need_gpu()
+    p, pos, q = small_jump(4, 40, H=16.0, z_lo=6.0, z_hi=10.0)   # no charge within 2 H_E of a wall
+    p = p.copy(Nz=65)
+    check(p, pos, q, 1e-9, label="inner only")
+    p, pos, q = small_jump(5, 40, H=16.0, z_lo=0.3, z_hi=2.0)    # all in the bottom band
+    p = p.copy(Nz=65)
+    check(p, pos, q, 1e-9, label="bottom band only")
+
+
+def test_gaussian_charges_and_gauge_off():
+    _need_gpu()
+    p, pos, q = small_jump(6, 50)
+    check(p.copy(g_w=0.05), pos, q, 1e-9, label="g_w=0.05")
+    check(p.copy(gauge=False), pos, q, 1e-9, label="gauge off")
+    check(p.copy(kmax_gt=True), pos, q, 1e-9, label="kmax g_t cap")
+
+
+def test_plan_reuse_with_changing_n():
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_jump(7, 120)
+    plan = dp.Plan(p, max_n=400)
+    for k in (240, 60, 240):
+        # a neutral subset: the first k/2 positive and the first k/2 negative charges
+        sel = np.sort(np.concatenate([np.nonzero(q > 0)[0][: k // 2], np.nonzero(q < 0)[0][: k // 2]]))
+        pp, qq = pos[sel], q[sel]
+        U0, phi0, F0, _ = O.solve(p, pp, qq)
+        _, st, U, phi, F = run(p, pp, qq, plan=plan)
+        assert st == 0
+        assert rel_rms(F, F0) < 1e-9 and rel_rms(phi, phi0) < 1e-9
+
+
+def test_device_validation_status():
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_jump(8, 20)
+    bad = pos.copy(); bad[3, 2] = p.H + 0.1
+    assert run(p, bad, q)[1] == 5          # DPSE_EOUTSIDE
+    bad = pos.copy(); bad[4, 0] = float("nan")
+    assert run(p, bad, q)[1] == 5
+    qq = q.copy(); qq[0] += 0.5
+    assert run(p, pos, qq)[1] == 4         # DPSE_ENONNEUTRAL
+    # far-field constraint 2 H_E < H + h_min (Sec. 5.3): H_E = 2.25, H = 3.2, a charge 0.4 from a wall
+    pc = p.copy(H=3.2)
+    pz = pos.copy(); pz[:, 2] = 1.6; pz[0, 2] = 0.4
+    assert run(pc, pz, q)[1] == 6          # DPSE_ECONSTRAINT
+    # the plan still works after errors
+    plan, st, U, phi, F = run(p, pos, q)
+    assert st == 0
+    with pytest.raises(dp.DpseError):
+        plan.solve(torch.zeros((len(q) + 1, 3), dtype=torch.float64, device="cuda"),
+                   torch.zeros(len(q) + 1, dtype=torch.float64, device="cuda"))
+
+
+def test_repeat_solves_agree():
+    _need_gpu()
+    p, pos, q = small_jump(9, 100)
+    plan, _, U1, phi1, F1 = run(p, pos, q)
+    _, _, U2, phi2, F2 = run(p, pos, q, plan=plan)
+    assert rel_rms(F2, F1) < 1e-13 and abs(U2 - U1) < 1e-12 * abs(U1)

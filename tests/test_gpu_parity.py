@@ -1,0 +1,103 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+FP64 bar: relative RMS force error <= 1e-9 (and the same bar for potentials
+and energy) against the oracle on identical seeded inputs; every stage output
+is also compared with the oracle's intermediate array of that stage.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dpse_oracle as O
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def gpu_solve(p, pos, q, precision=0, plan=None):
+    import paper_2101_07088_amd as dp
+    if plan is None:
+        plan = dp.Plan(p, max_n=len(q), precision=precision)
+    tp = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    U, phi, F = plan.solve(tp, tq)
+    plan.sync()
+    return plan, float(U.cpu()[0]), phi.cpu().numpy(), F.cpu().numpy()
+
+
+def jump_tiles(seed=1, n_pairs=100, eps_b=0.05, eps_t=20.0, Lx=16.0, Ly=16.0, H=8.0):
+    """Several spreading/interpolation tiles, both walls with images, Nz = 33."""
+    p = W.SlabParams(Lx=Lx, Ly=Ly, H=H, eps=1.0, eps_b=eps_b, eps_t=eps_t, xi=1.0, Nx=int(Lx / 0.25),
+                     Ny=int(Ly / 0.25), Nz=33, r_cut=3.0)
+    pos, q = W.charges(seed, n_pairs, n_pairs, Lx, Ly, 0.5, H - 0.5)
+    return p, pos, q
+
+
+CASES = {
+    "small": lambda: W.config_small(0),
+    "jump_tiles": lambda: jump_tiles(),
+    "rect_box": lambda: jump_tiles(seed=2, n_pairs=60, eps_b=0.5, eps_t=0.05, Lx=16.0, Ly=8.0, H=6.0),
+}
+
+
+def _stage_report(plan, inter, p, n):
+    import paper_2101_07088_amd as dp
+    S = dp.Stage
+    out = {}
+    out["f_i"] = rel_max(plan.debug(S.F_I), inter["f_i"])
+    out["f_o"] = rel_max(plan.debug(S.F_O), inter["f_o"]) if np.any(inter["f_o"]) else 0.0
+    out["FH_i"] = rel_max(plan.debug(S.FH_I), inter["F_i"])
+    out["Psi"] = rel_max(plan.debug(S.PSI), inter["Psi"])
+    out["Psi_z"] = rel_max(plan.debug(S.PSIZ), inter["Psi_z"])
+    out["grids"] = rel_max(plan.debug(S.GRIDS), inter["grids"])
+    out["far"] = rel_max(plan.debug(S.FAR)[:n], inter["far"])
+    out["near"] = rel_max(plan.debug(S.NEAR)[:n], inter["near"])
+    sc = plan.debug(S.SCALARS)
+    out["A_i"] = abs(sc[3] - inter["A_i"].real) / max(abs(inter["A_i"].real), 1e-300)
+    out["far0"] = abs(sc[4] - inter["far0"]) / max(abs(inter["far0"]), 1e-300)
+    out["near0"] = abs(sc[5] - inter["near0"]) / max(abs(inter["near0"]), 1e-300)
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fp64_stages_and_outputs_match_oracle(name):
+    _need_gpu()
+    p, pos, q = CASES[name]()
+    print(f"[parity] case={name} N={len(q)} grid={p.Nx}x{p.Ny}x{p.Nz}", flush=True)
+    U0, phi0, F0, inter = O.solve(p, pos, q)
+    plan, U, phi, F = gpu_solve(p, pos, q)
+    rep = _stage_report(plan, inter, p, len(q))
+    print("[parity] stages:", {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
+    for k in ("f_i", "f_o", "FH_i", "far", "near"):
+        assert rep[k] < 1e-12, (k, rep[k])
+    # node values of the harmonic correction grow like e^{k H_E} towards the
+    # edges of its window (Sec. 5.2.2 step 4), which magnifies rounding
+    # differences of the mismatches there; the interpolated results are not
+    # affected (checked below at the 1e-9 bar)
+    for k in ("Psi", "Psi_z", "grids"):
+        assert rep[k] < 1e-8, (k, rep[k])
+    errF = rel_rms(F, F0)
+    errp = rel_rms(phi, phi0)
+    print(f"[parity] relRMS F {errF:.2e} phi {errp:.2e} U {U:.12e} vs {U0:.12e}", flush=True)
+    assert errF < TOL
+    assert errp < TOL
+    assert abs(U - U0) < TOL * 0.5 * np.sum(np.abs(q * phi0))
