@@ -78,8 +78,8 @@ typedef struct {
   double eps, eps_bottom, eps_top;  /* permittivities; > 0                                   */
   double xi;                        /* Ewald splitting parameter (eq. gamreal); > 0          */
   double g_w;                       /* Gaussian charge width (eq. gcharge); >= 0             */
-  int32_t Nx, Ny, Nz;               /* grid; Nx, Ny powers of two in [8, 1024]; Nz - 1 a power of two in [4, 1024]; Lx/Nx == Ly/Ny */
-  int32_t support;                  /* n_g, even, 0 = 2*ceil(4.3*g_t/h); n_g <= min(Nx, Ny)  */
+  int32_t Nx, Ny, Nz;               /* grid; Nx, Ny powers of two in [32, 1024]; Nz - 1 a power of two in [32, 1024]; Lx/Nx == Ly/Ny */
+  int32_t support;                  /* n_g, even, <= 32; 0 = 2*ceil(4.3*g_t/h)               */
   double r_cut;                     /* near cutoff, 0 < r_cut < min(Lx, Ly)/2; 0 = derive from delta (eq. rnf) */
   double delta;                     /* tolerance used when r_cut == 0 (default 1e-4 if 0)    */
   int32_t precision;                /* DPSE_FP64 or DPSE_MIXED                               */

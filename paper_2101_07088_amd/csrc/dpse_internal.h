@@ -41,10 +41,16 @@ struct Part {
 // Group of an extended particle (charge or image), stored in meta & 3.
 enum { GRP_WALL = 0, GRP_INNER = 1, GRP_IMAGE = 2 };
 
+// Layout of Tables::ctab.
+constexpr int kCtabRows = 4;   // a_n, b_n, c_n, rhs scale
+constexpr int kNumFun = 10;    // S1, S2, S3, S4, V0, VH, D0, DH, Ea, Eb
+enum { FUN_S1 = 0, FUN_S2, FUN_S3, FUN_S4, FUN_V0, FUN_VH, FUN_D0, FUN_DH, FUN_EA, FUN_EB };
+
 // Launch shapes.
 constexpr int kSpreadT = 32;  // spreading tile (grid cells per side)
-constexpr int kInterpT = 16;  // interpolation tile
+constexpr int kInterpT = 32;  // interpolation tile
 constexpr int kBin = 16;      // particle bin width (grid cells)
+constexpr int kMaxSupport = 32;  // n_g <= the tile width (one contiguous window run per tile)
 
 template <typename R>
 struct Cplx;
@@ -99,6 +105,11 @@ struct Tables {
   double2* twx = nullptr;   // exp(-2 pi i k/Nx), k < Nx/2
   double2* twy = nullptr;   // exp(-2 pi i k/Ny)
   double2* twz = nullptr;   // exp(-2 pi i k/(2(Nz-1)))
+  // per-mode solver tables, [kCtabRows * Nz + kNumFun * (Nz + 2)] doubles:
+  // chain coefficients a_n, b_n, c_n, the right-hand-side scale of each
+  // Chebyshev coefficient, then weight vectors of the linear functionals
+  // (on y''_0..y''_{N-1}, y_0, y'_0; see k_column.hip)
+  double* ctab = nullptr;
   float2* twx_f = nullptr;
   float2* twy_f = nullptr;
 };

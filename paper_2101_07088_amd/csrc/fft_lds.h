@@ -52,4 +52,110 @@ __device__ void fft_lds(C* buf, int logL, int nseq, int ss, int es, const C* tw,
   }
 }
 
+// Same transform with a compile-time count of butterflies per thread and
+// stage (nseq * L/2 == BPT * nthr): the loads of all BPT butterflies are
+// issued before any arithmetic, so their latencies overlap.
+template <typename C, bool SEQ_FAST, int BPT, int NTHR>
+__device__ void fft_lds_u(C* buf, int logL, int nseq, int ss, int es, const C* tw, bool inverse, int tid) {
+  const int nb = (1 << logL) >> 1;
+  for (int lh = 0; lh < logL; ++lh) {
+    const int half = 1 << lh;
+    const int tstride = nb >> lh;
+    C u[BPT], v[BPT], w[BPT];
+    int p0[BPT], p1[BPT];
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int t = tid + q * NTHR;
+      int s, b;
+      if (SEQ_FAST) { s = t % nseq; b = t / nseq; }
+      else { b = t % nb; s = t / nb; }
+      const int grp = b >> lh, pos = b & (half - 1);
+      const int i0 = (grp << (lh + 1)) + pos;
+      p0[q] = s * ss + i0 * es;
+      p1[q] = p0[q] + half * es;
+      w[q] = tw[pos * tstride];
+      u[q] = buf[p0[q]];
+      v[q] = buf[p1[q]];
+    }
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      C ww = w[q];
+      if (inverse) ww.y = -ww.y;
+      const C vw = cmul(v[q], ww);
+      buf[p0[q]] = cadd(u[q], vw);
+      buf[p1[q]] = csub(u[q], vw);
+    }
+    __syncthreads();
+  }
+}
+
+// Radix-2^2 version: one pass fuses the radix-2 stages lh and lh+1 on four
+// elements (i, i+h, i+2h, i+3h), halving LDS traffic and barriers; an odd
+// log-length starts with one radix-2 stage. BPT4 = nseq * L/4 / NTHR.
+template <typename C, bool SEQ_FAST, int BPT4, int NTHR>
+__device__ void fft_lds_r22(C* buf, int logL, int lognseq, int ss, int es, const C* tw, bool inverse, int tid) {
+  const int nseq = 1 << lognseq;
+  const int L = 1 << logL;
+  const int nb4 = L >> 2;
+  const int lognb4 = logL - 2;
+  int lh = 0;
+  if (logL & 1) {
+    // first radix-2 stage (half = 1, twiddle 1): pairs (2b, 2b+1)
+#pragma unroll
+    for (int q = 0; q < 2 * BPT4; ++q) {
+      const int t = tid + q * NTHR;
+      int s, b;
+      if (SEQ_FAST) { s = t & (nseq - 1); b = t >> lognseq; }
+      else { b = t & ((L >> 1) - 1); s = t >> (logL - 1); }
+      C* p0 = buf + s * ss + (2 * b) * es;
+      C* p1 = p0 + es;
+      const C u = *p0, v = *p1;
+      *p0 = cadd(u, v);
+      *p1 = csub(u, v);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  for (; lh < logL; lh += 2) {
+    const int half = 1 << lh;
+    const int ts1 = (L >> 1) >> lh;   // twiddle stride of stage lh: L / (2 half)
+    const int ts2 = ts1 >> 1;         // of stage lh + 1: L / (4 half)
+    C a[BPT4][4], w1[BPT4], w2[BPT4];
+    int base[BPT4];
+#pragma unroll
+    for (int q = 0; q < BPT4; ++q) {
+      const int t = tid + q * NTHR;
+      int s, b;
+      if (SEQ_FAST) { s = t & (nseq - 1); b = t >> lognseq; }
+      else { b = t & (nb4 - 1); s = t >> lognb4; }
+      const int grp = b >> lh, pos = b & (half - 1);
+      base[q] = s * ss + ((grp << (lh + 2)) + pos) * es;
+      w1[q] = tw[pos * ts1];
+      w2[q] = tw[pos * ts2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[q][e] = buf[base[q] + e * half * es];
+    }
+#pragma unroll
+    for (int q = 0; q < BPT4; ++q) {
+      C x1 = w1[q], x2 = w2[q];
+      if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
+      const C t1 = cmul(a[q][1], x1), t3 = cmul(a[q][3], x1);
+      const C b0 = cadd(a[q][0], t1), b1 = csub(a[q][0], t1);
+      const C b2 = cadd(a[q][2], t3), b3 = csub(a[q][2], t3);
+      const C u2 = cmul(b2, x2);
+      C u3 = cmul(b3, x2);  // times -i (forward) or +i (inverse)
+      {
+        const auto re = u3.x;
+        if (inverse) { u3.x = -u3.y; u3.y = re; }
+        else { u3.x = u3.y; u3.y = -re; }
+      }
+      buf[base[q]] = cadd(b0, u2);
+      buf[base[q] + 2 * half * es] = csub(b0, u2);
+      buf[base[q] + half * es] = cadd(b1, u3);
+      buf[base[q] + 3 * half * es] = csub(b1, u3);
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dpse

@@ -46,21 +46,15 @@ __device__ inline int ilog2d(int v) {
   return l;
 }
 
-// Coefficients of y_n = a_n y''_{n-2} - b_n y''_n + c_n y''_{n+2} (n >= 2) and
-// y_1 = y'_0 - b_1 y''_1 + c_1 y''_3, from eqs. ds and cs with y''_n = 0 for
-// n > N-1 and y'_N = 0.
-__device__ inline void chain_coeffs(int n, int N, double& a, double& b, double& c) {
-  double dn = (double)n;
-  if (n == 0) { a = 0.0; b = 0.0; c = 0.0; return; }
-  if (n == 1) { a = 0.0; b = 0.125; c = 0.125; return; }
-  if (n == 2) { a = 0.25; b = 1.0 / 6.0; c = 1.0 / 24.0; }
-  else {
-    a = 1.0 / (4.0 * dn * (dn - 1.0));
-    b = 1.0 / (2.0 * (dn * dn - 1.0));
-    c = 1.0 / (4.0 * dn * (dn + 1.0));
-  }
-  if (n >= N - 2) c = 0.0;
-  if (n == N - 1) b = 1.0 / (4.0 * dn * (dn - 1.0));
+// Reciprocal of a double: hardware estimate refined by two Newton steps
+// (relative error at the level of the last bit; the solve needs no correctly
+// rounded division).
+__device__ inline double rcp_refined(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
 }
 
 template <typename R>
@@ -68,26 +62,37 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
                                                      const typename CT<R>::T* __restrict__ fx_o,
                                                      typename CT<R>::T* __restrict__ psi,
                                                      typename CT<R>::T* __restrict__ psiz,
-                                                     const double* __restrict__ zn, const double* __restrict__ T0,
-                                                     const double* __restrict__ TH, const double* __restrict__ dT0,
-                                                     const double* __restrict__ dTH,
+                                                     const double* __restrict__ zn,
+                                                     const double* __restrict__ ctab,
                                                      const double2* __restrict__ twz, double* scal) {
   using C = typename CT<R>::T;
-  __shared__ double2 A[kElems];  // psi_o* work, later derivative coefficients
-  __shared__ double2 B[kElems];  // psi_i* work
+  extern __shared__ double2 smem2[];
+  double2* A = smem2;               // psi_o* work, later the final series of psi_i*
+  double2* B = smem2 + kElems;      // psi_i* work, later its derivative series
+  double2* tw = smem2 + 2 * kElems; // twiddles exp(-2 pi i k / M), k < M/2
+  // chain coefficients a_n, b_n, c_n and rhs scales (4 Nz doubles), then the
+  // functionals of phase 3 (MB x 44 doubles)
+  double* lco = reinterpret_cast<double*>(tw + (g.Nz - 1));
   __shared__ double s_k[kMaxMB], s_kap[kMaxMB];
   __shared__ int s_keep[kMaxMB];
-  __shared__ double2 s_val[2][kMaxMB][4];  // [i/o][mode][v0, vH, d0, dH]
-  __shared__ double s_end[kMaxMB][2];      // d psi_o*/dz at z = a, b (k = 0)
-  __shared__ double2 s_ab[kMaxMB][2];      // alpha, beta
+  __shared__ double2 s_c[kMaxMB][2];      // free constants (y_0, y'_0) of psi_i*
+  __shared__ double2 s_ab[kMaxMB][2];     // correction alpha, beta
   __shared__ double s_Ai[kMaxMB];
 
   const int N = g.Nz, M = 2 * (N - 1), logM = ilog2d(M);
   const int MB = kElems / M;
+  const int logMB = 11 - logM;  // kElems = 2^11
+  const int NU = N + 2;
   const int nmodes = g.Ny * g.nkx;
   const int m0 = blockIdx.x * MB;
   const int tid = threadIdx.x;
   const double Rz = g.zR;
+  for (int i = tid; i < kCtabRows * N; i += kThreads) lco[i] = ctab[i];
+  const double* ca = lco;
+  const double* cb = lco + N;
+  const double* cc = lco + 2 * N;
+  const double* gsc = lco + 3 * N;
+  const double* W = ctab + kCtabRows * N;
 
   if (tid < MB) {
     int mi = m0 + tid;
@@ -109,9 +114,10 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     s_keep[tid] = keep;
   }
 
+  for (int i = tid; i < M / 2; i += kThreads) tw[i] = twz[i];
   // 1. even extension of the node values in bit-reversed order, then FFT
   for (int t = tid; t < M * MB; t += kThreads) {
-    int j = t / MB, m = t % MB, mi = m0 + m;
+    int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
     int c = j < N ? j : M - j;
     double2 vo = make_double2(0.0, 0.0), vi = make_double2(0.0, 0.0);
     if (mi < nmodes) {
@@ -128,204 +134,137 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     B[pos] = vi;
   }
   __syncthreads();
-  fft_lds<double2, true>(A, logM, MB, 1, MB, twz, false, tid, kThreads);
-  fft_lds<double2, true>(B, logM, MB, 1, MB, twz, false, tid, kThreads);
+  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(A, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(B, logM, logMB, 1, MB, tw, false, tid);
 
-  // 2. tridiagonal chains; thread = (mode, parity)
-  double* spA = reinterpret_cast<double*>(A + N * MB);  // spare: chain pivots cp
-  double* spB = reinterpret_cast<double*>(B + N * MB);  // spare: homogeneous solutions
-  // spare slot of (mode m, index idx): idx-th double after position N of mode m
+  // spare storage beyond index N of each buffer (N-2 complex = 2N-4 doubles per mode)
+  double* spA = reinterpret_cast<double*>(A + N * MB);  // chain pivots
+  double* spB = reinterpret_cast<double*>(B + N * MB);  // homogeneous solutions
   auto spare = [&](double* base, int m, int idx) -> double& {
     return base[(idx >> 1) * 2 * MB + 2 * m + (idx & 1)];
   };
   const int half0 = (N + 1) / 2;  // rows of the even chain
-  if (tid < 2 * MB) {
-    const int m = tid % MB, par = tid / MB;
+  double* s_fun = lco + kCtabRows * N;  // [MB][10][6]
+  // homogeneous y'' of chain parity n&1 at index n
+  auto hval = [&](int m, int n) -> double { return spare(spB, m, (n & 1) * half0 + (n >> 1)); };
+
+  // 2. tridiagonal chains: for each mode and parity, the mode equations in the
+  //    unknowns y''_n of that parity, with right-hand sides Re/Im g of psi_i*,
+  //    psi_o*, and the unit free constant (kappa^2 on the chain's first row).
+  //    Four threads per chain, one real right-hand side each (the first also
+  //    carries the free constant); each recomputes the elimination pivots.
+  if (tid < 8 * MB) {
+    const int k = tid >> (logMB + 1);          // right-hand side: 0 Re i, 1 Im i, 2 Re o, 3 Im o
+    const int cm = tid & (2 * MB - 1);
+    const int m = cm & (MB - 1), par = cm >> logMB;
+    double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);  // X[n * 2 MB]
     const double kap2 = s_kap[m] * s_kap[m];
-    const double gs = -Rz * Rz / (g.eps * (double)(N - 1));
-    double cp = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0, dh = 0.0;
+    double cp = 0.0, d = 0.0, dh = 0.0;
     int r = 0;
     for (int n = par; n < N; n += 2, ++r) {
-      double a, b, c;
-      chain_coeffs(n, N, a, b, c);
-      double sub = -kap2 * a, dia = 1.0 + kap2 * b, sup = -kap2 * c;
-      double den = r == 0 ? dia : dia - sub * cp;
-      double inv = 1.0 / den;
-      double scale = gs * ((n == 0 || n == N - 1) ? 0.5 : 1.0);
-      double2 gi = B[n * MB + m], go = A[n * MB + m];
-      double rh0 = scale * gi.x, rh1 = scale * gi.y, rh2 = scale * go.x, rh3 = scale * go.y;
-      double rhh = r == 0 ? kap2 : 0.0;
-      if (r == 0) {
-        d0 = rh0 * inv; d1 = rh1 * inv; d2 = rh2 * inv; d3 = rh3 * inv; dh = rhh * inv;
-      } else {
-        d0 = (rh0 - sub * d0) * inv; d1 = (rh1 - sub * d1) * inv;
-        d2 = (rh2 - sub * d2) * inv; d3 = (rh3 - sub * d3) * inv;
-        dh = (rhh - sub * dh) * inv;
+      const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
+      const double inv = rcp_refined(fma(-sub, cp, dia));
+      d = (gsc[n] * X[n * 2 * MB] - sub * d) * inv;
+      X[n * 2 * MB] = d;
+      if (k == 0) {
+        dh = ((r == 0 ? kap2 : 0.0) - sub * dh) * inv;
+        spare(spB, m, par * half0 + r) = dh;
       }
       cp = sup * inv;
-      spare(spA, m, par * half0 + r) = cp;
-      B[n * MB + m] = make_double2(d0, d1);
-      A[n * MB + m] = make_double2(d2, d3);
-      spare(spB, m, par * half0 + r) = dh;
+      if (k == 0) spare(spA, m, par * half0 + r) = cp;
     }
-    // back substitution
-    int rl = r - 1;
-    int nl = par + 2 * rl;
-    double2 xi = B[nl * MB + m], xo = A[nl * MB + m];
-    double xh = spare(spB, m, par * half0 + rl);
-    for (int rr = rl - 1; rr >= 0; --rr) {
-      int n = par + 2 * rr;
-      double c = spare(spA, m, par * half0 + rr);
-      double2 di = B[n * MB + m], dd = A[n * MB + m];
-      double dhh = spare(spB, m, par * half0 + rr);
-      xi = make_double2(di.x - c * xi.x, di.y - c * xi.y);
-      xo = make_double2(dd.x - c * xo.x, dd.y - c * xo.y);
-      xh = dhh - c * xh;
-      B[n * MB + m] = xi;
-      A[n * MB + m] = xo;
-      spare(spB, m, par * half0 + rr) = xh;
+  }
+  __syncthreads();
+  if (tid < 8 * MB) {
+    const int k = tid >> (logMB + 1);
+    const int cm = tid & (2 * MB - 1);
+    const int m = cm & (MB - 1), par = cm >> logMB;
+    double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);
+    const int L = par == 0 ? (N + 1) / 2 : N / 2;
+    double x = X[(par + 2 * (L - 1)) * 2 * MB];
+    double xh = spare(spB, m, par * half0 + L - 1);
+    for (int r = L - 2; r >= 0; --r) {
+      const int n = par + 2 * r;
+      const double c = spare(spA, m, par * half0 + r);
+      x = fma(-c, x, X[n * 2 * MB]);
+      X[n * 2 * MB] = x;
+      if (k == 0) {  // the only thread touching this chain's homogeneous entries
+        xh = fma(-c, xh, spare(spB, m, par * half0 + r));
+        spare(spB, m, par * half0 + r) = xh;
+      }
     }
   }
   __syncthreads();
 
-  // 3. boundary conditions, 2x2 Schur step, final coefficients; thread = (mode, i/o)
-  if (tid < 2 * MB) {
-    const int m = tid % MB, which = tid / MB;  // 0: psi_i* in B, 1: psi_o* in A
-    double2* X = which == 0 ? B : A;
-    const double kap = s_kap[m];
-    const bool dir = !(s_k[m] > 0.0);
-    auto ypp = [&](int n) -> double2 { return n < N ? X[n * MB + m] : make_double2(0.0, 0.0); };
-    auto hpp = [&](int n) -> double {  // homogeneous y'' (h1 on even n, h2 on odd n)
-      return n < N ? spare(spB, m, (n & 1) * half0 + (n >> 1)) : 0.0;
-    };
-    // derivative coefficient y'_n of the particular solution and of h1, h2
-    auto yp = [&](int n, double2& P, double& h1, double& h2) {
-      if (n == 0) { P = make_double2(0.0, 0.0); h1 = 0.0; h2 = 1.0; return; }
-      if (n >= N) { P = make_double2(0.0, 0.0); h1 = 0.0; h2 = 0.0; return; }
-      double2 lo = ypp(n - 1), hi = ypp(n + 1);
-      double hl = hpp(n - 1), hh = hpp(n + 1);
-      if (n == 1) {
-        P = make_double2(lo.x - 0.5 * hi.x, lo.y - 0.5 * hi.y);
-        double v = hl - 0.5 * hh;
-        h1 = (n - 1) % 2 == 0 ? v : 0.0;  // y''_0, y''_2 belong to the even chain (h1)
-        h2 = (n - 1) % 2 == 0 ? 0.0 : v;
-        return;
-      }
-      double f = 1.0 / (2.0 * n);
-      P = make_double2(f * (lo.x - hi.x), f * (lo.y - hi.y));
-      double v = f * (hl - hh);
-      // y''_{n-1}, y''_{n+1} have the parity of n-1
-      h1 = ((n - 1) & 1) == 0 ? v : 0.0;
-      h2 = ((n - 1) & 1) == 0 ? 0.0 : v;
-    };
-    // pass 1: boundary functionals
-    double2 tP = make_double2(0.0, 0.0), bP = make_double2(0.0, 0.0);
-    double t1 = 0.0, t2 = 0.0, b1 = 0.0, b2 = 0.0;
-    double2 pm, pc, pp;
-    double hm1, hm2, hc1, hc2, hp1, hp2;
-    // sliding window: pm = y'_{n-1}, pc = y'_n, pp = y'_{n+1}
-    pm = make_double2(0.0, 0.0); hm1 = 0.0; hm2 = 0.0;
-    yp(0, pc, hc1, hc2);
-    for (int n = 0; n < N; ++n) {
-      yp(n + 1, pp, hp1, hp2);
-      double2 Py;
-      double y1, y2;
-      if (n == 0) { Py = make_double2(0.0, 0.0); y1 = 1.0; y2 = 0.0; }
-      else if (n == 1) {  // y_1 = y'_0 - y'_2 / 2
-        Py = make_double2(pm.x - 0.5 * pp.x, pm.y - 0.5 * pp.y);
-        y1 = hm1 - 0.5 * hp1; y2 = hm2 - 0.5 * hp2;
-      } else {
-        double f = 1.0 / (2.0 * n);
-        double2 q = n + 1 < N ? pp : make_double2(0.0, 0.0);
-        double q1 = n + 1 < N ? hp1 : 0.0, q2 = n + 1 < N ? hp2 : 0.0;
-        Py = make_double2(f * (pm.x - q.x), f * (pm.y - q.y));
-        y1 = f * (hm1 - q1); y2 = f * (hm2 - q2);
-      }
-      double sg = (n & 1) ? -1.0 : 1.0;
-      if (dir) {
-        tP.x += Py.x; tP.y += Py.y; t1 += y1; t2 += y2;
-        bP.x += sg * Py.x; bP.y += sg * Py.y; b1 += sg * y1; b2 += sg * y2;
-      } else {
-        tP.x += pc.x + kap * Py.x; tP.y += pc.y + kap * Py.y;
-        t1 += hc1 + kap * y1; t2 += hc2 + kap * y2;
-        bP.x += sg * (pc.x - kap * Py.x); bP.y += sg * (pc.y - kap * Py.y);
-        b1 += sg * (hc1 - kap * y1); b2 += sg * (hc2 - kap * y2);
-      }
-      pm = pc; hm1 = hc1; hm2 = hc2;
-      pc = pp; hc1 = hp1; hc2 = hp2;
+  // 3. linear functionals of each solution vector: dot products of y'' (and
+  //    the free constants) with the plan's weight vectors S1..S4 (boundary
+  //    rows), V0, VH, D0, DH (values and z-derivatives at z = 0, H), Ea, Eb
+  //    (slopes at the domain ends). One thread per (mode, weight vector) sums
+  //    over all indices for six vectors: psi_i* re/im, psi_o* re/im, h1, h2.
+  //    s_fun[(m * 10 + f) * 6 + v].
+  for (int t = tid; t < MB * 10; t += kThreads) {
+    const int m = t / 10, f = t - 10 * m;
+    const double* Wf = W + f * NU;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = Wf[N], a5 = Wf[N + 1];
+#pragma unroll 4
+    for (int j = 0; j < N; ++j) {
+      const double w = Wf[j];
+      const double2 xi = B[j * MB + m], xo = A[j * MB + m];
+      const double hv = hval(m, j);
+      a0 = fma(w, xi.x, a0);
+      a1 = fma(w, xi.y, a1);
+      a2 = fma(w, xo.x, a2);
+      a3 = fma(w, xo.y, a3);
+      if (j & 1) a5 = fma(w, hv, a5); else a4 = fma(w, hv, a4);
     }
-    // [t1 t2; b1 b2] [y0; y0'] = -[tP; bP]
-    double det = t1 * b2 - t2 * b1;
-    double2 c0 = make_double2(-(tP.x * b2 - t2 * bP.x) / det, -(tP.y * b2 - t2 * bP.y) / det);
-    double2 c1 = make_double2(-(t1 * bP.x - tP.x * b1) / det, -(t1 * bP.y - tP.y * b1) / det);
-    // pass 2: final coefficients y_n = P_n + c0 h1_n + c1 h2_n, written in place
-    pm = make_double2(0.0, 0.0); hm1 = 0.0; hm2 = 0.0;
-    yp(0, pc, hc1, hc2);
-    for (int n = 0; n < N; ++n) {
-      yp(n + 1, pp, hp1, hp2);
-      double2 Py;
-      double y1, y2;
-      if (n == 0) { Py = make_double2(0.0, 0.0); y1 = 1.0; y2 = 0.0; }
-      else if (n == 1) {
-        Py = make_double2(pm.x - 0.5 * pp.x, pm.y - 0.5 * pp.y);
-        y1 = hm1 - 0.5 * hp1; y2 = hm2 - 0.5 * hp2;
-      } else {
-        double f = 1.0 / (2.0 * n);
-        double2 q = n + 1 < N ? pp : make_double2(0.0, 0.0);
-        double q1 = n + 1 < N ? hp1 : 0.0, q2 = n + 1 < N ? hp2 : 0.0;
-        Py = make_double2(f * (pm.x - q.x), f * (pm.y - q.y));
-        y1 = f * (hm1 - q1); y2 = f * (hm2 - q2);
-      }
-      pm = pc; hm1 = hc1; hm2 = hc2;
-      pc = pp; hc1 = hp1; hc2 = hp2;
-      // position n is no longer read: y''_n was consumed by y'_{n-1} and y'_{n+1}
-      X[n * MB + m] = make_double2(Py.x + c0.x * y1 + c1.x * y2, Py.y + c0.y * y1 + c1.y * y2);
-    }
+    double* o = s_fun + (m * 10 + f) * 6;
+    o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
   }
   __syncthreads();
 
-  // 4. values and derivatives at the walls (and slopes at the domain ends)
-  if (tid < 2 * MB) {
-    const int m = tid % MB, which = tid / MB;
-    const double2* X = which == 0 ? B : A;
-    double2 v0 = make_double2(0, 0), vH = v0, d0 = v0, dH = v0;
-    double ea = 0.0, eb = 0.0;
-    for (int n = 0; n < N; ++n) {
-      double2 y = X[n * MB + m];
-      double t0 = T0[n], tH = TH[n], e0 = dT0[n], eH = dTH[n];
-      v0.x += y.x * t0; v0.y += y.y * t0;
-      vH.x += y.x * tH; vH.y += y.y * tH;
-      d0.x += y.x * e0; d0.y += y.y * e0;
-      dH.x += y.x * eH; dH.y += y.y * eH;
-      double n2 = (double)n * n;
-      eb += y.x * n2;
-      ea += ((n & 1) ? 1.0 : -1.0) * y.x * n2;  // T_n'(-1) = (-1)^(n+1) n^2
-    }
-    s_val[which][m][0] = v0;
-    s_val[which][m][1] = vH;
-    s_val[which][m][2] = d0;
-    s_val[which][m][3] = dH;
-    if (which == 1) {
-      s_end[m][0] = ea / Rz;
-      s_end[m][1] = eb / Rz;
-    }
-  }
-  __syncthreads();
-
-  // 5. mismatches, harmonic correction, k = 0 linear mode; derivative coefficients
+  // 4. per mode: free constants, wall values, mismatches, harmonic correction, k = 0
   if (tid < MB) {
     const int m = tid;
+    const double* F = s_fun + m * 60;  // F[f * 6 + v]
+    const double kap = s_kap[m];
+    const bool dir = !(s_k[m] > 0.0);
+    // boundary rows: Robin top S1 + kap S2, bottom S3 - kap S4; Dirichlet S2, S4
+    auto top = [&](int v) { return dir ? F[FUN_S2 * 6 + v] : fma(kap, F[FUN_S2 * 6 + v], F[FUN_S1 * 6 + v]); };
+    auto bot = [&](int v) { return dir ? F[FUN_S4 * 6 + v] : fma(-kap, F[FUN_S4 * 6 + v], F[FUN_S3 * 6 + v]); };
+    const double t1 = top(4), t2 = top(5), b1 = bot(4), b2 = bot(5);
+    const double det = t1 * b2 - t2 * b1;
+    auto solve2 = [&](double tP, double bP, double& c0, double& c1) {
+      c0 = -(tP * b2 - t2 * bP) / det;
+      c1 = -(t1 * bP - tP * b1) / det;
+    };
+    double ci0r, ci1r, ci0i, ci1i, co0r, co1r, co0i, co1i;
+    solve2(top(0), bot(0), ci0r, ci1r);
+    solve2(top(1), bot(1), ci0i, ci1i);
+    solve2(top(2), bot(2), co0r, co1r);
+    solve2(top(3), bot(3), co0i, co1i);
+    s_c[m][0] = make_double2(ci0r, ci0i);
+    s_c[m][1] = make_double2(ci1r, ci1i);
+    // functional f of the final solutions: particular + y_0 h1 + y'_0 h2
+    auto fin_i = [&](int f) {
+      return make_double2(F[f * 6 + 0] + ci0r * F[f * 6 + 4] + ci1r * F[f * 6 + 5],
+                          F[f * 6 + 1] + ci0i * F[f * 6 + 4] + ci1i * F[f * 6 + 5]);
+    };
+    auto fin_o = [&](int f) {
+      return make_double2(F[f * 6 + 2] + co0r * F[f * 6 + 4] + co1r * F[f * 6 + 5],
+                          F[f * 6 + 3] + co0i * F[f * 6 + 4] + co1i * F[f * 6 + 5]);
+    };
+    const double2 vi0 = fin_i(FUN_V0), viH = fin_i(FUN_VH), di0 = fin_i(FUN_D0), diH = fin_i(FUN_DH);
+    const double2 vo0 = fin_o(FUN_V0), voH = fin_o(FUN_VH), do0 = fin_o(FUN_D0), doH = fin_o(FUN_DH);
     const double k = s_k[m];
     double2 al = make_double2(0, 0), be = make_double2(0, 0);
     double Ai = 0.0;
-    const double2* vi = s_val[0][m];
-    const double2* vo = s_val[1][m];
     if (k > 0.0 && s_keep[m]) {
       const double e = g.eps, eb = g.eps_b, et = g.eps_t, tb = g.tau_b, tt = g.tau_t;
-      double2 mpb = make_double2(vi[0].x - tb * vo[0].x, vi[0].y - tb * vo[0].y);
-      double2 meb = make_double2(e * vi[2].x - eb * tb * vo[2].x, e * vi[2].y - eb * tb * vo[2].y);
-      double2 mpt = make_double2(vi[1].x - tt * vo[1].x, vi[1].y - tt * vo[1].y);
-      double2 met = make_double2(e * vi[3].x - et * tt * vo[3].x, e * vi[3].y - et * tt * vo[3].y);
+      // mismatches (eqs. mm1-mm4, no wall charges)
+      double2 mpb = make_double2(vi0.x - tb * vo0.x, vi0.y - tb * vo0.y);
+      double2 meb = make_double2(e * di0.x - eb * tb * do0.x, e * di0.y - eb * tb * do0.y);
+      double2 mpt = make_double2(viH.x - tt * voH.x, viH.y - tt * voH.y);
+      double2 met = make_double2(e * diH.x - et * tt * doH.x, e * diH.y - et * tt * doH.y);
       double2 Rb = make_double2((eb * k * mpb.x - meb.x) / k, (eb * k * mpb.y - meb.y) / k);
       double2 Rt = make_double2(-(met.x + et * k * mpt.x) / k, -(met.y + et * k * mpt.y) / k);
       double E = exp(-k * g.H);
@@ -335,30 +274,95 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     }
     if (m0 + m == 0) {
       const double e = g.eps, tb = g.tau_b, tt = g.tau_t;
-      double Ab = -tb * s_end[m][0], At = -tt * s_end[m][1];
-      double A1 = (g.eps_b * (tb * vo[2].x + Ab) - e * vi[2].x) / e;
-      double A2 = (g.eps_t * (tt * vo[3].x + At) - e * vi[3].x) / e;
+      const double2 ea = fin_o(FUN_EA), ebd = fin_o(FUN_EB);
+      double Ab = -tb * ea.x, At = -tt * ebd.x;
+      double A1 = (g.eps_b * (tb * do0.x + Ab) - e * di0.x) / e;
+      double A2 = (g.eps_t * (tt * doH.x + At) - e * diH.x) / e;
       Ai = 0.5 * (A1 + A2);
       scal[3] = Ai;
     }
     s_ab[m][0] = al;
     s_ab[m][1] = be;
     s_Ai[m] = Ai;
-    // derivative series of psi_i*: d_{n-1} = d_{n+1} + 2 n y_n, d_0 halved, times 1/R
-    double2 dn1 = make_double2(0, 0), dn2 = make_double2(0, 0);  // d_{n}, d_{n+1}
-    A[(N - 1) * MB + m] = make_double2(0.0, 0.0);
-    for (int n = N - 1; n >= 1; --n) {
-      double2 y = B[n * MB + m];
-      double2 d = make_double2(dn2.x + 2.0 * n * y.x, dn2.y + 2.0 * n * y.y);  // d_{n-1}
-      dn2 = dn1;
-      dn1 = d;
-      double f = (n - 1 == 0) ? 0.5 / Rz : 1.0 / Rz;
-      A[(n - 1) * MB + m] = make_double2(f * d.x, f * d.y);
+  }
+  __syncthreads();
+
+  // 5. final series of psi_i* into A: y_n = Y[n].(P) + y_0 Y[n].(h1) + y'_0 Y[n].(h2)
+  for (int t = tid; t < N * MB; t += kThreads) {
+    const int n = t >> logMB, m = t & (MB - 1);
+    double2 yP = make_double2(0.0, 0.0);
+    double yh = 0.0;
+    if (n >= 1) {
+      const double a = ca[n], b = cb[n], c = cc[n];
+      double2 x0 = B[n * MB + m];
+      double h0 = hval(m, n);
+      yP.x = -b * x0.x;
+      yP.y = -b * x0.y;
+      yh = -b * h0;
+      if (n >= 2) {
+        double2 xm = B[(n - 2) * MB + m];
+        yP.x = fma(a, xm.x, yP.x);
+        yP.y = fma(a, xm.y, yP.y);
+        yh = fma(a, hval(m, n - 2), yh);
+      }
+      if (n + 2 < N) {
+        double2 xp = B[(n + 2) * MB + m];
+        yP.x = fma(c, xp.x, yP.x);
+        yP.y = fma(c, xp.y, yP.y);
+        yh = fma(c, hval(m, n + 2), yh);
+      }
+    }
+    if (n <= 1) yh += 1.0;  // y_0 = 1 in h1; y_1 = y'_0 + ... with y'_0 = 1 in h2
+    const double2 cf = s_c[m][n & 1];
+    A[n * MB + m] = make_double2(fma(cf.x, yh, yP.x), fma(cf.y, yh, yP.y));
+  }
+  __syncthreads();
+
+  // 6. derivative series into B: d_j = (2/R) sum_{m > j, m = j+1 mod 2} m y_m
+  //    (d_{N-1} = 0, d_0 halved), a suffix sum per mode and parity: one wave
+  //    per chain, lanes own consecutive entries, scanned from the top.
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    const double ir = 1.0 / Rz;
+    for (int ch = wv; ch < 2 * MB; ch += kThreads / 64) {
+      const int m = ch & (MB - 1), q = ch >> logMB;  // q: parity of the output index j
+      // outputs j = q, q+2, ... <= N-1; entry t (from the top) is j = jt - 2t
+      const int jt = (N - 1) - (((N - 1) - q) & 1);
+      const int Lc = jt / 2 + 1;
+      const int E = (Lc + 63) >> 6;
+      const int t0 = lane * E, t1 = min(Lc, t0 + E);
+      double sx = 0.0, sy = 0.0;
+      for (int t = t0; t < t1; ++t) {
+        const int j = jt - 2 * t;
+        if (j + 1 < N) {
+          const double2 y = A[(j + 1) * MB + m];
+          const double f = 2.0 * (j + 1);
+          sx = fma(f, y.x, sx);
+          sy = fma(f, y.y, sy);
+        }
+      }
+      for (int o = 1; o < 64; o <<= 1) {
+        const double cx = __shfl_up(sx, o, 64), cy = __shfl_up(sy, o, 64);
+        if (lane >= o) { sx += cx; sy += cy; }
+      }
+      double ax = __shfl_up(sx, 1, 64), ay = __shfl_up(sy, 1, 64);
+      if (lane == 0) { ax = 0.0; ay = 0.0; }
+      for (int t = t0; t < t1; ++t) {
+        const int j = jt - 2 * t;
+        if (j + 1 < N) {
+          const double2 y = A[(j + 1) * MB + m];
+          const double f = 2.0 * (j + 1);
+          ax = fma(f, y.x, ax);
+          ay = fma(f, y.y, ay);
+        }
+        const double sc = (j == 0) ? 0.5 * ir : ir;
+        B[j * MB + m] = make_double2(sc * ax, sc * ay);
+      }
     }
   }
   __syncthreads();
 
-  // 6. inverse DCT-I of B (series) and A (derivative series): v_j = 1/2 FFT(e)[j]
+  // 7. inverse DCT-I of A (series) and B (derivative series): v_j = 1/2 FFT(e)[j]
   //    with e the even extension of (2 c_0, c_1, ..., c_{N-2}, 2 c_{N-1})
   {
     constexpr int kPer = kElems / kThreads;  // M * MB == kElems
@@ -366,7 +370,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       int t = tid + q * kThreads;
-      int j = t / MB, m = t % MB;
+      int j = t >> logMB, m = t & (MB - 1);
       int n = j < N ? j : M - j;
       double f = (n == 0 || n == N - 1) ? 2.0 : 1.0;
       double2 a = A[n * MB + m], b = B[n * MB + m];
@@ -377,21 +381,21 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       int t = tid + q * kThreads;
-      int j = t / MB, m = t % MB;
+      int j = t >> logMB, m = t & (MB - 1);
       int pos = bitrev(j, logM) * MB + m;
       A[pos] = ra[q];
       B[pos] = rb[q];
     }
     __syncthreads();
   }
-  fft_lds<double2, true>(A, logM, MB, 1, MB, twz, false, tid, kThreads);
-  fft_lds<double2, true>(B, logM, MB, 1, MB, twz, false, tid, kThreads);
+  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(A, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(B, logM, logMB, 1, MB, tw, false, tid);
 
-  // 7. add the correction at the window nodes and the k = 0 linear mode; write out
+  // 8. add the correction at the window nodes and the k = 0 linear mode; write out
   for (int t = tid; t < N * MB; t += kThreads) {
-    int j = t / MB, m = t % MB, mi = m0 + m;
+    int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
     if (mi >= nmodes) continue;
-    double2 v = B[j * MB + m], d = A[j * MB + m];
+    double2 v = A[j * MB + m], d = B[j * MB + m];
     double ps_x = 0.5 * v.x, ps_y = 0.5 * v.y, pz_x = 0.5 * d.x, pz_y = 0.5 * d.y;
     double z = zn[j];
     double k = s_k[m];
@@ -426,10 +430,18 @@ hipError_t launch_column(dpse_plan* p) {
   const int MB = kElems / M;
   const int nmodes = g.Ny * g.nkx;
   const int nb = (nmodes + MB - 1) / MB;
-  hipLaunchKernelGGL(k_column<R>, dim3(nb), dim3(kThreads), 0, p->stream, g, (const C*)p->w.fx_i,
+  const size_t shmem = (size_t)(2 * kElems + M / 2) * sizeof(double2) +
+                       (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_column<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       96 * 1024);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_column<R>, dim3(nb), dim3(kThreads), shmem, p->stream, g, (const C*)p->w.fx_i,
                      (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
-                     (const double*)p->t.T0, (const double*)p->t.TH, (const double*)p->t.dT0,
-                     (const double*)p->t.dTH, (const double2*)p->t.twz, p->w.scal);
+                     (const double*)p->t.ctab, (const double2*)p->t.twz, p->w.scal);
   return hipGetLastError();
 }
 

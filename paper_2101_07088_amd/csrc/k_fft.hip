@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const R* __restr
     if (rl & 1) d->y = v; else d->x = v;
   }
   __syncthreads();
-  fft_lds<C, false>(buf, logN, nseq, Nx, 1, tw, false, threadIdx.x, kThreads);
+  fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(nseq), Nx, 1, tw, false, threadIdx.x);
   const R scale = (R)(1.0 / ((double)g.Nx * (double)g.Ny));
   for (int i = threadIdx.x; i < nseq * nkx; i += kThreads) {
     int s = i / nkx, k = i % nkx;
@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* d
     buf[bitrev(ky, logN) * KB + kl] = v;
   }
   __syncthreads();
-  fft_lds<C, true>(buf, logN, KB, 1, KB, tw, false, threadIdx.x, kThreads);
+  fft_lds_r22<C, true, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(KB), 1, KB, tw, false, threadIdx.x);
   for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
     int ky = i / KB, kl = i % KB;
     if (kb + kl < nkx) base[(size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
@@ -136,9 +136,9 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
   }
   __syncthreads();
   // the three fields are 3 KB sequences laid out with the same element stride
-  fft_lds<C, true>(buf, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
-  fft_lds<C, true>(buf + E3, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
-  fft_lds<C, true>(buf + 2 * E3, logN, KB, 1, KB, tw, true, threadIdx.x, kThreads);
+  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
+  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf + E3, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
+  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf + 2 * E3, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
   for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
     int ky = i / KB, kl = i % KB;
     if (kb + kl < nkx) {
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
     buf[(2 * rl + 1) * Nx + pos] = z2;
   }
   __syncthreads();
-  fft_lds<C, false>(buf, logN, 2 * nrow_blk, Nx, 1, tw, true, threadIdx.x, kThreads);
+  fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(2 * nrow_blk), Nx, 1, tw, true, threadIdx.x);
   using V = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
   V* out = reinterpret_cast<V*>(u4);
   for (int i = threadIdx.x; i < nr * Nx; i += kThreads) {

@@ -55,9 +55,9 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
       !pos_finite(p->eps_bottom) || !pos_finite(p->eps_top) || !pos_finite(p->xi))
     return DPSE_EINVAL;
   if (!std::isfinite(p->g_w) || p->g_w < 0.0) return DPSE_EINVAL;
-  if (!is_pow2(p->Nx) || !is_pow2(p->Ny) || p->Nx < 8 || p->Ny < 8 || p->Nx > 1024 || p->Ny > 1024)
+  if (!is_pow2(p->Nx) || !is_pow2(p->Ny) || p->Nx < 32 || p->Ny < 32 || p->Nx > 1024 || p->Ny > 1024)
     return DPSE_EINVAL;
-  if (p->Nz < 5 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
+  if (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
   if (p->precision != DPSE_FP64 && p->precision != DPSE_MIXED) return DPSE_EINVAL;
   if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT)) return DPSE_EINVAL;
   double h = p->Lx / p->Nx, hy = p->Ly / p->Ny;
@@ -65,7 +65,7 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   double g_t = std::sqrt(1.0 / (4.0 * p->xi * p->xi) + p->g_w * p->g_w);
   int ng = p->support;
   if (ng == 0) ng = 2 * (int)std::ceil(4.3 * g_t / h);
-  if (ng < 2 || (ng & 1) || ng > p->Nx || ng > p->Ny) return DPSE_EINVAL;
+  if (ng < 2 || (ng & 1) || ng > dpse::kMaxSupport) return DPSE_EINVAL;
   double H_E = ng * h / 2.0;
   double rc = p->r_cut;
   if (rc == 0.0) {
@@ -253,6 +253,7 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
   A(&t.z, g.Nz); A(&t.wq, g.Nz); A(&t.T0, g.Nz); A(&t.TH, g.Nz); A(&t.dT0, g.Nz); A(&t.dTH, g.Nz);
   A(&t.twx, g.Nx / 2); A(&t.twy, g.Ny / 2); A(&t.twz, g.Nz - 1);
   A(&t.twx_f, g.Nx / 2); A(&t.twy_f, g.Ny / 2);
+  A(&t.ctab, dpse::kCtabRows * g.Nz + dpse::kNumFun * (g.Nz + 2));
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -284,6 +285,46 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
     dT0[n] /= g.zR;
     dTH[n] /= g.zR;
   }
+  // Per-mode solver tables. With u = (y''_0..y''_{N-1}, y_0, y'_0), the
+  // integral relations of App. A give y'_n = P[n] . u (eq. ds) and
+  // y_n = Y[n] . u (eq. cs), with y''_n = 0 for n > N-1 and y'_N = 0.
+  const int NU = N + 2;
+  std::vector<long double> Pm((size_t)N * NU, 0.0L), Ym((size_t)N * NU, 0.0L);
+  auto Pr = [&](int n) { return &Pm[(size_t)n * NU]; };
+  auto Yr = [&](int n) { return &Ym[(size_t)n * NU]; };
+  Pr(0)[N + 1] = 1.0L;
+  Pr(1)[0] = 1.0L;
+  Pr(1)[2] = -0.5L;
+  for (int n = 2; n < N; ++n) {
+    Pr(n)[n - 1] = 1.0L / (2.0L * n);
+    if (n + 1 < N) Pr(n)[n + 1] = -1.0L / (2.0L * n);
+  }
+  Yr(0)[N] = 1.0L;
+  for (int j = 0; j < NU; ++j) Yr(1)[j] = Pr(0)[j] - 0.5L * Pr(2)[j];
+  for (int n = 2; n < N; ++n)
+    for (int j = 0; j < NU; ++j)
+      Yr(n)[j] = (Pr(n - 1)[j] - (n + 1 < N ? Pr(n + 1)[j] : 0.0L)) / (2.0L * n);
+  std::vector<double> ctab((size_t)dpse::kCtabRows * N + (size_t)dpse::kNumFun * NU, 0.0);
+  for (int n = 0; n < N; ++n) {
+    // mode equation n: y''_n - kappa^2 y_n = g_n, y_n = a y''_{n-2} - b y''_n + c y''_{n+2} (+ free constants)
+    ctab[n] = n >= 2 ? (double)Yr(n)[n - 2] : 0.0;
+    ctab[N + n] = n >= 1 ? (double)(-Yr(n)[n]) : 0.0;
+    ctab[2 * N + n] = (n >= 1 && n + 2 < N) ? (double)Yr(n)[n + 2] : 0.0;
+    // g_n = -R^2/eps * fhat_n, fhat_n = DCT-I_n / ((N-1) cbar_n), cbar = 2 at both ends
+    ctab[3 * N + n] = -(g.zR * g.zR) / (g.eps * (N - 1)) * ((n == 0 || n == N - 1) ? 0.5 : 1.0);
+  }
+  {
+    double* W = ctab.data() + (size_t)dpse::kCtabRows * N;
+    for (int n = 0; n < N; ++n) {
+      long double sg = (n & 1) ? -1.0L : 1.0L;
+      long double n2 = (long double)n * n / g.zR;
+      const long double fy[dpse::kNumFun] = {0.0L, 1.0L, 0.0L, sg, T0[n], TH[n], dT0[n], dTH[n], -sg * n2, n2};
+      const long double fp[dpse::kNumFun] = {1.0L, 0.0L, sg, 0.0L, 0, 0, 0, 0, 0, 0};
+      for (int f = 0; f < dpse::kNumFun; ++f)
+        for (int j = 0; j < NU; ++j)
+          W[(size_t)f * NU + j] += (double)(fy[f] * Yr(n)[j] + fp[f] * Pr(n)[j]);
+    }
+  }
   auto twid = [](int L) {
     std::vector<double2> tw(std::max(L / 2, 1));
     for (int k = 0; k < L / 2; ++k) {
@@ -305,6 +346,7 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
   H2D(t.twx, tox.data(), tox.size() * sizeof(double2));
   H2D(t.twy, toy.data(), toy.size() * sizeof(double2));
   H2D(t.twz, toz.data(), toz.size() * sizeof(double2));
+  H2D(t.ctab, ctab.data(), ctab.size() * sizeof(double));
   H2D(t.twx_f, txf.data(), txf.size() * sizeof(float2));
   H2D(t.twy_f, tyf.data(), tyf.size() * sizeof(float2));
   int zero4[4] = {0, 0, 0, 0};
