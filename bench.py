@@ -101,6 +101,142 @@ def cpu_baseline(p, pos, q, near_stride=8):
                       f"estimated full solve {t:.1f} s"}
 
 
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / np.sum(b ** 2)))
+
+
+def bench_batch(dp, torch, steps, n_sys=64, n_branches=8):
+    """Uneven batch: 64 independent slabs (N log-uniform in [1024, 65536],
+    L in {32,64,128}, H in {16,32,64}, eps_b, eps_t in {0.05,1,20}, xi=1.5,
+    h=0.25, r_cut=2), mixed precision, one graph launch per step; against
+    the same 64 solves one after another on one stream without a graph."""
+    import workloads as W
+    from paper_2101_07088_amd.batch import BatchRunner
+    systems = W.batch_systems(n_sys)
+    tens = [(p, torch.tensor(pos, dtype=torch.float64, device="cuda"),
+             torch.tensor(q, dtype=torch.float64, device="cuda")) for p, pos, q in systems]
+    n_total = sum(len(q) for _, _, q in systems)
+    out = {"systems": n_sys, "charges": n_total, "branches": n_branches}
+
+    def timed(runner, k):
+        runner.run()
+        torch.cuda.synchronize()
+        st = runner.statuses()
+        assert all(x == 0 for x in st), st
+        t0 = time.perf_counter()
+        for _ in range(k):
+            runner.run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    seq = BatchRunner(tens, precision=dp.DPSE_MIXED, n_branches=1, use_graph=False)
+    t_seq = timed(seq, max(2, steps // 4))
+    seq.close()
+    del seq
+    br = BatchRunner(tens, precision=dp.DPSE_MIXED, n_branches=n_branches, use_graph=True)
+    t_b = timed(br, steps)
+    out.update({"evals_per_s": n_total / t_b, "ms_per_batch": 1e3 * t_b,
+                "sequential_evals_per_s": n_total / t_seq, "sequential_ms": 1e3 * t_seq,
+                "speedup_vs_sequential": t_seq / t_b, "arena_bytes": br.workspace_bytes})
+    # accuracy of the mixed batch against FP64 single solves on a sample of systems
+    errs = []
+    for k in range(0, n_sys, 16):
+        p, tp, tq = tens[k]
+        pl = dp.Plan(p, max_n=int(tq.shape[0]), precision=dp.DPSE_FP64)
+        U, phi, F = pl.solve(tp, tq)
+        pl.sync()
+        errs.append(rel_rms(br.force[k].cpu().numpy(), F.cpu().numpy()))
+        pl.close()
+    out["mixed_vs_fp64_rel_rms_force_max"] = max(errs)
+    out["accuracy_sample"] = f"systems {list(range(0, n_sys, 16))}"
+    br.close()
+    return out
+
+
+def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_slots=8, max_queue=256):
+    """Serving stream: Poisson arrivals of solves from n_traj Brownian-like
+    trajectories (N log-uniform in [512, 262144], box and permittivities
+    fixed per trajectory, each request moves every charge by N(0, 0.05^2)
+    per axis on the device). Latency is arrival to result on the host; the
+    first `warm` seconds are not counted."""
+    import workloads as W
+    from paper_2101_07088_amd.serve import Overloaded, Server
+    trajs = W.serving_trajectories(n_traj)
+    srv = Server(budget_bytes=int(budget_gb * 2 ** 30), n_slots=n_slots, precision=dp.DPSE_MIXED,
+                 max_queue=max_queue)
+    state = []
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2000)
+    for t, (p, pos, q) in enumerate(trajs):
+        srv.register(t, p, 1 << int(math.ceil(math.log2(len(q)))))
+        state.append([p, torch.tensor(pos, dtype=torch.float64, device="cuda"),
+                      torch.tensor(q, dtype=torch.float64, device="cuda")])
+    times, which = W.poisson_arrivals(rate, duration, n_traj)
+
+    def step_positions(st):
+        p, pos, _ = st
+        x = pos + 0.05 * torch.randn(pos.shape, dtype=torch.float64, device="cuda", generator=gen)
+        x[:, 0].remainder_(p.Lx)
+        x[:, 1].remainder_(p.Ly)
+        lo, hi = 0.5, p.H - 0.5
+        z = x[:, 2]
+        z = torch.where(z < lo, 2 * lo - z, z)
+        z = torch.where(z > hi, 2 * hi - z, z)
+        x[:, 2] = z.clamp(lo, hi)
+        st[1] = x
+        return x
+
+    done = []
+    shed = 0
+    sample = {}
+    i = 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while i < len(times) and times[i] <= now:
+            st = state[which[i]]
+            x = step_positions(st)
+            ev = torch.cuda.Event()
+            ev.record()
+            try:
+                r = srv.submit(int(which[i]), x, st[2], ready_event=ev, arrival=t0 + times[i])
+                r.callbacks.append(done.append)
+                if i % 997 == 0 and len(sample) < 4:
+                    sample[i] = (int(which[i]), x.clone(), r)
+            except Overloaded:
+                shed += times[i] >= warm
+            i += 1
+        srv.step()
+        if i >= len(times) and not srv.pending():
+            break
+    wall = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    counted = [r for r in done if r.arrival - t0 >= warm]
+    lat = np.array([r.latency for r in counted]) * 1e3
+    evals = sum(r.n for r in counted)
+    offered = int(np.sum(times >= warm))
+    span = max(r.finished for r in counted) - (t0 + warm) if counted else float("nan")
+    out = {"rate_offered_req_s": rate, "duration_s": duration, "warmup_s": warm, "trajectories": n_traj,
+           "requests_offered": offered, "requests_served": len(counted), "requests_shed": int(shed),
+           "served_req_s": len(counted) / span, "evals_per_s": evals / span,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "slots": n_slots, "budget_bytes": srv.budget, "peak_bytes": srv.stats["peak_bytes"],
+           "peak_active": srv.stats["peak_active"], "failed": srv.stats["failed"], "wall_s": wall}
+    errs = []
+    for k, (t, x, r) in sample.items():
+        if not r.done():
+            continue
+        p, _, q = state[t]
+        pl = dp.Plan(p, max_n=len(q), precision=dp.DPSE_FP64)
+        U, phi, F = pl.solve(x, q)
+        pl.sync()
+        errs.append(rel_rms(r.result[2].cpu().numpy(), F.cpu().numpy()))
+        pl.close()
+    out["mixed_vs_fp64_rel_rms_force_max"] = max(errs) if errs else None
+    srv.close()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +245,13 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["auto", "fp64", "mixed"], default="auto")
+    ap.add_argument("--batch", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 64-system uneven batch")
+    ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
+                    help="also run the serving stream")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-duration", type=float, default=10.0)
+    ap.add_argument("--serve-warmup", type=float, default=1.0)
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -166,6 +309,18 @@ def main(argv=None):
         line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / a.steps)
         line[f"{prec}_p50_ms"] = float(np.percentile(rr["lat_ms"], 50))
         line[f"{prec}_p99_ms"] = float(np.percentile(rr["lat_ms"], 99))
+    if a.batch:
+        line["batch"] = bench_batch(dp, torch, a.steps)
+        print(f"[bench] batch: {line['batch']}", file=sys.stderr, flush=True)
+    if a.serve:
+        line["serving"] = bench_serve(dp, torch, a.serve_rate, a.serve_duration, a.serve_warmup)
+        print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
+        cap = line["serving"]["served_req_s"]
+        if a.serve_rate > 0.8 * cap:
+            # the offered stream exceeds what one GPU serves: also report latency at 70% of that capacity
+            line["serving_at_70pct_capacity"] = bench_serve(dp, torch, 0.7 * cap, a.serve_duration / 2,
+                                                            a.serve_warmup)
+            print(f"[bench] serving at 70%: {line['serving_at_70pct_capacity']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, pos, q)
     print(json.dumps(line), flush=True)

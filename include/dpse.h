@@ -30,7 +30,10 @@
  *
  * Streams and ownership. All position, charge and output pointers are DEVICE
  * pointers owned by the caller (e.g. torch.Tensor.data_ptr() of float64 HIP
- * tensors). The plan owns its workspace. dpse_solve only enqueues work on
+ * tensors). A plan from dpse_plan_create owns its workspace; a plan from
+ * dpse_plan_create_unbound uses caller-owned device memory attached with
+ * dpse_plan_bind (so that many plans can share one arena, one plan at a time
+ * per stream). dpse_solve only enqueues work on
  * the plan's HIP stream and returns; the caller's buffers must stay valid
  * until that stream has passed the solve. A plan is not thread safe and must
  * not run two solves concurrently. Data-dependent errors (charge outside the
@@ -113,6 +116,28 @@ int dpse_derive(const dpse_params* params, dpse_info* info);
  * numbers). *out receives the plan. */
 int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out);
 
+/* Device bytes of the workspace of one solve of up to max_n charges with
+ * these parameters (host only; the same figure as dpse_info.workspace_bytes). */
+int dpse_workspace_size(const dpse_params* params, int64_t max_n, int64_t* bytes);
+
+/* Creates a plan like dpse_plan_create but allocates only its tables (a few
+ * KB to MB: nodes, weights, twiddles, per-mode solver coefficients) and no
+ * workspace. Before its first solve the caller attaches a workspace with
+ * dpse_plan_bind; entry points that need one return DPSE_EINVAL until then. */
+int dpse_plan_create_unbound(const dpse_params* params, int64_t max_n, dpse_plan** out);
+
+/* Attaches caller-owned device memory `workspace` (256-byte aligned, at
+ * least dpse_workspace_size bytes; the caller keeps ownership and frees it
+ * after the plan's last solve has finished) and the HIP stream `stream` to a
+ * plan from dpse_plan_create_unbound. May be called again to move the plan to
+ * other memory or another stream; the workspace holds no state between
+ * solves except the device status of dpse_sync, which binding clears (with a
+ * kernel on `stream`, ordered after the work already queued there). Plans that
+ * share a workspace must run on one stream, or the caller orders them.
+ * DPSE_EINVAL for a plan that owns its workspace, a null or misaligned
+ * pointer, or too few bytes. */
+int dpse_plan_bind(dpse_plan* plan, void* workspace, int64_t bytes, void* stream);
+
 /* Copies the derived quantities of a plan into *info. */
 int dpse_plan_info(const dpse_plan* plan, dpse_info* info);
 
@@ -128,6 +153,16 @@ int dpse_plan_info(const dpse_plan* plan, dpse_info* info);
 int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
                double* energy, double* phi, double* force);
 
+/* The solve of dpse_solve as one HIP graph launch. The first call (and any
+ * call whose n, pointers, workspace or stream differ from the previous one)
+ * captures the solve's kernels into a graph (no allocation or memset node:
+ * buffers are cleared by kernels) and instantiates it; later calls with the
+ * same arguments only launch it, which removes the per-kernel launch cost for
+ * small systems. Stage timing is not recorded for graph solves. Same
+ * arguments, results and errors as dpse_solve. */
+int dpse_solve_graph(dpse_plan* plan, int64_t n, const double* pos, const double* q,
+                     double* energy, double* phi, double* force);
+
 /* Enqueues n_sys independent solves (one per plan, each with its own sizes and
  * parameters) as one batch. Array arguments have n_sys entries with the
  * meaning of dpse_solve's. Plans may share a stream; the batch is ordered on
@@ -135,6 +170,24 @@ int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
 int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
                      const double* const* pos, const double* const* q,
                      double* const* energy, double* const* phi, double* const* force);
+
+/* A batch of solves captured into one HIP graph: one launch runs every
+ * system of the batch (the work of dpse_solve_batch). System i runs on branch
+ * branch[i] (0 <= branch[i] < n_branches <= 64; NULL = i mod n_branches);
+ * systems of one branch run in the given order, different branches may run
+ * concurrently, so plans bound to one workspace must share a branch. The
+ * graph records the pointers and sizes given here: relaunching it solves
+ * again with whatever those buffers then hold. The plans must stay alive
+ * and bound to the same workspaces while the graph exists. Stage timing is
+ * not recorded. dpse_graph_launch enqueues the whole batch on `stream`;
+ * device-side statuses go to each plan's workspace (dpse_sync). */
+typedef struct dpse_graph dpse_graph;
+int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n,
+                            const double* const* pos, const double* const* q,
+                            double* const* energy, double* const* phi, double* const* force,
+                            const int32_t* branch, int n_branches, dpse_graph** out);
+int dpse_graph_launch(dpse_graph* graph, void* stream);
+int dpse_graph_destroy(dpse_graph* graph);
 
 /* Waits for the plan's stream and returns the device-side status of the
  * solves enqueued since the previous dpse_sync (DPSE_OK, DPSE_ENONNEUTRAL,

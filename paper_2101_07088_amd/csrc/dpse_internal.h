@@ -130,6 +130,11 @@ struct dpse_plan {
   int ncells = 0;
   int npartials = 0;
   std::vector<void*> allocs;
+  bool bound = false;                  // a workspace is attached
+  bool owns_workspace = false;
+  hipGraphExec_t graph_exec = nullptr; // captured solve (dpse_solve_graph)
+  const void* graph_sig[7] = {};
+  hipStream_t graph_stream = nullptr;
   // per-stage timing: one row of DPSE_NUM_STAGES + 1 events per recorded solve
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -150,6 +155,9 @@ template <typename R> hipError_t launch_near(dpse_plan* p, int64_t n);
 template <typename R> hipError_t launch_gauge(dpse_plan* p, int64_t n);
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
                            double* phi, double* force);
+
+// Sets kernel attributes once (before any stream capture).
+hipError_t prepare_kernels();
 
 // Small helpers.
 hipError_t fill_int(int* ptr, int value, int64_t count, hipStream_t s);

@@ -432,17 +432,21 @@ hipError_t launch_column(dpse_plan* p) {
   const int nb = (nmodes + MB - 1) / MB;
   const size_t shmem = (size_t)(2 * kElems + M / 2) * sizeof(double2) +
                        (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_column<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       96 * 1024);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
   hipLaunchKernelGGL(k_column<R>, dim3(nb), dim3(kThreads), shmem, p->stream, g, (const C*)p->w.fx_i,
                      (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
                      (const double*)p->t.ctab, (const double2*)p->t.twz, p->w.scal);
   return hipGetLastError();
+}
+
+// Raises the dynamic LDS limit of the column kernels on the current device;
+// called at plan creation so that no attribute call happens inside a solve
+// (which may be captured into a graph).
+hipError_t prepare_kernels() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_column<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     96 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_column<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+  return e;
 }
 
 template hipError_t launch_column<double>(dpse_plan*);

@@ -136,19 +136,67 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   return DPSE_OK;
 }
 
-template <typename T>
-hipError_t dalloc(dpse_plan* p, T** ptr, size_t count, int64_t* bytes) {
-  size_t b = std::max<size_t>(count, 1) * sizeof(T);
-  b = (b + 255) & ~size_t(255);
-  hipError_t e = hipMalloc((void**)ptr, b);
-  if (e == hipSuccess) {
-    p->allocs.push_back((void*)*ptr);
-    *bytes += (int64_t)b;
+// Carves 256-byte aligned sub-buffers out of one allocation: with base ==
+// nullptr it only accumulates the size.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  void take(T** ptr, size_t count) {
+    off = (off + 255) & ~size_t(255);
+    if (base) *ptr = reinterpret_cast<T*>(base + off);
+    off += std::max<size_t>(count, 1) * sizeof(T);
   }
-  return e;
+};
+
+void plan_sizes(dpse_plan* p) {
+  const Geom& g = p->g;
+  p->nkeys = g.nbx * g.nby * g.nzb;
+  p->ncells = g.ncx * g.ncy * g.ncz;
+  p->npartials = 1024;
+}
+
+// Workspace of one solve (all per-solve device buffers), for max_n charges.
+size_t carve_workspace(dpse_plan* p, char* base) {
+  const Geom& g = p->g;
+  const size_t rs = p->prm.precision == DPSE_MIXED ? 4 : 8;
+  const size_t G = (size_t)g.Nz * g.Ny * g.Nx;
+  const size_t C = (size_t)g.Nz * g.Ny * g.nkx;
+  const size_t max_n = (size_t)p->max_n;
+  Carver c{base};
+  dpse::Workspace& w = p->w;
+  size_t next = 3 * max_n;
+  c.take(&w.ext, next); c.take(&w.ext_meta, next); c.take(&w.srt, next); c.take(&w.srt_meta, next);
+  c.take(&w.bin_cnt, p->nkeys + 1); c.take(&w.bin_off, p->nkeys + 1); c.take(&w.bin_cur, p->nkeys + 1);
+  c.take(&w.n_img, 4);
+  c.take(&w.nsrt, max_n); c.take(&w.nsrt_idx, max_n);
+  c.take(&w.cell_cnt, p->ncells + 1); c.take(&w.cell_off, p->ncells + 1); c.take(&w.cell_cur, p->ncells + 1);
+  c.take((char**)&w.f_i, G * rs);
+  c.take((char**)&w.f_o, G * rs);
+  char** cgrids[] = {(char**)&w.fx_i, (char**)&w.fx_o, (char**)&w.psi, (char**)&w.psiz,
+                     (char**)&w.p0, (char**)&w.py, (char**)&w.pz};
+  for (char** gp : cgrids) c.take(gp, C * 2 * rs);
+  c.take((char**)&w.u4, 4 * G * rs);
+  c.take(&w.far4, max_n); c.take(&w.near4, max_n);
+  c.take(&w.scal, 16); c.take(&w.partials, 4 * (size_t)p->npartials); c.take(&w.status, 4);
+  return (c.off + 255) & ~size_t(255);
+}
+
+size_t carve_tables(dpse_plan* p, char* base) {
+  const Geom& g = p->g;
+  Carver c{base};
+  dpse::Tables& t = p->t;
+  c.take(&t.z, g.Nz); c.take(&t.wq, g.Nz); c.take(&t.T0, g.Nz); c.take(&t.TH, g.Nz);
+  c.take(&t.dT0, g.Nz); c.take(&t.dTH, g.Nz);
+  c.take(&t.twx, g.Nx / 2); c.take(&t.twy, g.Ny / 2); c.take(&t.twz, g.Nz - 1);
+  c.take(&t.twx_f, g.Nx / 2); c.take(&t.twy_f, g.Ny / 2);
+  c.take(&t.ctab, dpse::kCtabRows * g.Nz + dpse::kNumFun * (g.Nz + 2));
+  return c.off;
 }
 
 void free_all(dpse_plan* p) {
+  if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
+  p->graph_exec = nullptr;
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
 }
@@ -205,7 +253,8 @@ int dpse_derive(const dpse_params* params, dpse_info* info) {
   return s;
 }
 
-int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out) {
+static int plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out,
+                       bool unbound) {
   if (!out || max_n <= 0 || max_n > (int64_t(1) << 28)) return DPSE_EINVAL;
   dpse_plan* p = new (std::nothrow) dpse_plan();
   if (!p) return DPSE_ENOMEM;
@@ -222,44 +271,34 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
     return DPSE_EHIP;
   }
   const Geom& g = p->g;
-  const bool mixed = params->precision == DPSE_MIXED;
-  const size_t rs = mixed ? 4 : 8;
-  const size_t G = (size_t)g.Nz * g.Ny * g.Nx;
-  const size_t C = (size_t)g.Nz * g.Ny * g.nkx;
-  p->nkeys = g.nbx * g.nby * g.nzb;
-  p->ncells = g.ncx * g.ncy * g.ncz;
-  p->npartials = 1024;
-  int64_t bytes = 0;
+  plan_sizes(p);
   hipError_t e = hipSuccess;
-  auto A = [&](auto** ptr, size_t count) {
-    if (e == hipSuccess) e = dalloc(p, ptr, count, &bytes);
-  };
-  dpse::Workspace& w = p->w;
-  size_t next = 3 * (size_t)max_n;
-  A(&w.ext, next); A(&w.ext_meta, next); A(&w.srt, next); A(&w.srt_meta, next);
-  A(&w.bin_cnt, p->nkeys + 1); A(&w.bin_off, p->nkeys + 1); A(&w.bin_cur, p->nkeys + 1);
-  A(&w.n_img, 4);
-  A(&w.nsrt, max_n); A(&w.nsrt_idx, max_n);
-  A(&w.cell_cnt, p->ncells + 1); A(&w.cell_off, p->ncells + 1); A(&w.cell_cur, p->ncells + 1);
-  char** grids[] = {(char**)&w.f_i, (char**)&w.f_o};
-  for (char** gp : grids) A(gp, G * rs);
-  char** cgrids[] = {(char**)&w.fx_i, (char**)&w.fx_o, (char**)&w.psi, (char**)&w.psiz,
-                     (char**)&w.p0, (char**)&w.py, (char**)&w.pz};
-  for (char** gp : cgrids) A(gp, C * 2 * rs);
-  A((char**)&w.u4, 4 * G * rs);
-  A(&w.far4, max_n); A(&w.near4, max_n);
-  A(&w.scal, 16); A(&w.partials, 4 * p->npartials); A(&w.status, 4);
-  dpse::Tables& t = p->t;
-  A(&t.z, g.Nz); A(&t.wq, g.Nz); A(&t.T0, g.Nz); A(&t.TH, g.Nz); A(&t.dT0, g.Nz); A(&t.dTH, g.Nz);
-  A(&t.twx, g.Nx / 2); A(&t.twy, g.Ny / 2); A(&t.twz, g.Nz - 1);
-  A(&t.twx_f, g.Nx / 2); A(&t.twy_f, g.Ny / 2);
-  A(&t.ctab, dpse::kCtabRows * g.Nz + dpse::kNumFun * (g.Nz + 2));
+  void* tbl = nullptr;
+  size_t tbytes = carve_tables(p, nullptr);
+  e = hipMalloc(&tbl, tbytes);
   if (e != hipSuccess) {
-    free_all(p);
     delete p;
     return DPSE_ENOMEM;
   }
-  p->info.workspace_bytes = bytes;
+  p->allocs.push_back(tbl);
+  carve_tables(p, (char*)tbl);
+  dpse::Workspace& w = p->w;
+  dpse::Tables& t = p->t;
+  size_t wbytes = carve_workspace(p, nullptr);
+  if (!unbound) {
+    void* ws = nullptr;
+    e = hipMalloc(&ws, wbytes);
+    if (e != hipSuccess) {
+      free_all(p);
+      delete p;
+      return DPSE_ENOMEM;
+    }
+    p->allocs.push_back(ws);
+    carve_workspace(p, (char*)ws);
+    p->bound = true;
+    p->owns_workspace = true;
+  }
+  p->info.workspace_bytes = (int64_t)wbytes;
   p->info.max_n = max_n;
 
   // plan tables
@@ -350,7 +389,8 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
   H2D(t.twx_f, txf.data(), txf.size() * sizeof(float2));
   H2D(t.twy_f, tyf.data(), tyf.size() * sizeof(float2));
   int zero4[4] = {0, 0, 0, 0};
-  H2D(w.status, zero4, sizeof(zero4));
+  if (p->bound) H2D(w.status, zero4, sizeof(zero4));
+  if (e == hipSuccess) e = dpse::prepare_kernels();
   if (e != hipSuccess) {
     free_all(p);
     delete p;
@@ -358,6 +398,42 @@ int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dps
   }
   *out = p;
   return DPSE_OK;
+}
+
+int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out) {
+  return plan_create(params, max_n, stream, out, false);
+}
+
+int dpse_plan_create_unbound(const dpse_params* params, int64_t max_n, dpse_plan** out) {
+  return plan_create(params, max_n, nullptr, out, true);
+}
+
+int dpse_workspace_size(const dpse_params* params, int64_t max_n, int64_t* bytes) {
+  if (!params || !bytes || max_n <= 0 || max_n > (int64_t(1) << 28)) return DPSE_EINVAL;
+  dpse_plan tmp;
+  int s = derive_all(params, &tmp.info, &tmp.g);
+  if (s != DPSE_OK) return s;
+  tmp.prm = *params;
+  tmp.max_n = max_n;
+  plan_sizes(&tmp);
+  *bytes = (int64_t)carve_workspace(&tmp, nullptr);
+  return DPSE_OK;
+}
+
+int dpse_plan_bind(dpse_plan* p, void* workspace, int64_t bytes, void* stream) {
+  if (!p || !workspace || bytes < p->info.workspace_bytes) return DPSE_EINVAL;
+  if (((uintptr_t)workspace & 255) != 0) return DPSE_EINVAL;
+  if (p->owns_workspace) return DPSE_EINVAL;  // created by dpse_plan_create
+  if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  carve_workspace(p, (char*)workspace);
+  p->stream = (hipStream_t)stream;
+  p->bound = true;
+  if (p->graph_exec) {
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+  }
+  hipError_t e = dpse::fill_int(p->w.status, 0, 4, p->stream);
+  return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
 }
 
 int dpse_plan_info(const dpse_plan* plan, dpse_info* info) {
@@ -371,7 +447,7 @@ static const char* kStageNames[DPSE_NUM_STAGES] = {
 
 static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* q,
                       double* energy, double* phi, double* force) {
-  if (!p || !pos || !q || n <= 0) return DPSE_EINVAL;
+  if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
   if (n > p->max_n) return DPSE_ETOOMANY;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
@@ -425,6 +501,141 @@ int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q, d
   return solve_impl(plan, n, pos, q, energy, phi, force);
 }
 
+int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,
+                     double* phi, double* force) {
+  if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
+  if (n > p->max_n) return DPSE_ETOOMANY;
+  const void* sig[7] = {(const void*)(intptr_t)n, pos, q, energy, phi, force, (const void*)p->w.ext};
+  bool same = p->graph_exec != nullptr && p->graph_stream == p->stream;
+  for (int i = 0; i < 7 && same; ++i) same = p->graph_sig[i] == sig[i];
+  if (!same) {
+    if (p->graph_exec) {
+      (void)hipGraphExecDestroy(p->graph_exec);
+      p->graph_exec = nullptr;
+    }
+    hipStream_t cs = p->stream;
+    bool own_stream = false;
+    if (cs == nullptr) {  // the null stream cannot be captured: capture on a private stream
+      if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return DPSE_EHIP;
+      own_stream = true;
+    }
+    hipStream_t keep = p->stream;
+    bool timing = p->timing;
+    p->stream = cs;
+    p->timing = false;
+    hipGraph_t graph = nullptr;
+    int st = DPSE_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = DPSE_EHIP;
+    if (st == DPSE_OK) st = solve_impl(p, n, pos, q, energy, phi, force);
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    p->stream = keep;
+    p->timing = timing;
+    if (own_stream) (void)hipStreamDestroy(cs);
+    if (st != DPSE_OK || ec != hipSuccess || graph == nullptr) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st != DPSE_OK ? st : DPSE_EHIP;
+    }
+    hipError_t ei = hipGraphInstantiate(&p->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      p->graph_exec = nullptr;
+      return DPSE_EHIP;
+    }
+    for (int i = 0; i < 7; ++i) p->graph_sig[i] = sig[i];
+    p->graph_stream = p->stream;
+  }
+  p->last_n = n;
+  return hipGraphLaunch(p->graph_exec, p->stream) == hipSuccess ? DPSE_OK : DPSE_EHIP;
+}
+
+struct dpse_graph {
+  hipGraphExec_t exec = nullptr;
+  int device = 0;
+};
+
+int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n,
+                            const double* const* pos, const double* const* q,
+                            double* const* energy, double* const* phi, double* const* force,
+                            const int32_t* branch, int n_branches, dpse_graph** out) {
+  if (!out || n_sys <= 0 || !plans || !n || !pos || !q || n_branches <= 0 || n_branches > 64)
+    return DPSE_EINVAL;
+  for (int i = 0; i < n_sys; ++i) {
+    if (!plans[i] || !plans[i]->bound || n[i] <= 0 || !pos[i] || !q[i]) return DPSE_EINVAL;
+    if (n[i] > plans[i]->max_n) return DPSE_ETOOMANY;
+    if (branch && (branch[i] < 0 || branch[i] >= n_branches)) return DPSE_EINVAL;
+  }
+  std::vector<hipStream_t> st(n_branches + 1, nullptr);
+  std::vector<hipEvent_t> ev(n_branches + 1, nullptr);
+  int status = DPSE_OK;
+  for (int b = 0; b <= n_branches && status == DPSE_OK; ++b) {
+    if (hipStreamCreateWithFlags(&st[b], hipStreamNonBlocking) != hipSuccess) status = DPSE_EHIP;
+    else if (hipEventCreateWithFlags(&ev[b], hipEventDisableTiming) != hipSuccess) status = DPSE_EHIP;
+  }
+  hipGraph_t graph = nullptr;
+  hipStream_t root = st[n_branches];
+  bool capturing = false;
+  if (status == DPSE_OK) {
+    if (hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal) != hipSuccess) status = DPSE_EHIP;
+    else capturing = true;
+  }
+  // fork: every branch stream joins the capture through an event of the root
+  if (status == DPSE_OK && hipEventRecord(ev[n_branches], root) != hipSuccess) status = DPSE_EHIP;
+  for (int b = 0; b < n_branches && status == DPSE_OK; ++b)
+    if (hipStreamWaitEvent(st[b], ev[n_branches], 0) != hipSuccess) status = DPSE_EHIP;
+  for (int i = 0; i < n_sys && status == DPSE_OK; ++i) {
+    dpse_plan* p = plans[i];
+    const int b = branch ? branch[i] : i % n_branches;
+    hipStream_t keep = p->stream;
+    bool timing = p->timing;
+    p->stream = st[b];
+    p->timing = false;
+    status = solve_impl(p, n[i], pos[i], q[i], energy ? energy[i] : nullptr, phi ? phi[i] : nullptr,
+                        force ? force[i] : nullptr);
+    p->stream = keep;
+    p->timing = timing;
+  }
+  // join
+  for (int b = 0; b < n_branches && status == DPSE_OK; ++b) {
+    if (hipEventRecord(ev[b], st[b]) != hipSuccess || hipStreamWaitEvent(root, ev[b], 0) != hipSuccess)
+      status = DPSE_EHIP;
+  }
+  if (capturing) {
+    hipError_t ec = hipStreamEndCapture(root, &graph);
+    if (status == DPSE_OK && ec != hipSuccess) status = DPSE_EHIP;
+  }
+  dpse_graph* gr = nullptr;
+  if (status == DPSE_OK && graph) {
+    gr = new (std::nothrow) dpse_graph();
+    if (!gr) status = DPSE_ENOMEM;
+    else if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) status = DPSE_EHIP;
+    if (gr) gr->device = plans[0]->device;
+  }
+  if (graph) (void)hipGraphDestroy(graph);
+  for (int b = 0; b <= n_branches; ++b) {
+    if (ev[b]) (void)hipEventDestroy(ev[b]);
+    if (st[b]) (void)hipStreamDestroy(st[b]);
+  }
+  if (status != DPSE_OK) {
+    if (gr && gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    delete gr;
+    return status;
+  }
+  *out = gr;
+  return DPSE_OK;
+}
+
+int dpse_graph_launch(dpse_graph* g, void* stream) {
+  if (!g || !g->exec) return DPSE_EINVAL;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? DPSE_OK : DPSE_EHIP;
+}
+
+int dpse_graph_destroy(dpse_graph* g) {
+  if (!g) return DPSE_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  delete g;
+  return DPSE_OK;
+}
+
 int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
                      const double* const* pos, const double* const* q, double* const* energy,
                      double* const* phi, double* const* force) {
@@ -456,7 +667,7 @@ int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
 }
 
 int dpse_sync(dpse_plan* p) {
-  if (!p) return DPSE_EINVAL;
+  if (!p || !p->bound) return DPSE_EINVAL;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;
   int st[4] = {0, 0, 0, 0};
   if (hipMemcpy(st, p->w.status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return DPSE_EHIP;
@@ -512,7 +723,7 @@ int dpse_plan_destroy(dpse_plan* p) {
 
 int dpse_debug_copy(dpse_plan* p, int which, void* dst, int64_t bytes, int32_t* elem_bytes,
                     int64_t* count) {
-  if (!p || !dst || bytes < 0) return DPSE_EINVAL;
+  if (!p || !dst || bytes < 0 || !p->bound) return DPSE_EINVAL;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;
   const dpse::Geom& g = p->g;
   const bool mixed = p->prm.precision == DPSE_MIXED;

@@ -81,6 +81,16 @@ def _lib():
         L.dpse_solve_batch.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                        ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                        ctypes.POINTER(vp), ctypes.POINTER(vp)]
+        L.dpse_workspace_size.argtypes = [ctypes.POINTER(_Params), i64, ctypes.POINTER(i64)]
+        L.dpse_plan_create_unbound.argtypes = [ctypes.POINTER(_Params), i64, ctypes.POINTER(vp)]
+        L.dpse_plan_bind.argtypes = [vp, vp, i64, vp]
+        L.dpse_solve_graph.argtypes = [vp, i64, pd, pd, pd, pd, pd]
+        L.dpse_batch_graph_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                              ctypes.c_int, ctypes.POINTER(vp)]
+        L.dpse_graph_launch.argtypes = [vp, vp]
+        L.dpse_graph_destroy.argtypes = [vp]
         L.dpse_sync.argtypes = [vp]
         L.dpse_plan_destroy.argtypes = [vp]
         L.dpse_debug_copy.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -91,7 +101,8 @@ def _lib():
         L.dpse_stage_name.argtypes = [ctypes.c_int]
         for name in ("dpse_derive", "dpse_plan_create", "dpse_plan_info", "dpse_solve", "dpse_solve_batch",
                      "dpse_sync", "dpse_plan_destroy", "dpse_debug_copy", "dpse_set_timing",
-                     "dpse_stage_times"):
+                     "dpse_stage_times", "dpse_workspace_size", "dpse_plan_create_unbound", "dpse_plan_bind",
+                     "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -126,10 +137,22 @@ def derive(params, precision: int = DPSE_FP64) -> dict:
     return _info_dict(info)
 
 
-class Plan:
-    """A plan for one slab system on the current HIP device and stream."""
+def workspace_size(params, max_n: int, precision: int = DPSE_FP64) -> int:
+    """Device bytes of the workspace of a solve of up to max_n charges (host only)."""
+    prm = _params(params, precision)
+    b = ctypes.c_int64()
+    _check(_lib().dpse_workspace_size(ctypes.byref(prm), int(max_n), ctypes.byref(b)), "dpse_workspace_size")
+    return b.value
 
-    def __init__(self, params, max_n: int, precision: int = DPSE_FP64, stream=None):
+
+class Plan:
+    """A plan for one slab system on the current HIP device and stream.
+
+    With own_workspace=False the plan holds only its tables; attach device
+    memory with bind() before solving (several plans may share one arena if
+    they run on one stream)."""
+
+    def __init__(self, params, max_n: int, precision: int = DPSE_FP64, stream=None, own_workspace: bool = True):
         import torch
         self._torch = torch
         self.params = params
@@ -138,10 +161,15 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.workspace = None
         prm = _params(params, precision)
         h = ctypes.c_void_p()
-        _check(_lib().dpse_plan_create(ctypes.byref(prm), self.max_n, ctypes.c_void_p(stream.cuda_stream),
-                                       ctypes.byref(h)), "dpse_plan_create")
+        if own_workspace:
+            _check(_lib().dpse_plan_create(ctypes.byref(prm), self.max_n, ctypes.c_void_p(stream.cuda_stream),
+                                           ctypes.byref(h)), "dpse_plan_create")
+        else:
+            _check(_lib().dpse_plan_create_unbound(ctypes.byref(prm), self.max_n, ctypes.byref(h)),
+                   "dpse_plan_create_unbound")
         self._h = h
         info = _Info()
         _check(_lib().dpse_plan_info(h, ctypes.byref(info)), "dpse_plan_info")
@@ -168,6 +196,24 @@ class Plan:
             force = torch.empty((n, 3), dtype=torch.float64, device=dev)
         _check(_lib().dpse_solve(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
                                  force.data_ptr()), "dpse_solve")
+        return energy, phi, force
+
+    def bind(self, workspace, stream=None):
+        """Attaches a caller-owned uint8 device tensor (kept referenced here)
+        and a stream to a plan made with own_workspace=False."""
+        if stream is None:
+            stream = self._torch.cuda.current_stream()
+        _check(_lib().dpse_plan_bind(self._h, workspace.data_ptr(), workspace.numel() * workspace.element_size(),
+                                     ctypes.c_void_p(stream.cuda_stream)), "dpse_plan_bind")
+        self.workspace = workspace
+        self.stream = stream
+
+    def solve_graph(self, pos, q, energy, phi, force):
+        """dpse_solve_graph: the solve as one graph launch (re-captured when
+        the sizes, buffers or stream change). Outputs must be given."""
+        n = int(q.shape[0])
+        _check(_lib().dpse_solve_graph(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(),
+                                       phi.data_ptr(), force.data_ptr()), "dpse_solve_graph")
         return energy, phi, force
 
     def sync(self) -> int:
@@ -248,3 +294,40 @@ def solve_batch(plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Optio
     _check(_lib().dpse_solve_batch(k, hs, ns, ptr(pos), ptr(q), ptr(energy), ptr(phi), ptr(force)),
            "dpse_solve_batch")
     return energy, phi, force
+
+
+class BatchGraph:
+    """dpse_batch_graph_create: a batch of solves captured into one graph.
+    The tensors passed here are kept referenced; launch() re-runs the batch on
+    whatever they hold."""
+
+    def __init__(self, plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Sequence, phi: Sequence,
+                 force: Sequence, branch: Optional[Sequence[int]] = None, n_branches: int = 1):
+        k = len(plans)
+        VP = ctypes.c_void_p * k
+        hs = VP(*[p_.handle.value for p_ in plans])
+        ns = (ctypes.c_int64 * k)(*[int(q_.shape[0]) for q_ in q])
+        ptr = lambda ts: VP(*[t.data_ptr() for t in ts])
+        br = None if branch is None else (ctypes.c_int32 * k)(*[int(b) for b in branch])
+        h = ctypes.c_void_p()
+        _check(_lib().dpse_batch_graph_create(k, hs, ns, ptr(pos), ptr(q), ptr(energy), ptr(phi), ptr(force), br,
+                                              int(n_branches), ctypes.byref(h)), "dpse_batch_graph_create")
+        self._h = h
+        self._keep = (list(plans), list(pos), list(q), list(energy), list(phi), list(force))
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(_lib().dpse_graph_launch(self._h, ctypes.c_void_p(stream.cuda_stream)), "dpse_graph_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib().dpse_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,215 @@
+"""GPU tests of the batching and serving paths: caller-bound workspaces,
+graph-captured solves (replayed with eager work in between), one-launch
+batches of uneven systems, and the request loop, whose results must be the
+same for a request served alone and in a mix."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dpse_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def dev(a):
+    return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+
+def small_system(seed, n_pairs, L=16.0, H=8.0, eb=0.05, et=20.0, Nz=33):
+    p = W.SlabParams(Lx=L, Ly=L, H=H, eps=1.0, eps_b=eb, eps_t=et, xi=1.0, Nx=int(L / 0.25), Ny=int(L / 0.25),
+                     Nz=Nz, r_cut=3.0)
+    pos, q = W.charges(seed, n_pairs, n_pairs, L, L, 0.5, H - 0.5)
+    return p, pos, q
+
+
+def outputs(n):
+    return (torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+            torch.empty((n, 3), dtype=torch.float64, device="cuda"))
+
+
+def test_bound_workspace_matches_owned_and_is_shared():
+    """Two unbound plans of different systems share one arena on one stream
+    and give the results of plans that own their workspace."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    sys_a = small_system(11, 100)
+    sys_b = small_system(12, 60, L=32.0, H=12.0, eb=1.0, et=0.05)
+    ref = []
+    for p, pos, q in (sys_a, sys_b):
+        pl = dp.Plan(p, max_n=len(q))
+        U, phi, F = pl.solve(dev(pos), dev(q))
+        assert pl.sync_status() == 0
+        ref.append((float(U.cpu()[0]), phi.cpu().numpy(), F.cpu().numpy()))
+        pl.close()
+    plans = [dp.Plan(p, max_n=len(q), own_workspace=False) for p, _, q in (sys_a, sys_b)]
+    need = max(pl.info["workspace_bytes"] for pl in plans)
+    assert need == max(dp.workspace_size(p, len(q)) for p, _, q in (sys_a, sys_b))
+    arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dp.DpseError):   # not bound yet
+        plans[0].solve(dev(sys_a[1]), dev(sys_a[2]))
+    with pytest.raises(dp.DpseError):   # too small
+        plans[0].bind(arena[: 1024])
+    for rep in range(2):
+        for k, (p, pos, q) in enumerate((sys_a, sys_b)):
+            plans[k].bind(arena)
+            U, phi, F = plans[k].solve(dev(pos), dev(q))
+            assert plans[k].sync_status() == 0
+            U0, phi0, F0 = ref[k]
+            print(f"[case] shared arena rep {rep} system {k}: F {rel_rms(F.cpu().numpy(), F0):.2e}", flush=True)
+            assert rel_rms(F.cpu().numpy(), F0) < 1e-13 and rel_rms(phi.cpu().numpy(), phi0) < 1e-13
+            assert abs(float(U.cpu()[0]) - U0) < 1e-12 * abs(U0)
+    for pl in plans:
+        pl.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_solve_replays_match_eager(precision):
+    """dpse_solve_graph: several replays with eager solves and host syncs in
+    between, new positions written into the captured buffers, and a
+    re-capture when n changes; every replay equals the eager result."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_system(13, 120)
+    tol = 1e-13 if precision == 0 else 2e-6
+    plan_g = dp.Plan(p, max_n=len(q), precision=precision)
+    plan_e = dp.Plan(p, max_n=len(q), precision=precision)
+    tp, tq = dev(pos), dev(q)
+    E, PH, F = outputs(len(q))
+    rng = np.random.default_rng(5)
+    for rep in range(4):
+        cur = W.perturb(pos, rng, 0.05, p.Lx, p.Ly, p.H) if rep else pos
+        tp.copy_(dev(cur))
+        plan_g.solve_graph(tp, tq, E, PH, F)
+        assert plan_g.sync_status() == 0
+        Ue, phie, Fe = plan_e.solve(dev(cur), tq)
+        assert plan_e.sync_status() == 0
+        eF = rel_rms(F.cpu().numpy(), Fe.cpu().numpy())
+        print(f"[case] graph replay {rep} prec={precision}: F {eF:.2e}", flush=True)
+        assert eF < tol and rel_rms(PH.cpu().numpy(), phie.cpu().numpy()) < tol
+        assert abs(float(E.cpu()[0]) - float(Ue.cpu()[0])) < 10 * tol * abs(float(Ue.cpu()[0]))
+    # a neutral subset: new n -> re-capture
+    sel = np.sort(np.concatenate([np.nonzero(q > 0)[0][:40], np.nonzero(q < 0)[0][:40]]))
+    tp2, tq2 = dev(pos[sel]), dev(q[sel])
+    E2, PH2, F2 = outputs(len(sel))
+    for rep in range(2):
+        plan_g.solve_graph(tp2, tq2, E2, PH2, F2)
+        assert plan_g.sync_status() == 0
+    U0, phi0, F0, _ = O.solve(p, pos[sel], q[sel])
+    assert rel_rms(F2.cpu().numpy(), F0) < (1e-9 if precision == 0 else 1e-5)
+    plan_g.close()
+    plan_e.close()
+
+
+def test_graph_detects_device_errors():
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_system(14, 30)
+    plan = dp.Plan(p, max_n=len(q))
+    tp, tq = dev(pos), dev(q)
+    E, PH, F = outputs(len(q))
+    plan.solve_graph(tp, tq, E, PH, F)
+    assert plan.sync_status() == 0
+    bad = pos.copy(); bad[2, 2] = p.H + 1.0
+    tp.copy_(dev(bad))
+    plan.solve_graph(tp, tq, E, PH, F)
+    assert plan.sync_status() == 5
+    tp.copy_(dev(pos))
+    plan.solve_graph(tp, tq, E, PH, F)
+    assert plan.sync_status() == 0
+    plan.close()
+
+
+def uneven_batch():
+    out = []
+    specs = [(21, 40, 16.0, 8.0, 0.05, 20.0, 33), (22, 150, 32.0, 8.0, 1.0, 1.0, 33),
+             (23, 90, 16.0, 16.0, 20.0, 0.05, 65), (24, 16, 8.0, 8.0, 0.05, 0.05, 33),
+             (25, 220, 32.0, 16.0, 1.0, 20.0, 65), (26, 64, 16.0, 8.0, 20.0, 20.0, 33)]
+    for seed, npair, L, H, eb, et, Nz in specs:
+        out.append(small_system(seed, npair, L=L, H=H, eb=eb, et=et, Nz=Nz))
+    return out
+
+
+@pytest.mark.parametrize("precision,use_graph", [(0, True), (0, False), (1, True)])
+def test_batch_matches_single_solves(precision, use_graph):
+    """Six uneven systems in three branches (one graph launch per run) equal
+    their single solves, over repeated runs with changed positions."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    from paper_2101_07088_amd.batch import BatchRunner
+    systems = uneven_batch()
+    tens = [(p, dev(pos), dev(q)) for p, pos, q in systems]
+    br = BatchRunner(tens, precision=precision, n_branches=3, use_graph=use_graph)
+    tol = 1e-13 if precision == 0 else 2e-6
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        cur = [W.perturb(pos, rng, 0.05, p.Lx, p.Ly, p.H) if rep else pos for p, pos, _ in systems]
+        for k, c in enumerate(cur):
+            tens[k][1].copy_(dev(c))
+        torch.cuda.synchronize()
+        br.run()
+        torch.cuda.synchronize()
+        assert all(s == 0 for s in br.statuses())
+        for k, (p, _, q) in enumerate(systems):
+            pl = dp.Plan(p, max_n=len(q), precision=precision)
+            U, phi, F = pl.solve(dev(cur[k]), dev(q))
+            assert pl.sync_status() == 0
+            eF = rel_rms(br.force[k].cpu().numpy(), F.cpu().numpy())
+            assert eF < tol, (rep, k, eF)
+            assert rel_rms(br.phi[k].cpu().numpy(), phi.cpu().numpy()) < tol
+            pl.close()
+        print(f"[case] batch rep {rep} prec={precision} graph={use_graph} ok", flush=True)
+    # two systems against the oracle
+    for k in (0, 4):
+        p, _, q = systems[k]
+        U0, phi0, F0, _ = O.solve(p, cur[k], q)
+        assert rel_rms(br.force[k].cpu().numpy(), F0) < (1e-9 if precision == 0 else 1e-5)
+    br.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_server_alone_equals_mix(precision):
+    """Each request gives the same result served alone (a fresh plan, nothing
+    else on the device) and in a mix of concurrent requests from several
+    systems under a memory budget that forces queueing."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    from paper_2101_07088_amd.serve import Server
+    systems = uneven_batch()
+    fps = [dp.workspace_size(p, len(q), precision) for p, _, q in systems]
+    budget = int(sum(sorted(fps)[-3:]) * 1.05)          # at most about three in flight
+    srv = Server(budget_bytes=budget, n_slots=4, precision=precision)
+    for k, (p, _, q) in enumerate(systems):
+        srv.register(k, p, len(q))
+    rng = np.random.default_rng(17)
+    reqs = []
+    for rnd in range(3):
+        for k, (p, pos, q) in enumerate(systems):
+            cur = W.perturb(pos, rng, 0.05, p.Lx, p.Ly, p.H)
+            reqs.append((k, cur, srv.submit(k, dev(cur), dev(q))))
+        srv.step()
+    srv.drain()
+    assert srv.stats["completed"] == len(reqs) and srv.stats["failed"] == 0
+    assert srv.stats["peak_bytes"] <= budget
+    print(f"[case] server prec={precision}: {srv.stats}", flush=True)
+    tol = 1e-13 if precision == 0 else 2e-6
+    for k, cur, r in reqs:
+        p, _, q = systems[k]
+        pl = dp.Plan(p, max_n=len(q), precision=precision)
+        U, phi, F = pl.solve(dev(cur), dev(q))
+        assert pl.sync_status() == 0
+        E1, PH1, F1 = r.result
+        assert rel_rms(F1.cpu().numpy(), F.cpu().numpy()) < tol
+        assert rel_rms(PH1.cpu().numpy(), phi.cpu().numpy()) < tol
+        assert abs(float(E1.cpu()[0]) - float(U.cpu()[0])) < 10 * tol * abs(float(U.cpu()[0]))
+        pl.close()
+    srv.close()

@@ -149,6 +149,40 @@ def perturb(pos: np.ndarray, rng: np.random.Generator, std: float,
     return np.ascontiguousarray(p)
 
 
+def serving_trajectories(n_traj: int = 256, seed0: int = 3000) -> List[Tuple[SlabParams, np.ndarray, np.ndarray]]:
+    """Independent Brownian-like trajectories for a serving stream: N
+    log-uniform in [512, 262144] (even, +-1), box and permittivities drawn as
+    in batch_systems and fixed per trajectory; returns the initial state."""
+    out = []
+    for t in range(n_traj):
+        rng = np.random.default_rng(seed0 + t)
+        n = int(round(math.exp(rng.uniform(math.log(512), math.log(262144)))))
+        n -= n % 2
+        L = float(rng.choice([32.0, 64.0, 128.0]))
+        H = float(rng.choice([16.0, 32.0, 64.0]))
+        eb = float(rng.choice([0.05, 1.0, 20.0]))
+        et = float(rng.choice([0.05, 1.0, 20.0]))
+        nxy = int(round(L / 0.25))
+        p = SlabParams(Lx=L, Ly=L, H=H, eps=1.0, eps_b=eb, eps_t=et, xi=1.5,
+                       Nx=nxy, Ny=nxy, Nz=int(round(H / 0.25)) + 1, r_cut=2.0)
+        pos, q = charges(seed0 + 104729 * (t + 1), n // 2, n // 2, L, L, 0.5, H - 0.5)
+        out.append((p, pos, q))
+    return out
+
+
+def poisson_arrivals(rate: float, duration: float, n_traj: int, seed: int = 2000) -> Tuple[np.ndarray, np.ndarray]:
+    """Arrival times (s) of a Poisson stream of the given rate over
+    [0, duration) and the trajectory of each request (uniform)."""
+    rng = np.random.default_rng(seed)
+    n = int(rate * duration * 1.5) + 64
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    while t[-1] < duration:
+        t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate, n))])
+    t = t[t < duration]
+    traj = rng.integers(0, n_traj, len(t))
+    return t, traj
+
+
 NAMED: Dict[str, object] = {
     "small": config_small,
     "jump": config_jump,
