@@ -51,6 +51,7 @@ def band_fraction(p, info):
 
 def time_path(dp, torch, p, tpos, tq, precision, steps, warmup):
     plan = dp.Plan(p, max_n=len(tq), precision=precision)
+    tiles, tile_ms = plan.autotune(tpos, tq, reps=3)   # plan-time tuning, outside the timed region
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     PH = torch.empty(len(tq), dtype=torch.float64, device="cuda")
     F = torch.empty((len(tq), 3), dtype=torch.float64, device="cuda")
@@ -76,7 +77,7 @@ def time_path(dp, torch, p, tpos, tq, precision, steps, warmup):
     stages, _ = plan.stage_times()
     plan.set_timing(False)
     plan.sync()
-    out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]),
+    out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]), tiles=tiles,
                phi=PH.cpu().numpy(), F=F.cpu().numpy(), far=plan.debug(dp.Stage.FAR)[: len(tq)], info=plan.info)
     plan.close()
     return out
@@ -252,6 +253,8 @@ def main(argv=None):
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
@@ -261,6 +264,12 @@ def main(argv=None):
     import paper_2101_07088_amd as dp
     import workloads as W
 
+    if a.copy_probe_mb:
+        src = torch.ones(a.copy_probe_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p, pos, q = W.config_jump(a.seed)
     tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
     tq = torch.tensor(q, dtype=torch.float64, device="cuda")
@@ -301,6 +310,7 @@ def main(argv=None):
                    "precision": head, "parallelism": "single GPU"},
         "p50_ms": float(np.percentile(r["lat_ms"], 50)), "p99_ms": float(np.percentile(r["lat_ms"], 99)),
         "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
+        "tiles": {"spread": r["tiles"][0], "interp": r["tiles"][1], "column": r["tiles"][2]},
         "accuracy": acc,
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},

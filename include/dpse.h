@@ -189,6 +189,26 @@ int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n
 int dpse_graph_launch(dpse_graph* graph, void* stream);
 int dpse_graph_destroy(dpse_graph* graph);
 
+/* Launch shapes picked per grid. Spreading and interpolation work on LDS
+ * tiles of T x T grid columns by P Chebyshev nodes; the column kernel on
+ * blocks of KE / (2(Nz-1)) modes (KE complex LDS elements per buffer). The
+ * fastest shapes depend on the grid, the support and the charge density.
+ * dpse_plan_autotune runs one solve of the given charges (outputs discarded),
+ * then times every applicable candidate of each tuned stage `reps` times with
+ * HIP events on the plan's stream, keeps the fastest in the plan, writes the
+ * chosen candidate of stage s (0 spreading, 1 interpolation, 2 column) to
+ * choice[s] if choice is not NULL (DPSE_NUM_TUNED entries), and the mean
+ * milliseconds of candidate i of stage s to ms[8 s + i] (-1 where a candidate
+ * does not apply) if ms is not NULL (8 * DPSE_NUM_TUNED entries). Synchronous;
+ * returns the device status of the solve like dpse_sync. dpse_plan_set_tiles
+ * applies stored choices (-1 = the default rule) to a plan of the same grid;
+ * DPSE_EINVAL if a choice does not apply. Results depend on the choice only
+ * through rounding (the order of floating-point sums). */
+enum { DPSE_NUM_TUNED = 3 };
+int dpse_plan_autotune(dpse_plan* plan, int64_t n, const double* pos, const double* q, int reps,
+                       int32_t* choice, double* ms);
+int dpse_plan_set_tiles(dpse_plan* plan, const int32_t* choice);
+
 /* Waits for the plan's stream and returns the device-side status of the
  * solves enqueued since the previous dpse_sync (DPSE_OK, DPSE_ENONNEUTRAL,
  * DPSE_EOUTSIDE or DPSE_ECONSTRAINT), clearing it. */

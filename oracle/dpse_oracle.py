@@ -361,12 +361,21 @@ def near_kernel(r, p, xi_e):
     return G, -dG / r
 
 
-def near_field(p, d, pos, q, chunk=1024, rows=None):
+def near_field(p, d, pos, q, chunk=1024, rows=None, targets=None):
     """For each charge k: sum over charges j != k and over the bottom/top
     images of all j (strengths gamma_b q_j, gamma_t q_j, at (x,y,-z) and
     (x,y,2H-z)) with minimal-image distance r < r_cut. Returns [n, 4].
     ``rows`` (a slice step) restricts the targets to every rows-th chunk of
-    ``chunk`` charges (the others stay 0); used only to time a sample."""
+    ``chunk`` charges (the others stay 0); used only to time a sample.
+    ``targets`` (an index array) computes only those charges and returns
+    [len(targets), 4] (sampled checks of large systems)."""
+    if targets is not None:
+        targets = np.asarray(targets)
+        out = np.zeros((len(targets), 4))
+        for t0 in range(0, len(targets), 32):
+            tt = targets[t0:t0 + 32]
+            out[t0:t0 + 32] = _near_targets(p, d, pos, q, tt)
+        return out / (FOUR_PI * p.eps)
     n = len(q)
     out = np.zeros((n, 4))
     srcs = [(pos, q, True)]
@@ -397,6 +406,36 @@ def near_field(p, d, pos, q, chunk=1024, rows=None):
             np.add.at(out[:, 2], ti + t0, qs * e * dy[ti, sj])
             np.add.at(out[:, 3], ti + t0, qs * e * dz[ti, sj])
     return out / (FOUR_PI * p.eps)
+
+
+def _near_targets(p, d, pos, q, tt):
+    """Unscaled near sums (times 4 pi eps) for the charges with indices tt."""
+    out = np.zeros((len(tt), 4))
+    srcs = [(pos, q, True)]
+    if d["gamma_b"] != 0.0:
+        srcs.append((np.stack([pos[:, 0], pos[:, 1], -pos[:, 2]], 1), d["gamma_b"] * q, False))
+    if d["gamma_t"] != 0.0:
+        srcs.append((np.stack([pos[:, 0], pos[:, 1], 2 * p.H - pos[:, 2]], 1), d["gamma_t"] * q, False))
+    tp = pos[tt]
+    for sp, sq, exclude_self in srcs:
+        dx = tp[:, None, 0] - sp[None, :, 0]
+        dy = tp[:, None, 1] - sp[None, :, 1]
+        dz = tp[:, None, 2] - sp[None, :, 2]
+        dx -= p.Lx * np.round(dx / p.Lx)
+        dy -= p.Ly * np.round(dy / p.Ly)
+        r2 = dx * dx + dy * dy + dz * dz
+        m = r2 < p.r_cut ** 2
+        if exclude_self:
+            m[np.arange(len(tt)), tt] = False
+        ti, sj = np.nonzero(m)
+        r = np.sqrt(r2[ti, sj])
+        G, e = near_kernel(r, p, d["xi_e"])
+        qs = sq[sj]
+        np.add.at(out[:, 0], ti, qs * G)
+        np.add.at(out[:, 1], ti, qs * e * dx[ti, sj])
+        np.add.at(out[:, 2], ti, qs * e * dy[ti, sj])
+        np.add.at(out[:, 3], ti, qs * e * dz[ti, sj])
+    return out
 
 
 def near_at_origin(p, d, pos, q):

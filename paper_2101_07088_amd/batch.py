@@ -43,7 +43,8 @@ class BatchRunner:
     systems: sequence of (params, pos, q) with pos, q float64 device tensors
     ([n,3] and [n]); they stay referenced and are read on every run()."""
 
-    def __init__(self, systems, precision: int = native.DPSE_MIXED, n_branches: int = 8, use_graph: bool = True):
+    def __init__(self, systems, precision: int = native.DPSE_MIXED, n_branches: int = 8, use_graph: bool = True,
+                 autotune: bool = True):
         import torch
         self.torch = torch
         self.n_branches = max(1, min(n_branches, len(systems)))
@@ -61,6 +62,19 @@ class BatchRunner:
         self.streams = [torch.cuda.Stream(device=dev) for _ in range(self.n_branches)]
         for i, pl in enumerate(self.plans):
             pl.bind(self.arenas[self.branch[i]], self.streams[self.branch[i]])
+        self.tiles = {}
+        if autotune:
+            torch.cuda.synchronize()
+            # one tuning run per distinct grid shape, on its first system; the
+            # others of that shape reuse the choice
+            for i, pl in enumerate(self.plans):
+                p, pos, q = self.systems[i]
+                key = (p.Nx, p.Ny, p.Nz, pl.info["support"])
+                if key not in self.tiles:
+                    self.tiles[key], _ = pl.autotune(pos, q, reps=2)
+                else:
+                    pl.set_tiles(self.tiles[key])
+            torch.cuda.synchronize()
         self.energy = [torch.empty(1, dtype=torch.float64, device=dev) for _ in self.systems]
         self.phi = [torch.empty(int(q.shape[0]), dtype=torch.float64, device=dev) for _, _, q in self.systems]
         self.force = [torch.empty((int(q.shape[0]), 3), dtype=torch.float64, device=dev) for _, _, q in self.systems]

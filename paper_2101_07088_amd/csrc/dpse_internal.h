@@ -47,8 +47,6 @@ constexpr int kNumFun = 10;    // S1, S2, S3, S4, V0, VH, D0, DH, Ea, Eb
 enum { FUN_S1 = 0, FUN_S2, FUN_S3, FUN_S4, FUN_V0, FUN_VH, FUN_D0, FUN_DH, FUN_EA, FUN_EB };
 
 // Launch shapes.
-constexpr int kSpreadT = 32;  // spreading tile (grid cells per side)
-constexpr int kInterpT = 32;  // interpolation tile
 constexpr int kBin = 16;      // particle bin width (grid cells)
 constexpr int kMaxSupport = 32;  // n_g <= the tile width (one contiguous window run per tile)
 
@@ -135,6 +133,11 @@ struct dpse_plan {
   hipGraphExec_t graph_exec = nullptr; // captured solve (dpse_solve_graph)
   const void* graph_sig[7] = {};
   hipStream_t graph_stream = nullptr;
+  // tile shapes of spreading and interpolation: index into the candidate
+  // lists of k_grid.hip, or -1 for the default rule (dpse_plan_autotune)
+  int spread_cfg = -1;
+  int interp_cfg = -1;
+  int column_cfg = -1;   // modes per column block (kColumnKE of k_column.hip)
   // per-stage timing: one row of DPSE_NUM_STAGES + 1 events per recorded solve
   bool timing = false;
   std::vector<hipEvent_t> events;
@@ -155,6 +158,17 @@ template <typename R> hipError_t launch_near(dpse_plan* p, int64_t n);
 template <typename R> hipError_t launch_gauge(dpse_plan* p, int64_t n);
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
                            double* phi, double* force);
+
+// Tile-shape candidates of spreading (stage 0) and interpolation (stage 1):
+// count, shape of candidate i (x,y tile width T and z nodes per block P), and
+// whether it applies to the plan's grid.
+int tile_candidates(int stage);
+void tile_shape(int stage, int i, int* T, int* P);
+bool tile_valid(const Geom& g, int stage, int i, bool fp64);
+// Column-kernel block sizes (complex LDS elements per buffer).
+int column_candidates();
+int column_block(int i);
+bool column_valid(const Geom& g, int i);
 
 // Sets kernel attributes once (before any stream capture).
 hipError_t prepare_kernels();

@@ -30,8 +30,12 @@ namespace dpse {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kElems = 2048;  // complex elements per buffer (modes x 2(Nz-1))
-constexpr int kMaxMB = 32;    // modes per block for the smallest Nz
+// KE (a template parameter) = complex elements per LDS buffer = modes per
+// block x 2(Nz-1); one of kColumnKE, chosen per grid by the autotuner.
+constexpr int kColumnKE[] = {2048, 1024, 4096};
+constexpr int kNumColumn = 3;
+constexpr int kMaxMB = 32;    // modes per block: 8 MB chain threads <= kThreads
+constexpr size_t kMaxLds = 160 * 1024;
 
 template <typename R>
 struct CT;
@@ -57,7 +61,7 @@ __device__ inline double rcp_refined(double d) {
   return fma(r, e, r);
 }
 
-template <typename R>
+template <typename R, int KE>
 __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                      const typename CT<R>::T* __restrict__ fx_o,
                                                      typename CT<R>::T* __restrict__ psi,
@@ -67,6 +71,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
                                                      const double2* __restrict__ twz, double* scal) {
   using C = typename CT<R>::T;
   extern __shared__ double2 smem2[];
+  constexpr int kElems = KE;
   double2* A = smem2;               // psi_o* work, later the final series of psi_i*
   double2* B = smem2 + kElems;      // psi_i* work, later its derivative series
   double2* tw = smem2 + 2 * kElems; // twiddles exp(-2 pi i k / M), k < M/2
@@ -81,7 +86,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
 
   const int N = g.Nz, M = 2 * (N - 1), logM = ilog2d(M);
   const int MB = kElems / M;
-  const int logMB = 11 - logM;  // kElems = 2^11
+  const int logMB = ilog2d(KE) - logM;
   const int NU = N + 2;
   const int nmodes = g.Ny * g.nkx;
   const int m0 = blockIdx.x * MB;
@@ -153,25 +158,53 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   //    psi_o*, and the unit free constant (kappa^2 on the chain's first row).
   //    Four threads per chain, one real right-hand side each (the first also
   //    carries the free constant); each recomputes the elimination pivots.
+  //    Both sweeps move through the chain in groups of kSweep rows: the LDS
+  //    operands of a group are loaded together and its results stored
+  //    together, so the serial recurrence runs on registers and the LDS
+  //    latency is paid once per group instead of once per row.
+  constexpr int kSweep = 8;
   if (tid < 8 * MB) {
     const int k = tid >> (logMB + 1);          // right-hand side: 0 Re i, 1 Im i, 2 Re o, 3 Im o
     const int cm = tid & (2 * MB - 1);
     const int m = cm & (MB - 1), par = cm >> logMB;
     double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);  // X[n * 2 MB]
     const double kap2 = s_kap[m] * s_kap[m];
+    const int L = par == 0 ? (N + 1) / 2 : N / 2;
     double cp = 0.0, d = 0.0, dh = 0.0;
-    int r = 0;
-    for (int n = par; n < N; n += 2, ++r) {
-      const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
-      const double inv = rcp_refined(fma(-sub, cp, dia));
-      d = (gsc[n] * X[n * 2 * MB] - sub * d) * inv;
-      X[n * 2 * MB] = d;
-      if (k == 0) {
-        dh = ((r == 0 ? kap2 : 0.0) - sub * dh) * inv;
-        spare(spB, m, par * half0 + r) = dh;
+    for (int r0 = 0; r0 < L; r0 += kSweep) {
+      double xv[kSweep], av[kSweep], bv[kSweep], cv[kSweep], gv[kSweep];
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        const int n = par + 2 * min(r0 + u, L - 1);
+        xv[u] = X[n * 2 * MB];
+        av[u] = ca[n];
+        bv[u] = cb[n];
+        cv[u] = cc[n];
+        gv[u] = gsc[n];
       }
-      cp = sup * inv;
-      if (k == 0) spare(spA, m, par * half0 + r) = cp;
+      double dv[kSweep], cpv[kSweep], dhv[kSweep];
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        const double sub = -kap2 * av[u], dia = fma(kap2, bv[u], 1.0), sup = -kap2 * cv[u];
+        const double inv = rcp_refined(fma(-sub, cp, dia));
+        d = (gv[u] * xv[u] - sub * d) * inv;
+        dh = ((r0 + u == 0 ? kap2 : 0.0) - sub * dh) * inv;
+        cp = sup * inv;
+        dv[u] = d;
+        dhv[u] = dh;
+        cpv[u] = cp;
+      }
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        const int r = r0 + u;
+        if (r < L) {
+          X[(par + 2 * r) * 2 * MB] = dv[u];
+          if (k == 0) {
+            spare(spB, m, par * half0 + r) = dhv[u];
+            spare(spA, m, par * half0 + r) = cpv[u];
+          }
+        }
+      }
     }
   }
   __syncthreads();
@@ -183,14 +216,30 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     const int L = par == 0 ? (N + 1) / 2 : N / 2;
     double x = X[(par + 2 * (L - 1)) * 2 * MB];
     double xh = spare(spB, m, par * half0 + L - 1);
-    for (int r = L - 2; r >= 0; --r) {
-      const int n = par + 2 * r;
-      const double c = spare(spA, m, par * half0 + r);
-      x = fma(-c, x, X[n * 2 * MB]);
-      X[n * 2 * MB] = x;
-      if (k == 0) {  // the only thread touching this chain's homogeneous entries
-        xh = fma(-c, xh, spare(spB, m, par * half0 + r));
-        spare(spB, m, par * half0 + r) = xh;
+    // rows L-2 down to 0, in groups of kSweep from the top
+    for (int r1 = L - 2; r1 >= 0; r1 -= kSweep) {
+      double xv[kSweep], cv[kSweep], hv[kSweep];
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        const int r = max(r1 - u, 0);
+        xv[u] = X[(par + 2 * r) * 2 * MB];
+        cv[u] = spare(spA, m, par * half0 + r);
+        hv[u] = spare(spB, m, par * half0 + r);
+      }
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        x = fma(-cv[u], x, xv[u]);
+        xh = fma(-cv[u], xh, hv[u]);
+        xv[u] = x;
+        hv[u] = xh;
+      }
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) {
+        const int r = r1 - u;
+        if (r >= 0) {
+          X[(par + 2 * r) * 2 * MB] = xv[u];
+          if (k == 0) spare(spB, m, par * half0 + r) = hv[u];  // the only thread touching these entries
+        }
       }
     }
   }
@@ -202,12 +251,16 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   //    (slopes at the domain ends). One thread per (mode, weight vector) sums
   //    over all indices for six vectors: psi_i* re/im, psi_o* re/im, h1, h2.
   //    s_fun[(m * 10 + f) * 6 + v].
-  for (int t = tid; t < MB * 10; t += kThreads) {
-    const int m = t / 10, f = t - 10 * m;
+  //    Two lanes (adjacent, same wave) share a dot product: each sums half
+  //    of the indices and a lane exchange adds the halves.
+  for (int t = tid; t < MB * 20; t += kThreads) {
+    const int pr = t >> 1, part = t & 1;
+    const int m = pr / 10, f = pr - 10 * m;
     const double* Wf = W + f * NU;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = Wf[N], a5 = Wf[N + 1];
+    const int jh = (N + 1) / 2, ja = part ? jh : 0, jb = part ? N : jh;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = part ? 0.0 : Wf[N], a5 = part ? 0.0 : Wf[N + 1];
 #pragma unroll 4
-    for (int j = 0; j < N; ++j) {
+    for (int j = ja; j < jb; ++j) {
       const double w = Wf[j];
       const double2 xi = B[j * MB + m], xo = A[j * MB + m];
       const double hv = hval(m, j);
@@ -217,8 +270,16 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
       a3 = fma(w, xo.y, a3);
       if (j & 1) a5 = fma(w, hv, a5); else a4 = fma(w, hv, a4);
     }
-    double* o = s_fun + (m * 10 + f) * 6;
-    o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
+    a0 += __shfl_xor(a0, 1, 64);
+    a1 += __shfl_xor(a1, 1, 64);
+    a2 += __shfl_xor(a2, 1, 64);
+    a3 += __shfl_xor(a3, 1, 64);
+    a4 += __shfl_xor(a4, 1, 64);
+    a5 += __shfl_xor(a5, 1, 64);
+    if (part == 0) {
+      double* o = s_fun + (m * 10 + f) * 6;
+      o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
+    }
   }
   __syncthreads();
 
@@ -422,19 +483,47 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
 
 }  // namespace
 
-template <typename R>
-hipError_t launch_column(dpse_plan* p) {
+namespace {
+size_t column_lds(const Geom& g, int KE) {
+  const int M = 2 * (g.Nz - 1);
+  const int MB = KE / M;
+  return (size_t)(2 * KE + M / 2) * sizeof(double2) + (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
+}
+
+template <typename R, int KE>
+void column_as(dpse_plan* p) {
   using C = typename CT<R>::T;
   const Geom& g = p->g;
   const int M = 2 * (g.Nz - 1);
-  const int MB = kElems / M;
+  const int MB = KE / M;
   const int nmodes = g.Ny * g.nkx;
   const int nb = (nmodes + MB - 1) / MB;
-  const size_t shmem = (size_t)(2 * kElems + M / 2) * sizeof(double2) +
-                       (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
-  hipLaunchKernelGGL(k_column<R>, dim3(nb), dim3(kThreads), shmem, p->stream, g, (const C*)p->w.fx_i,
-                     (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
+  hipLaunchKernelGGL((k_column<R, KE>), dim3(nb), dim3(kThreads), column_lds(g, KE), p->stream, g,
+                     (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
                      (const double*)p->t.ctab, (const double2*)p->t.twz, p->w.scal);
+}
+}  // namespace
+
+int column_candidates() { return kNumColumn; }
+
+int column_block(int i) { return kColumnKE[i]; }
+
+// A block of KE / M modes needs M <= KE, at most kMaxMB modes and its LDS.
+bool column_valid(const Geom& g, int i) {
+  if (i < 0 || i >= kNumColumn) return false;
+  const int KE = kColumnKE[i], M = 2 * (g.Nz - 1);
+  return M <= KE && KE / M <= kMaxMB && column_lds(g, KE) <= kMaxLds;
+}
+
+template <typename R>
+hipError_t launch_column(dpse_plan* p) {
+  int c = p->column_cfg;
+  if (!column_valid(p->g, c)) c = column_valid(p->g, 0) ? 0 : (column_valid(p->g, 1) ? 1 : 2);
+  switch (c) {
+    case 0: column_as<R, 2048>(p); break;
+    case 1: column_as<R, 1024>(p); break;
+    default: column_as<R, 4096>(p); break;
+  }
   return hipGetLastError();
 }
 
@@ -442,11 +531,14 @@ hipError_t launch_column(dpse_plan* p) {
 // called at plan creation so that no attribute call happens inside a solve
 // (which may be captured into a graph).
 hipError_t prepare_kernels() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_column<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     96 * 1024);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_column<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
-  return e;
+  const void* fns[] = {(const void*)k_column<double, 2048>, (const void*)k_column<float, 2048>,
+                       (const void*)k_column<double, 1024>, (const void*)k_column<float, 1024>,
+                       (const void*)k_column<double, 4096>, (const void*)k_column<float, 4096>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template hipError_t launch_column<double>(dpse_plan*);

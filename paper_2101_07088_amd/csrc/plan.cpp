@@ -666,6 +666,91 @@ int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
   return DPSE_OK;
 }
 
+// Tuned launch shapes: stage 0 spreading tiles, 1 interpolation tiles, 2
+// column-kernel blocks.
+static int tuned_count(int s) { return s < 2 ? dpse::tile_candidates(s) : dpse::column_candidates(); }
+
+static bool tuned_valid(const dpse_plan* p, int s, int i) {
+  const bool fp64 = p->prm.precision != DPSE_MIXED;
+  return s < 2 ? dpse::tile_valid(p->g, s, i, fp64) : dpse::column_valid(p->g, i);
+}
+
+static int& tuned_cfg(dpse_plan* p, int s) {
+  return s == 0 ? p->spread_cfg : (s == 1 ? p->interp_cfg : p->column_cfg);
+}
+
+static hipError_t launch_tuned(dpse_plan* p, int s, int64_t n) {
+  const bool fp64 = p->prm.precision != DPSE_MIXED;
+  if (s == 0) return fp64 ? dpse::launch_spread<double>(p) : dpse::launch_spread<float>(p);
+  if (s == 1) return fp64 ? dpse::launch_interp<double>(p, n) : dpse::launch_interp<float>(p, n);
+  return fp64 ? dpse::launch_column<double>(p) : dpse::launch_column<float>(p);
+}
+
+static void drop_graph(dpse_plan* p) {
+  if (p->graph_exec) {  // the captured kernels no longer match
+    (void)hipGraphExecDestroy(p->graph_exec);
+    p->graph_exec = nullptr;
+  }
+}
+
+int dpse_plan_set_tiles(dpse_plan* p, const int32_t* choice) {
+  if (!p || !choice) return DPSE_EINVAL;
+  for (int s = 0; s < DPSE_NUM_TUNED; ++s)
+    if (choice[s] != -1 && !tuned_valid(p, s, choice[s])) return DPSE_EINVAL;
+  for (int s = 0; s < DPSE_NUM_TUNED; ++s) tuned_cfg(p, s) = choice[s];
+  drop_graph(p);
+  return DPSE_OK;
+}
+
+int dpse_plan_autotune(dpse_plan* p, int64_t n, const double* pos, const double* q, int reps,
+                       int32_t* choice, double* ms) {
+  if (!p || !pos || !q || n <= 0 || !p->bound || reps <= 0) return DPSE_EINVAL;
+  if (n > p->max_n) return DPSE_ETOOMANY;
+  const bool timing = p->timing;
+  p->timing = false;
+  int st = solve_impl(p, n, pos, q, nullptr, nullptr, nullptr);  // bins and grids for the stage runs
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (st == DPSE_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = DPSE_EHIP;
+  if (ms)
+    for (int i = 0; i < 8 * DPSE_NUM_TUNED; ++i) ms[i] = -1.0;
+  for (int s = 0; s < DPSE_NUM_TUNED && st == DPSE_OK; ++s) {
+    int best = -1;
+    double tbest = 0.0;
+    for (int i = 0; i < tuned_count(s) && st == DPSE_OK; ++i) {
+      if (!tuned_valid(p, s, i)) continue;
+      tuned_cfg(p, s) = i;
+      hipError_t e = hipSuccess;
+      for (int r = -1; r < reps && e == hipSuccess; ++r) {  // one untimed run first
+        if (r == 0) e = hipEventRecord(e0, p->stream);
+        if (e == hipSuccess) e = launch_tuned(p, s, n);
+      }
+      float t = 0.0f;
+      if (e == hipSuccess) e = hipEventRecord(e1, p->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+      if (e != hipSuccess) {
+        st = DPSE_EHIP;
+        break;
+      }
+      const double tm = (double)t / reps;
+      if (ms) ms[s * 8 + i] = tm;
+      if (best < 0 || tm < tbest) {
+        best = i;
+        tbest = tm;
+      }
+    }
+    tuned_cfg(p, s) = best;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  p->timing = timing;
+  drop_graph(p);
+  if (choice)
+    for (int s = 0; s < DPSE_NUM_TUNED; ++s) choice[s] = tuned_cfg(p, s);
+  if (st != DPSE_OK) return st;
+  return dpse_sync(p);
+}
+
 int dpse_sync(dpse_plan* p) {
   if (!p || !p->bound) return DPSE_EINVAL;
   if (hipStreamSynchronize(p->stream) != hipSuccess) return DPSE_EHIP;

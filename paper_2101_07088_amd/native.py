@@ -91,6 +91,9 @@ def _lib():
                                               ctypes.c_int, ctypes.POINTER(vp)]
         L.dpse_graph_launch.argtypes = [vp, vp]
         L.dpse_graph_destroy.argtypes = [vp]
+        L.dpse_plan_autotune.argtypes = [vp, i64, pd, pd, ctypes.c_int, ctypes.POINTER(i32),
+                                         ctypes.POINTER(ctypes.c_double)]
+        L.dpse_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32)]
         L.dpse_sync.argtypes = [vp]
         L.dpse_plan_destroy.argtypes = [vp]
         L.dpse_debug_copy.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -102,7 +105,8 @@ def _lib():
         for name in ("dpse_derive", "dpse_plan_create", "dpse_plan_info", "dpse_solve", "dpse_solve_batch",
                      "dpse_sync", "dpse_plan_destroy", "dpse_debug_copy", "dpse_set_timing",
                      "dpse_stage_times", "dpse_workspace_size", "dpse_plan_create_unbound", "dpse_plan_bind",
-                     "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy"):
+                     "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy",
+                     "dpse_plan_autotune", "dpse_plan_set_tiles"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -215,6 +219,21 @@ class Plan:
         _check(_lib().dpse_solve_graph(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(),
                                        phi.data_ptr(), force.data_ptr()), "dpse_solve_graph")
         return energy, phi, force
+
+    def autotune(self, pos, q, reps: int = 3):
+        """dpse_plan_autotune: times the launch-shape candidates of spreading,
+        interpolation and the column kernel on these charges and keeps the
+        fastest. Returns (choice[3], {(stage, index): ms})."""
+        ch = (ctypes.c_int32 * 3)()
+        ms = (ctypes.c_double * 24)()
+        _check(_lib().dpse_plan_autotune(self._h, int(q.shape[0]), pos.data_ptr(), q.data_ptr(), int(reps), ch, ms),
+               "dpse_plan_autotune")
+        times = {(s, i): ms[8 * s + i] for s in range(3) for i in range(8) if ms[8 * s + i] > 0}
+        return tuple(ch), times
+
+    def set_tiles(self, choice):
+        ch = (ctypes.c_int32 * 3)(*[int(c) for c in choice])
+        _check(_lib().dpse_plan_set_tiles(self._h, ch), "dpse_plan_set_tiles")
 
     def sync(self) -> int:
         """Waits for the stream; raises DpseError for a device-detected error."""

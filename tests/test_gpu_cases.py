@@ -140,3 +140,37 @@ def test_repeat_solves_agree():
     plan, _, U1, phi1, F1 = run(p, pos, q)
     _, _, U2, phi2, F2 = run(p, pos, q, plan=plan)
     assert rel_rms(F2, F1) < 1e-13 and abs(U2 - U1) < 1e-12 * abs(U1)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_every_tile_shape_and_autotune(precision):
+    """Each applicable spreading/interpolation tile shape gives the default
+    result (up to atomic-order rounding); the autotuner keeps a valid one."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_jump(10, 200, L=32.0)
+    tol = 1e-13 if precision == 0 else 2e-6
+    plan = dp.Plan(p, max_n=len(q), precision=precision)
+    tp = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    U0, phi0, F0 = [t.cpu().numpy() for t in plan.solve(tp, tq)]
+    assert plan.sync_status() == 0
+    choice, times = plan.autotune(tp, tq, reps=2)
+    print(f"[case] autotune prec={precision}: choice {choice}, times {times}", flush=True)
+    assert min(choice) >= 0
+    tried = 0
+    for s in range(3):
+        for i in range(6):
+            ch = [-1, -1, -1]
+            ch[s] = i
+            if (s, i) not in times:
+                with pytest.raises(dp.DpseError):
+                    plan.set_tiles(ch)
+                continue
+            plan.set_tiles(ch)
+            U, phi, F = [t.cpu().numpy() for t in plan.solve(tp, tq)]
+            assert plan.sync_status() == 0
+            assert rel_rms(F, F0) < tol and rel_rms(phi, phi0) < tol, (s, i)
+            tried += 1
+    assert tried >= 8
+    plan.close()

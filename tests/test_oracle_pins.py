@@ -222,6 +222,9 @@ def test_near_field_matches_pair_loop():
                         e = (math.erfc(p.xi * r) / r ** 2 + 2 * p.xi / math.sqrt(math.pi) * math.exp(-(p.xi * r) ** 2) / r) / r
                         ref[t] += st * np.array([G, e * rx, e * ry, e * rz]) / (4 * math.pi * p.eps)
     assert np.abs(out - ref).max() < 1e-13
+    # the sampled-target form gives the same rows
+    tt = np.array([6, 1, 3])
+    assert np.abs(O.near_field(p, d, pos, q, targets=tt) - ref[tt]).max() < 1e-13
 
 
 # --- the whole oracle against the Ewald2D + image-series reference ------------
