@@ -133,7 +133,9 @@ int dpse_plan_create_unbound(const dpse_params* params, int64_t max_n, dpse_plan
  * other memory or another stream; the workspace holds no state between
  * solves except the device status of dpse_sync, which binding clears (with a
  * kernel on `stream`, ordered after the work already queued there). Plans that
- * share a workspace must run on one stream, or the caller orders them.
+ * share a workspace must run on one stream, or the caller orders them; they
+ * share one status word (at the start of the workspace), which dpse_sync on
+ * any of them reports and clears.
  * DPSE_EINVAL for a plan that owns its workspace, a null or misaligned
  * pointer, or too few bytes. */
 int dpse_plan_bind(dpse_plan* plan, void* workspace, int64_t bytes, void* stream);

@@ -35,7 +35,9 @@ constexpr int kThreads = 256;
 constexpr int kColumnKE[] = {2048, 1024, 4096};
 constexpr int kNumColumn = 3;
 constexpr int kMaxMB = 32;    // modes per block: 8 MB chain threads <= kThreads
-constexpr size_t kMaxLds = 160 * 1024;
+// dynamic LDS per block: 160 KB per workgroup less a margin for the static
+// arrays of the kernel (under 3 KB)
+constexpr size_t kMaxLds = 156 * 1024;
 
 template <typename R>
 struct CT;
@@ -504,6 +506,8 @@ void column_as(dpse_plan* p) {
 }
 }  // namespace
 
+bool g_column_ok[kNumColumn] = {true, true, true};
+
 int column_candidates() { return kNumColumn; }
 
 int column_block(int i) { return kColumnKE[i]; }
@@ -512,7 +516,7 @@ int column_block(int i) { return kColumnKE[i]; }
 bool column_valid(const Geom& g, int i) {
   if (i < 0 || i >= kNumColumn) return false;
   const int KE = kColumnKE[i], M = 2 * (g.Nz - 1);
-  return M <= KE && KE / M <= kMaxMB && column_lds(g, KE) <= kMaxLds;
+  return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && column_lds(g, KE) <= kMaxLds;
 }
 
 template <typename R>
@@ -530,15 +534,21 @@ hipError_t launch_column(dpse_plan* p) {
 // Raises the dynamic LDS limit of the column kernels on the current device;
 // called at plan creation so that no attribute call happens inside a solve
 // (which may be captured into a graph).
+// A candidate whose limit cannot be raised is left out of column_valid().
 hipError_t prepare_kernels() {
-  const void* fns[] = {(const void*)k_column<double, 2048>, (const void*)k_column<float, 2048>,
-                       (const void*)k_column<double, 1024>, (const void*)k_column<float, 1024>,
-                       (const void*)k_column<double, 4096>, (const void*)k_column<float, 4096>};
-  for (const void* f : fns) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds);
-    if (e != hipSuccess) return e;
+  const void* fns[kNumColumn][2] = {{(const void*)k_column<double, 2048>, (const void*)k_column<float, 2048>},
+                                    {(const void*)k_column<double, 1024>, (const void*)k_column<float, 1024>},
+                                    {(const void*)k_column<double, 4096>, (const void*)k_column<float, 4096>}};
+  bool any = false;
+  for (int i = 0; i < kNumColumn; ++i) {
+    bool ok = true;
+    for (const void* f : fns[i])
+      ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) == hipSuccess;
+    g_column_ok[i] = ok;
+    any = any || ok;
   }
-  return hipSuccess;
+  (void)hipGetLastError();  // clear a failed attribute call
+  return any ? hipSuccess : hipErrorInvalidValue;
 }
 
 template hipError_t launch_column<double>(dpse_plan*);

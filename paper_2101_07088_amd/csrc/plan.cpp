@@ -165,6 +165,9 @@ size_t carve_workspace(dpse_plan* p, char* base) {
   const size_t max_n = (size_t)p->max_n;
   Carver c{base};
   dpse::Workspace& w = p->w;
+  // the status word first: at the same place for every plan bound to an
+  // arena, whatever its sizes, so that plans sharing the arena share it
+  c.take(&w.status, 4);
   size_t next = 3 * max_n;
   c.take(&w.ext, next); c.take(&w.ext_meta, next); c.take(&w.srt, next); c.take(&w.srt_meta, next);
   c.take(&w.bin_cnt, p->nkeys + 1); c.take(&w.bin_off, p->nkeys + 1); c.take(&w.bin_cur, p->nkeys + 1);
@@ -178,7 +181,7 @@ size_t carve_workspace(dpse_plan* p, char* base) {
   for (char** gp : cgrids) c.take(gp, C * 2 * rs);
   c.take((char**)&w.u4, 4 * G * rs);
   c.take(&w.far4, max_n); c.take(&w.near4, max_n);
-  c.take(&w.scal, 16); c.take(&w.partials, 4 * (size_t)p->npartials); c.take(&w.status, 4);
+  c.take(&w.scal, 16); c.take(&w.partials, 4 * (size_t)p->npartials);
   return (c.off + 255) & ~size_t(255);
 }
 

@@ -158,7 +158,8 @@ def test_batch_matches_single_solves(precision, use_graph):
         torch.cuda.synchronize()
         br.run()
         torch.cuda.synchronize()
-        assert all(s == 0 for s in br.statuses())
+        st = br.statuses()
+        assert all(s == 0 for s in st), st
         for k, (p, _, q) in enumerate(systems):
             pl = dp.Plan(p, max_n=len(q), precision=precision)
             U, phi, F = pl.solve(dev(cur[k]), dev(q))
