@@ -200,13 +200,14 @@ int dpse_graph_destroy(dpse_graph* graph);
  * HIP events on the plan's stream, keeps the fastest in the plan, writes the
  * chosen candidate of stage s (0 spreading, 1 interpolation, 2 column) to
  * choice[s] if choice is not NULL (DPSE_NUM_TUNED entries), and the mean
- * milliseconds of candidate i of stage s to ms[8 s + i] (-1 where a candidate
- * does not apply) if ms is not NULL (8 * DPSE_NUM_TUNED entries). Synchronous;
+ * milliseconds of candidate i of stage s to ms[DPSE_MAX_CANDIDATES s + i] (-1
+ * where a candidate does not apply) if ms is not NULL (DPSE_MAX_CANDIDATES *
+ * DPSE_NUM_TUNED entries). Synchronous;
  * returns the device status of the solve like dpse_sync. dpse_plan_set_tiles
  * applies stored choices (-1 = the default rule) to a plan of the same grid;
  * DPSE_EINVAL if a choice does not apply. Results depend on the choice only
  * through rounding (the order of floating-point sums). */
-enum { DPSE_NUM_TUNED = 3 };
+enum { DPSE_NUM_TUNED = 3, DPSE_MAX_CANDIDATES = 16 };
 int dpse_plan_autotune(dpse_plan* plan, int64_t n, const double* pos, const double* q, int reps,
                        int32_t* choice, double* ms);
 int dpse_plan_set_tiles(dpse_plan* plan, const int32_t* choice);

@@ -715,7 +715,7 @@ int dpse_plan_autotune(dpse_plan* p, int64_t n, const double* pos, const double*
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (st == DPSE_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = DPSE_EHIP;
   if (ms)
-    for (int i = 0; i < 8 * DPSE_NUM_TUNED; ++i) ms[i] = -1.0;
+    for (int i = 0; i < DPSE_MAX_CANDIDATES * DPSE_NUM_TUNED; ++i) ms[i] = -1.0;
   for (int s = 0; s < DPSE_NUM_TUNED && st == DPSE_OK; ++s) {
     int best = -1;
     double tbest = 0.0;
@@ -736,7 +736,7 @@ int dpse_plan_autotune(dpse_plan* p, int64_t n, const double* pos, const double*
         break;
       }
       const double tm = (double)t / reps;
-      if (ms) ms[s * 8 + i] = tm;
+      if (ms) ms[s * DPSE_MAX_CANDIDATES + i] = tm;
       if (best < 0 || tm < tbest) {
         best = i;
         tbest = tm;

@@ -225,10 +225,10 @@ class Plan:
         interpolation and the column kernel on these charges and keeps the
         fastest. Returns (choice[3], {(stage, index): ms})."""
         ch = (ctypes.c_int32 * 3)()
-        ms = (ctypes.c_double * 24)()
+        ms = (ctypes.c_double * (3 * 16))()
         _check(_lib().dpse_plan_autotune(self._h, int(q.shape[0]), pos.data_ptr(), q.data_ptr(), int(reps), ch, ms),
                "dpse_plan_autotune")
-        times = {(s, i): ms[8 * s + i] for s in range(3) for i in range(8) if ms[8 * s + i] > 0}
+        times = {(s, i): ms[16 * s + i] for s in range(3) for i in range(16) if ms[16 * s + i] > 0}
         return tuple(ch), times
 
     def set_tiles(self, choice):

@@ -160,7 +160,7 @@ def test_every_tile_shape_and_autotune(precision):
     assert min(choice) >= 0
     tried = 0
     for s in range(3):
-        for i in range(6):
+        for i in range(16):
             ch = [-1, -1, -1]
             ch[s] = i
             if (s, i) not in times:
