@@ -100,8 +100,10 @@ typedef struct {
   double xi_e;         /* (4 g_w^2 + xi^-2)^(-1/2)                                */
   int32_t support;     /* n_g                                                      */
   int32_t n_modes;     /* Ny (Nx/2 + 1) transverse modes                          */
-  int64_t workspace_bytes; /* device memory owned by the plan (0 from dpse_derive) */
+  int64_t workspace_bytes; /* device memory of one solve's workspace (0 from dpse_derive) */
   int64_t max_n;       /* charges per solve the plan accepts (0 from dpse_derive)  */
+  int64_t table_bytes; /* device memory of the plan's resident tables, including the
+                          factorised per-mode solver operators (0 from dpse_derive) */
 } dpse_info;
 
 typedef struct dpse_plan dpse_plan;
@@ -113,7 +115,9 @@ int dpse_derive(const dpse_params* params, dpse_info* info);
 /* Creates a plan for up to max_n charges per solve on the HIP stream `stream`
  * (a hipStream_t; NULL = the null stream) of the current device. Allocates the
  * workspace and uploads the plan tables (nodes, quadrature weights, wave
- * numbers). *out receives the plan. */
+ * numbers) and factorises the per-mode boundary value operators of App. A
+ * (their elimination multipliers depend on |k| only; a kernel on a private
+ * stream, waited for). *out receives the plan. */
 int dpse_plan_create(const dpse_params* params, int64_t max_n, void* stream, dpse_plan** out);
 
 /* Device bytes of the workspace of one solve of up to max_n charges with

@@ -110,6 +110,9 @@ struct Tables {
   double* ctab = nullptr;
   float2* twx_f = nullptr;
   float2* twy_f = nullptr;
+  // factorised per-mode chains: elimination multipliers, [Nz][Ny (Nx/2+1)]
+  // (chain-major rows, see k_pivots in k_column.hip)
+  double* cpiv = nullptr;
 };
 
 }  // namespace dpse
@@ -167,6 +170,8 @@ void tile_shape(int stage, int i, int* T, int* P);
 bool tile_valid(const Geom& g, int stage, int i, bool fp64);
 // Column-kernel block sizes (complex LDS elements per buffer).
 int column_candidates();
+// Plan-time factorisation of the per-mode chains into Tables::cpiv.
+hipError_t launch_pivots(dpse_plan* p, hipStream_t s);
 int column_block(int i);
 bool column_valid(const Geom& g, int i);
 

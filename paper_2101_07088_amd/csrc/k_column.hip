@@ -63,6 +63,47 @@ __device__ inline double rcp_refined(double d) {
   return fma(r, e, r);
 }
 
+// |k|, kappa = |k| R and whether the harmonic correction applies, of mode mi
+// (mode index ky * (Nx/2+1) + kx of the half spectrum).
+__device__ inline void mode_wave(const Geom& g, int mi, double& kk, int& keep) {
+  const int kyi = mi / g.nkx, kxi = mi % g.nkx;
+  const int nx = kxi == g.Nx / 2 ? -(g.Nx / 2) : kxi;
+  const int ny = kyi < g.Ny / 2 ? kyi : kyi - g.Ny;
+  const double kx = 2.0 * kPi * nx / g.Lx, ky = 2.0 * kPi * ny / g.Ly;
+  kk = sqrt(kx * kx + ky * ky);
+  const long long lhs = 4LL * ((long long)nx * nx * g.Ny * g.Ny + (long long)ny * ny * g.Nx * g.Nx);
+  const long long rhs = (long long)g.Nx * g.Ny * (long long)g.Nx * g.Ny;
+  keep = (lhs <= rhs) ? 1 : 0;
+  if ((g.flags & DPSE_KMAX_GT) && !(kk <= 4.2 / g.g_t)) keep = 0;
+}
+
+// Plan-time factorisation of the per-mode chains (they depend on kappa only):
+// the elimination multipliers cp_r of the even (rows n = 2r) and odd (n =
+// 2r+1) chains, stored chain-major, cpiv[(par * ceil(N/2) + r) * nmodes + mode].
+__global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __restrict__ ctab,
+                                                     double* __restrict__ cpiv) {
+  const int nmodes = g.Ny * g.nkx, N = g.Nz;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= 2 * nmodes) return;
+  const int mi = t % nmodes, par = t / nmodes;
+  double kk;
+  int keep;
+  mode_wave(g, mi, kk, keep);
+  const double kap = kk * g.zR, kap2 = kap * kap;
+  const double* ca = ctab;
+  const double* cb = ctab + N;
+  const double* cc = ctab + 2 * N;
+  const int half0 = (N + 1) / 2;
+  double cp = 0.0;
+  int r = 0;
+  for (int n = par; n < N; n += 2, ++r) {
+    const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
+    const double inv = rcp_refined(fma(-sub, cp, dia));
+    cp = sup * inv;
+    cpiv[(size_t)(par * half0 + r) * nmodes + mi] = cp;
+  }
+}
+
 template <typename R, int KE>
 __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                      const typename CT<R>::T* __restrict__ fx_o,
@@ -70,7 +111,8 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
                                                      typename CT<R>::T* __restrict__ psiz,
                                                      const double* __restrict__ zn,
                                                      const double* __restrict__ ctab,
-                                                     const double2* __restrict__ twz, double* scal) {
+                                                     const double2* __restrict__ twz,
+                                                     const double* __restrict__ cpiv, double* scal) {
   using C = typename CT<R>::T;
   extern __shared__ double2 smem2[];
   constexpr int kElems = KE;
@@ -105,40 +147,58 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     int mi = m0 + tid;
     double kk = 0.0;
     int keep = 0;
-    if (mi < nmodes) {
-      int kyi = mi / g.nkx, kxi = mi % g.nkx;
-      int nx = kxi == g.Nx / 2 ? -(g.Nx / 2) : kxi;
-      int ny = kyi < g.Ny / 2 ? kyi : kyi - g.Ny;
-      double kx = 2.0 * kPi * nx / g.Lx, ky = 2.0 * kPi * ny / g.Ly;
-      kk = sqrt(kx * kx + ky * ky);
-      long long lhs = 4LL * ((long long)nx * nx * g.Ny * g.Ny + (long long)ny * ny * g.Nx * g.Nx);
-      long long rhs = (long long)g.Nx * g.Ny * (long long)g.Nx * g.Ny;
-      keep = (lhs <= rhs) ? 1 : 0;
-      if ((g.flags & DPSE_KMAX_GT) && !(kk <= 4.2 / g.g_t)) keep = 0;
-    }
+    if (mi < nmodes) mode_wave(g, mi, kk, keep);
     s_k[tid] = kk;
     s_kap[tid] = kk * Rz;
     s_keep[tid] = keep;
   }
 
+  // the plan-time chain multipliers of the block's modes (N MB values), and
+  // the functional weights W when they fit the spare storage, are fetched
+  // into registers now and put in LDS once the buffers they share are free
+  constexpr int kCp = KE / (2 * kThreads) + 1;  // >= N MB / kThreads
+  constexpr int kWr = 12;                       // W staged when 10 (N+2) <= kWr kThreads
+  double cpr[kCp], wr[kWr];
+#pragma unroll
+  for (int q = 0; q < kCp; ++q) {
+    const int t = tid + q * kThreads, row = t >> logMB, m = t & (MB - 1);
+    cpr[q] = (row < N && m0 + m < nmodes) ? cpiv[(size_t)row * nmodes + m0 + m] : 0.0;
+  }
+  const bool w_lds = kNumFun * NU <= kWr * kThreads && kNumFun * NU <= 2 * (N - 2) * MB;
+  if (w_lds) {
+#pragma unroll
+    for (int q = 0; q < kWr; ++q) {
+      const int t = tid + q * kThreads;
+      wr[q] = t < kNumFun * NU ? W[t] : 0.0;
+    }
+  }
+
   for (int i = tid; i < M / 2; i += kThreads) tw[i] = twz[i];
-  // 1. even extension of the node values in bit-reversed order, then FFT
-  for (int t = tid; t < M * MB; t += kThreads) {
-    int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
-    int c = j < N ? j : M - j;
-    double2 vo = make_double2(0.0, 0.0), vi = make_double2(0.0, 0.0);
-    if (mi < nmodes) {
-      size_t o = (size_t)c * nmodes + mi;
-      C a = fx_i[o];
-      vi = make_double2((double)a.x, (double)a.y);
-      if (c < g.top_end || c >= g.bot_begin) {
-        C b = fx_o[o];
-        vo = make_double2((double)b.x, (double)b.y);
+  // 1. even extension of the node values in bit-reversed order, then FFT;
+  //    all global loads of the thread are issued before the LDS stores
+  {
+    constexpr int kPer = KE / kThreads;  // M * MB == KE
+    C va[kPer], vb[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * kThreads;
+      const int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
+      const int c = j < N ? j : M - j;
+      va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
+      if (mi < nmodes) {
+        const size_t o = (size_t)c * nmodes + mi;
+        va[q] = fx_i[o];
+        if (c < g.top_end || c >= g.bot_begin) vb[q] = fx_o[o];
       }
     }
-    int pos = bitrev(j, logM) * MB + m;
-    A[pos] = vo;
-    B[pos] = vi;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * kThreads;
+      const int j = t >> logMB, m = t & (MB - 1);
+      const int pos = bitrev(j, logM) * MB + m;
+      A[pos] = make_double2((double)vb[q].x, (double)vb[q].y);
+      B[pos] = make_double2((double)va[q].x, (double)va[q].y);
+    }
   }
   __syncthreads();
   fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(A, logM, logMB, 1, MB, tw, false, tid);
@@ -152,6 +212,12 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   };
   const int half0 = (N + 1) / 2;  // rows of the even chain
   double* s_fun = lco + kCtabRows * N;  // [MB][10][6]
+#pragma unroll
+  for (int q = 0; q < kCp; ++q) {
+    const int t = tid + q * kThreads, row = t >> logMB, m = t & (MB - 1);
+    if (row < N) spare(spA, m, row) = cpr[q];
+  }
+  __syncthreads();
   // homogeneous y'' of chain parity n&1 at index n
   auto hval = [&](int m, int n) -> double { return spare(spB, m, (n & 1) * half0 + (n >> 1)); };
 
@@ -172,39 +238,37 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);  // X[n * 2 MB]
     const double kap2 = s_kap[m] * s_kap[m];
     const int L = par == 0 ? (N + 1) / 2 : N / 2;
-    double cp = 0.0, d = 0.0, dh = 0.0;
+    double d = 0.0, dh = 0.0;
     for (int r0 = 0; r0 < L; r0 += kSweep) {
-      double xv[kSweep], av[kSweep], bv[kSweep], cv[kSweep], gv[kSweep];
+      double xv[kSweep], av[kSweep], bv[kSweep], gv[kSweep], pv[kSweep];
 #pragma unroll
       for (int u = 0; u < kSweep; ++u) {
-        const int n = par + 2 * min(r0 + u, L - 1);
+        const int r = min(r0 + u, L - 1), n = par + 2 * r;
         xv[u] = X[n * 2 * MB];
         av[u] = ca[n];
         bv[u] = cb[n];
-        cv[u] = cc[n];
         gv[u] = gsc[n];
+        pv[u] = r > 0 ? spare(spA, m, par * half0 + r - 1) : 0.0;  // multiplier of the row above
       }
-      double dv[kSweep], cpv[kSweep], dhv[kSweep];
+      // the pivots do not depend on each other any more: only d and dh recur
+      double inv[kSweep];
+#pragma unroll
+      for (int u = 0; u < kSweep; ++u) inv[u] = rcp_refined(fma(kap2 * av[u], pv[u], fma(kap2, bv[u], 1.0)));
+      double dv[kSweep], dhv[kSweep];
 #pragma unroll
       for (int u = 0; u < kSweep; ++u) {
-        const double sub = -kap2 * av[u], dia = fma(kap2, bv[u], 1.0), sup = -kap2 * cv[u];
-        const double inv = rcp_refined(fma(-sub, cp, dia));
-        d = (gv[u] * xv[u] - sub * d) * inv;
-        dh = ((r0 + u == 0 ? kap2 : 0.0) - sub * dh) * inv;
-        cp = sup * inv;
+        const double sub = -kap2 * av[u];
+        d = (gv[u] * xv[u] - sub * d) * inv[u];
+        dh = ((r0 + u == 0 ? kap2 : 0.0) - sub * dh) * inv[u];
         dv[u] = d;
         dhv[u] = dh;
-        cpv[u] = cp;
       }
 #pragma unroll
       for (int u = 0; u < kSweep; ++u) {
         const int r = r0 + u;
         if (r < L) {
           X[(par + 2 * r) * 2 * MB] = dv[u];
-          if (k == 0) {
-            spare(spB, m, par * half0 + r) = dhv[u];
-            spare(spA, m, par * half0 + r) = cpv[u];
-          }
+          if (k == 0) spare(spB, m, par * half0 + r) = dhv[u];
         }
       }
     }
@@ -255,34 +319,48 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   //    s_fun[(m * 10 + f) * 6 + v].
   //    Two lanes (adjacent, same wave) share a dot product: each sums half
   //    of the indices and a lane exchange adds the halves.
-  for (int t = tid; t < MB * 20; t += kThreads) {
-    const int pr = t >> 1, part = t & 1;
-    const int m = pr / 10, f = pr - 10 * m;
-    const double* Wf = W + f * NU;
-    const int jh = (N + 1) / 2, ja = part ? jh : 0, jb = part ? N : jh;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = part ? 0.0 : Wf[N], a5 = part ? 0.0 : Wf[N + 1];
-#pragma unroll 4
-    for (int j = ja; j < jb; ++j) {
-      const double w = Wf[j];
-      const double2 xi = B[j * MB + m], xo = A[j * MB + m];
-      const double hv = hval(m, j);
-      a0 = fma(w, xi.x, a0);
-      a1 = fma(w, xi.y, a1);
-      a2 = fma(w, xo.x, a2);
-      a3 = fma(w, xo.y, a3);
-      if (j & 1) a5 = fma(w, hv, a5); else a4 = fma(w, hv, a4);
-    }
-    a0 += __shfl_xor(a0, 1, 64);
-    a1 += __shfl_xor(a1, 1, 64);
-    a2 += __shfl_xor(a2, 1, 64);
-    a3 += __shfl_xor(a3, 1, 64);
-    a4 += __shfl_xor(a4, 1, 64);
-    a5 += __shfl_xor(a5, 1, 64);
-    if (part == 0) {
-      double* o = s_fun + (m * 10 + f) * 6;
-      o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
+  //    The weights come from LDS (the multipliers' storage, free after the
+  //    back substitution) when they fit there, else from global memory.
+  if (w_lds) {
+#pragma unroll
+    for (int q = 0; q < kWr; ++q) {
+      const int t = tid + q * kThreads;
+      if (t < kNumFun * NU) spA[t] = wr[q];
     }
   }
+  __syncthreads();
+  auto functionals = [&](const double* Wsrc) {
+    for (int t = tid; t < MB * 20; t += kThreads) {
+      const int pr = t >> 1, part = t & 1;
+      const int m = pr / 10, f = pr - 10 * m;
+      const double* Wf = Wsrc + f * NU;
+      const int jh = (N + 1) / 2, ja = part ? jh : 0, jb = part ? N : jh;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = part ? 0.0 : Wf[N], a5 = part ? 0.0 : Wf[N + 1];
+#pragma unroll 4
+      for (int j = ja; j < jb; ++j) {
+        const double w = Wf[j];
+        const double2 xi = B[j * MB + m], xo = A[j * MB + m];
+        const double hv = hval(m, j);
+        a0 = fma(w, xi.x, a0);
+        a1 = fma(w, xi.y, a1);
+        a2 = fma(w, xo.x, a2);
+        a3 = fma(w, xo.y, a3);
+        if (j & 1) a5 = fma(w, hv, a5); else a4 = fma(w, hv, a4);
+      }
+      a0 += __shfl_xor(a0, 1, 64);
+      a1 += __shfl_xor(a1, 1, 64);
+      a2 += __shfl_xor(a2, 1, 64);
+      a3 += __shfl_xor(a3, 1, 64);
+      a4 += __shfl_xor(a4, 1, 64);
+      a5 += __shfl_xor(a5, 1, 64);
+      if (part == 0) {
+        double* o = s_fun + (m * 10 + f) * 6;
+        o[0] = a0; o[1] = a1; o[2] = a2; o[3] = a3; o[4] = a4; o[5] = a5;
+      }
+    }
+  };
+  if (w_lds) functionals(spA);
+  else functionals(W);
   __syncthreads();
 
   // 4. per mode: free constants, wall values, mismatches, harmonic correction, k = 0
@@ -502,13 +580,21 @@ void column_as(dpse_plan* p) {
   const int nb = (nmodes + MB - 1) / MB;
   hipLaunchKernelGGL((k_column<R, KE>), dim3(nb), dim3(kThreads), column_lds(g, KE), p->stream, g,
                      (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
-                     (const double*)p->t.ctab, (const double2*)p->t.twz, p->w.scal);
+                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal);
 }
 }  // namespace
 
 bool g_column_ok[kNumColumn] = {true, true, true};
 
 int column_candidates() { return kNumColumn; }
+
+hipError_t launch_pivots(dpse_plan* p, hipStream_t s) {
+  const Geom& g = p->g;
+  const int nt = 2 * g.Ny * g.nkx;
+  hipLaunchKernelGGL(k_pivots, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
+                     (const double*)p->t.ctab, p->t.cpiv);
+  return hipGetLastError();
+}
 
 int column_block(int i) { return kColumnKE[i]; }
 

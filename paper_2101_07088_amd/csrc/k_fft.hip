@@ -16,7 +16,11 @@ namespace dpse {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kElems = 2048;  // complex elements per LDS FFT buffer
+constexpr int kElems = 2048;  // complex elements per LDS FFT buffer (x passes)
+// y passes: 32 KB of LDS per buffer, so that a block spans KB = kYElems / Ny
+// consecutive kx columns and its global rows are 128 bytes when Ny <= 256
+template <typename R>
+constexpr int kYElems = sizeof(R) == 8 ? 2048 : 4096;
 
 template <typename R>
 struct CT;
@@ -73,31 +77,41 @@ template <typename R>
 __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* data, int p0,
                                                     const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
-  __shared__ C buf[kElems];
+  constexpr int KE = kYElems<R>;
+  constexpr int kPer = KE / kThreads;
+  __shared__ C buf[KE];
   __shared__ C tw[512];
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
-  const int KB = kElems / Ny;
+  const int KB = KE / Ny, logKB = ilog2(KB);
   const int nblk = (nkx + KB - 1) / KB;
   const int plane = p0 + blockIdx.x / nblk;
   const int kb = (blockIdx.x % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   C* base = data + (size_t)plane * Ny * nkx;
-  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
-    int ky = i / KB, kl = i % KB;
-    C v;
-    v.x = 0; v.y = 0;
-    if (kb + kl < nkx) v = base[(size_t)ky * nkx + kb + kl];
-    buf[bitrev(ky, logN) * KB + kl] = v;
+  C v[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+    v[q].x = 0; v[q].y = 0;
+    if (kb + kl < nkx) v[q] = base[(size_t)ky * nkx + kb + kl];
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+    buf[bitrev(ky, logN) * KB + kl] = v[q];
   }
   __syncthreads();
-  fft_lds_r22<C, true, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(KB), 1, KB, tw, false, threadIdx.x);
-  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
-    int ky = i / KB, kl = i % KB;
+  fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf, logN, logKB, 1, KB, tw, false, threadIdx.x);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
     if (kb + kl < nkx) base[(size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
   }
 }
 
-// Inverse C2C along y: (Psi, Psi_z) -> (P0 = Psi, PY = -i ky Psi, PZ = Psi_z), y-transformed.
+// Inverse C2C along y: (Psi, Psi_z) -> (P0 = Psi, PY = -i ky Psi, PZ = Psi_z),
+// y-transformed. Psi is read once into registers for the first two fields,
+// then Psi_z for the third; the fields take turns in one LDS buffer.
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R>::T* __restrict__ psi,
                                                      const typename CT<R>::T* __restrict__ psiz,
@@ -105,49 +119,52 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
                                                      typename CT<R>::T* pz,
                                                      const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
-  constexpr int E3 = kElems / 2;  // per field
-  __shared__ C buf[3 * E3];
+  constexpr int KE = kYElems<R>;
+  constexpr int kPer = KE / kThreads;
+  __shared__ C buf[KE];
   __shared__ C tw[512];
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
-  const int KB = max(1, E3 / Ny);
+  const int KB = KE / Ny, logKB = ilog2(KB);
   const int nblk = (nkx + KB - 1) / KB;
   const int plane = blockIdx.x / nblk;
   const int kb = (blockIdx.x % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   const size_t off = (size_t)plane * Ny * nkx;
+  C a[kPer];
   const double kyf = 2.0 * kPi / g.Ly;
-  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
-    int ky = i / KB, kl = i % KB;
-    C a, c;
-    a.x = 0; a.y = 0; c.x = 0; c.y = 0;
-    if (kb + kl < nkx) {
-      a = psi[off + (size_t)ky * nkx + kb + kl];
-      c = psiz[off + (size_t)ky * nkx + kb + kl];
+#pragma nounroll
+  for (int f = 0; f < 3; ++f) {
+    if (f != 1) {
+      const C* src = f == 0 ? psi : psiz;
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+        a[q].x = 0; a[q].y = 0;
+        if (kb + kl < nkx) a[q] = src[off + (size_t)ky * nkx + kb + kl];
+      }
     }
-    int ny = ky < Ny / 2 ? ky : ky - Ny;
-    R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
-    C b;  // -i ky a
-    b.x = kyv * a.y;
-    b.y = -kyv * a.x;
-    int pos = bitrev(ky, logN) * KB + kl;
-    buf[pos] = a;
-    buf[E3 + pos] = b;
-    buf[2 * E3 + pos] = c;
-  }
-  __syncthreads();
-  // the three fields are 3 KB sequences laid out with the same element stride
-  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
-  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf + E3, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
-  fft_lds_r22<C, true, E3 / 4 / kThreads, kThreads>(buf + 2 * E3, logN, ilog2(KB), 1, KB, tw, true, threadIdx.x);
-  for (int i = threadIdx.x; i < Ny * KB; i += kThreads) {
-    int ky = i / KB, kl = i % KB;
-    if (kb + kl < nkx) {
-      size_t o = off + (size_t)ky * nkx + kb + kl;
-      int pos = ky * KB + kl;
-      p0[o] = buf[pos];
-      py[o] = buf[E3 + pos];
-      pz[o] = buf[2 * E3 + pos];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+      C v = a[q];
+      if (f == 1) {  // -i ky Psi
+        const int ny = ky < Ny / 2 ? ky : ky - Ny;
+        const R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
+        const C t = v;
+        v.x = kyv * t.y;
+        v.y = -kyv * t.x;
+      }
+      buf[bitrev(ky, logN) * KB + kl] = v;
     }
+    __syncthreads();
+    fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf, logN, logKB, 1, KB, tw, true, threadIdx.x);
+    C* dst = f == 0 ? p0 : (f == 1 ? py : pz);
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+      if (kb + kl < nkx) dst[off + (size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
+    }
+    __syncthreads();
   }
 }
 
@@ -232,7 +249,7 @@ template <typename R>
 void launch_y_planes(dpse_plan* p, typename CT<R>::T* data, int plane_a, int plane_b) {
   const Geom& g = p->g;
   if (plane_b <= plane_a) return;
-  int KB = kElems / g.Ny;
+  int KB = kYElems<R> / g.Ny;
   int nblk = (g.nkx + KB - 1) / KB;
   hipLaunchKernelGGL(k_fft_y<R>, dim3(nblk * (plane_b - plane_a)), dim3(kThreads), 0, p->stream, g, data,
                      plane_a, twy<R>(p));
@@ -262,7 +279,7 @@ template <typename R>
 hipError_t launch_fft_inverse(dpse_plan* p) {
   using C = typename CT<R>::T;
   const Geom& g = p->g;
-  int KB = std::max(1, (kElems / 2) / g.Ny);
+  int KB = kYElems<R> / g.Ny;
   int nblk = (g.nkx + KB - 1) / KB;
   hipLaunchKernelGGL(k_ifft_y<R>, dim3(nblk * g.Nz), dim3(kThreads), 0, p->stream, g, (const C*)p->w.psi,
                      (const C*)p->w.psiz, (C*)p->w.p0, (C*)p->w.py, (C*)p->w.pz, twy<R>(p));

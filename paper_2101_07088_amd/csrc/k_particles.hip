@@ -283,13 +283,23 @@ __global__ void __launch_bounds__(kThreads) k_near_origin(Geom g, int64_t n, con
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_gauge_final(Geom g, int nb, const double* partials, double* scal) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += partials[i];
-  double near0 = s / (4.0 * kPi * g.eps);
-  scal[5] = near0;
-  scal[2] = (g.flags & DPSE_GAUGE_NONE) ? 0.0 : -(scal[4] + near0);
+// One wave: the near part at the origin from nb block partials, the far part
+// from the per-node partials far_part[0 .. Nz), then the gauge constant.
+__global__ void k_gauge_final(Geom g, int nb, const double* partials, const double* far_part, double* scal) {
+  const int lane = threadIdx.x;
+  double sn = 0.0, sf = 0.0;
+  for (int i = lane; i < nb; i += 64) sn += partials[i];
+  for (int i = lane; i < g.Nz; i += 64) sf += far_part[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    sn += __shfl_down(sn, o, 64);
+    sf += __shfl_down(sf, o, 64);
+  }
+  if (lane == 0) {
+    const double near0 = sn / (4.0 * kPi * g.eps);
+    scal[4] = sf;
+    scal[5] = near0;
+    scal[2] = (g.flags & DPSE_GAUGE_NONE) ? 0.0 : -(sf + near0);
+  }
 }
 
 // phibar = far + near + B_i - q * 2 xi_e / (4 pi eps sqrt(pi)); F = q (E_far + E_near).
@@ -393,7 +403,7 @@ hipError_t launch_gauge_near(dpse_plan* p, int64_t n) {
   hipLaunchKernelGGL(k_near_origin, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.ext,
                      p->w.partials);
   hipLaunchKernelGGL(k_gauge_final, dim3(1), dim3(64), 0, p->stream, p->g, nb, (const double*)p->w.partials,
-                     p->w.scal);
+                     (const double*)(p->w.partials + 2 * p->npartials), p->w.scal);
   return hipGetLastError();
 }
 

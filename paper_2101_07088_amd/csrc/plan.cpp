@@ -194,6 +194,7 @@ size_t carve_tables(dpse_plan* p, char* base) {
   c.take(&t.twx, g.Nx / 2); c.take(&t.twy, g.Ny / 2); c.take(&t.twz, g.Nz - 1);
   c.take(&t.twx_f, g.Nx / 2); c.take(&t.twy_f, g.Ny / 2);
   c.take(&t.ctab, dpse::kCtabRows * g.Nz + dpse::kNumFun * (g.Nz + 2));
+  c.take(&t.cpiv, (size_t)g.Nz * g.Ny * g.nkx);
   return c.off;
 }
 
@@ -302,6 +303,7 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
     p->owns_workspace = true;
   }
   p->info.workspace_bytes = (int64_t)wbytes;
+  p->info.table_bytes = (int64_t)tbytes;
   p->info.max_n = max_n;
 
   // plan tables
@@ -394,6 +396,15 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
   int zero4[4] = {0, 0, 0, 0};
   if (p->bound) H2D(w.status, zero4, sizeof(zero4));
   if (e == hipSuccess) e = dpse::prepare_kernels();
+  // factorise the per-mode chains once (they depend on the plan only), on a
+  // private stream so that work already queued on other streams is not waited for
+  if (e == hipSuccess) {
+    hipStream_t ps = nullptr;
+    e = hipStreamCreateWithFlags(&ps, hipStreamNonBlocking);
+    if (e == hipSuccess) e = dpse::launch_pivots(p, ps);
+    if (e == hipSuccess) e = hipStreamSynchronize(ps);
+    if (ps) (void)hipStreamDestroy(ps);
+  }
   if (e != hipSuccess) {
     free_all(p);
     delete p;

@@ -54,7 +54,7 @@ class _Info(ctypes.Structure):
                 ("n_sigma", ctypes.c_double), ("z_lo", ctypes.c_double), ("z_hi", ctypes.c_double),
                 ("r_cut", ctypes.c_double), ("xi_e", ctypes.c_double), ("support", ctypes.c_int32),
                 ("n_modes", ctypes.c_int32), ("workspace_bytes", ctypes.c_int64),
-                ("max_n", ctypes.c_int64)]
+                ("max_n", ctypes.c_int64), ("table_bytes", ctypes.c_int64)]
 
 
 _LIB = None
