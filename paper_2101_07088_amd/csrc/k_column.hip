@@ -207,9 +207,10 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   // spare storage beyond index N of each buffer (N-2 complex = 2N-4 doubles per mode)
   double* spA = reinterpret_cast<double*>(A + N * MB);  // chain pivots
   double* spB = reinterpret_cast<double*>(B + N * MB);  // homogeneous solutions
-  auto spare = [&](double* base, int m, int idx) -> double& {
-    return base[(idx >> 1) * 2 * MB + 2 * m + (idx & 1)];
-  };
+  // per mode, a row of cst doubles: index par * ceil(N/2) + r for row r of
+  // the parity-par chain (fits: MB (N + 8) <= 2 (N - 2) MB for N >= 12)
+  const int cst = N + 8;
+  auto spare = [&](double* base, int m, int idx) -> double& { return base[m * cst + idx]; };
   const int half0 = (N + 1) / 2;  // rows of the even chain
   double* s_fun = lco + kCtabRows * N;  // [MB][10][6]
 #pragma unroll
@@ -235,42 +236,59 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     const int k = tid >> (logMB + 1);          // right-hand side: 0 Re i, 1 Im i, 2 Re o, 3 Im o
     const int cm = tid & (2 * MB - 1);
     const int m = cm & (MB - 1), par = cm >> logMB;
-    double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);  // X[n * 2 MB]
+    // row r of the chain: X at Xp[r * s4], coefficients at cp0[2 r], multiplier at crow[r]
+    double* Xp = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1) + par * 2 * MB;
+    const int s4 = 4 * MB;
+    const double* ap = ca + par;
+    const double* bp = cb + par;
+    const double* gp = gsc + par;
+    const double* crow = spA + m * cst + par * half0;
+    double* hrow = spB + m * cst + par * half0;
     const double kap2 = s_kap[m] * s_kap[m];
     const int L = par == 0 ? (N + 1) / 2 : N / 2;
     double d = 0.0, dh = 0.0;
-    for (int r0 = 0; r0 < L; r0 += kSweep) {
+    // forward: d_r = (g_r x_r - sub_r d_{r-1}) / (dia_r - sub_r cp_{r-1}); the
+    // pivots no longer recur (cp comes from the plan), only d and dh do
+    auto fwd = [&](int r, double xv, double av, double bv, double gv, double pv, double& dv, double& dhv) {
+      const double inv = rcp_refined(fma(kap2 * av, pv, fma(kap2, bv, 1.0)));
+      const double sub = -kap2 * av;
+      d = (gv * xv - sub * d) * inv;
+      dh = ((r == 0 ? kap2 : 0.0) - sub * dh) * inv;
+      dv = d;
+      dhv = dh;
+    };
+    const int Lfull = L & ~(kSweep - 1);
+    for (int r0 = 0; r0 < Lfull; r0 += kSweep) {
+      double* Xr = Xp + r0 * s4;
+      const double* ar = ap + 2 * r0;
+      const double* br = bp + 2 * r0;
+      const double* gr = gp + 2 * r0;
+      const double* cr = crow + r0 - 1;  // in LDS for r0 = 0 too (the value is not used)
       double xv[kSweep], av[kSweep], bv[kSweep], gv[kSweep], pv[kSweep];
 #pragma unroll
       for (int u = 0; u < kSweep; ++u) {
-        const int r = min(r0 + u, L - 1), n = par + 2 * r;
-        xv[u] = X[n * 2 * MB];
-        av[u] = ca[n];
-        bv[u] = cb[n];
-        gv[u] = gsc[n];
-        pv[u] = r > 0 ? spare(spA, m, par * half0 + r - 1) : 0.0;  // multiplier of the row above
+        xv[u] = Xr[u * s4];
+        av[u] = ar[2 * u];
+        bv[u] = br[2 * u];
+        gv[u] = gr[2 * u];
+        pv[u] = cr[u];
       }
-      // the pivots do not depend on each other any more: only d and dh recur
-      double inv[kSweep];
-#pragma unroll
-      for (int u = 0; u < kSweep; ++u) inv[u] = rcp_refined(fma(kap2 * av[u], pv[u], fma(kap2, bv[u], 1.0)));
+      if (r0 == 0) pv[0] = 0.0;
       double dv[kSweep], dhv[kSweep];
 #pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
-        const double sub = -kap2 * av[u];
-        d = (gv[u] * xv[u] - sub * d) * inv[u];
-        dh = ((r0 + u == 0 ? kap2 : 0.0) - sub * dh) * inv[u];
-        dv[u] = d;
-        dhv[u] = dh;
-      }
+      for (int u = 0; u < kSweep; ++u) fwd(r0 + u, xv[u], av[u], bv[u], gv[u], pv[u], dv[u], dhv[u]);
 #pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
-        const int r = r0 + u;
-        if (r < L) {
-          X[(par + 2 * r) * 2 * MB] = dv[u];
-          if (k == 0) spare(spB, m, par * half0 + r) = dhv[u];
-        }
+      for (int u = 0; u < kSweep; ++u) Xr[u * s4] = dv[u];
+      if (k == 0) {
+#pragma unroll
+        for (int u = 0; u < kSweep; ++u) hrow[r0 + u] = dhv[u];
       }
+    }
+    for (int r = Lfull; r < L; ++r) {
+      double dv, dhv;
+      fwd(r, Xp[r * s4], ap[2 * r], bp[2 * r], gp[2 * r], r > 0 ? crow[r - 1] : 0.0, dv, dhv);
+      Xp[r * s4] = dv;
+      if (k == 0) hrow[r] = dhv;
     }
   }
   __syncthreads();
@@ -278,34 +296,46 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     const int k = tid >> (logMB + 1);
     const int cm = tid & (2 * MB - 1);
     const int m = cm & (MB - 1), par = cm >> logMB;
-    double* X = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1);
+    double* Xp = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1) + par * 2 * MB;
+    const int s4 = 4 * MB;
+    const double* crow = spA + m * cst + par * half0;
+    double* hrow = spB + m * cst + par * half0;
     const int L = par == 0 ? (N + 1) / 2 : N / 2;
-    double x = X[(par + 2 * (L - 1)) * 2 * MB];
-    double xh = spare(spB, m, par * half0 + L - 1);
-    // rows L-2 down to 0, in groups of kSweep from the top
-    for (int r1 = L - 2; r1 >= 0; r1 -= kSweep) {
+    // back substitution x_r = d_r - cp_r x_{r+1} for rows L-2 .. 0: first the
+    // rows above a multiple of kSweep one by one, then whole groups (all in range)
+    double x = Xp[(L - 1) * s4];
+    double xh = hrow[L - 1];
+    int r = L - 2;
+    for (int i = 0; i < ((L - 1) & (kSweep - 1)); ++i, --r) {
+      const double c = crow[r];
+      x = fma(-c, x, Xp[r * s4]);
+      xh = fma(-c, xh, hrow[r]);
+      Xp[r * s4] = x;
+      if (k == 0) hrow[r] = xh;  // the only thread touching this chain's entries
+    }
+    for (; r >= 0; r -= kSweep) {  // rows r, r-1, ..., r-kSweep+1 >= 0
+      double* Xr = Xp + (r - kSweep + 1) * s4;
+      const double* cr = crow + r - kSweep + 1;
+      double* hr = hrow + r - kSweep + 1;
       double xv[kSweep], cv[kSweep], hv[kSweep];
 #pragma unroll
       for (int u = 0; u < kSweep; ++u) {
-        const int r = max(r1 - u, 0);
-        xv[u] = X[(par + 2 * r) * 2 * MB];
-        cv[u] = spare(spA, m, par * half0 + r);
-        hv[u] = spare(spB, m, par * half0 + r);
+        xv[u] = Xr[u * s4];
+        cv[u] = cr[u];
+        hv[u] = hr[u];
       }
 #pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
+      for (int u = kSweep - 1; u >= 0; --u) {
         x = fma(-cv[u], x, xv[u]);
         xh = fma(-cv[u], xh, hv[u]);
         xv[u] = x;
         hv[u] = xh;
       }
 #pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
-        const int r = r1 - u;
-        if (r >= 0) {
-          X[(par + 2 * r) * 2 * MB] = xv[u];
-          if (k == 0) spare(spB, m, par * half0 + r) = hv[u];  // the only thread touching these entries
-        }
+      for (int u = 0; u < kSweep; ++u) Xr[u * s4] = xv[u];
+      if (k == 0) {
+#pragma unroll
+        for (int u = 0; u < kSweep; ++u) hr[u] = hv[u];
       }
     }
   }
