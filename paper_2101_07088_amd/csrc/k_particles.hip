@@ -147,29 +147,32 @@ __global__ void __launch_bounds__(kThreads) k_scatter_cells(Geom g, int64_t n, c
   idx[s] = (int)i;
 }
 
-// Exclusive scan of cnt[0..m) into off[0..m] and cur[0..m) by one block.
+// Exclusive scan of cnt[0..m) into off[0..m] and cur[0..m) by one block:
+// per-thread runs, a shuffle scan inside each wave, one barrier for the wave
+// totals.
 __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int* off, int* cur, int m) {
-  __shared__ int sh[1024];
-  const int T = 1024;
-  int per = (m + T - 1) / T;
-  int b = threadIdx.x * per, e = min(m, b + per);
+  __shared__ int wsum[1024 / 64];
+  const int T = 1024, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int per = (m + T - 1) / T;
+  const int b = threadIdx.x * per, e = min(m, b + per);
   int s = 0;
   for (int i = b; i < e; ++i) s += cnt[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 1; o < T; o <<= 1) {
-    int v = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+  int incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int v = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += v;
   }
-  int run = sh[threadIdx.x] - s;
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int wofs = 0;
+  for (int i = 0; i < w; ++i) wofs += wsum[i];
+  int run = wofs + incl - s;
   for (int i = b; i < e; ++i) {
     off[i] = run;
     cur[i] = run;
     run += cnt[i];
   }
-  if (threadIdx.x == T - 1) off[m] = sh[T - 1];
+  if (threadIdx.x == T - 1) off[m] = wofs + incl;
 }
 
 // --- near field -------------------------------------------------------------
@@ -207,54 +210,73 @@ __device__ inline void near_pair(const Geom& g, double dx, double dy, double dz,
   ez += qr * e * (R)dz;
 }
 
-// One thread per target charge (cell-sorted order). Sources: other charges in
-// the 27 neighbouring cells (minimal image), and the bottom/top images of all
+// kNearLanes lanes per target charge (cell-sorted order), each taking every
+// kNearLanes-th of the neighbouring cells; the lanes' sums are combined by a
+// butterfly inside the lane group. Sources: other charges in the 27
+// neighbouring cells (minimal image), and the bottom/top images of all
 // charges, found through the mirror points (x, y, -z) and (x, y, 2H - z).
+constexpr int kNearLanes = 8;
+
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part* __restrict__ srt,
                                                    const int* __restrict__ idx, const int* __restrict__ off,
                                                    double4* near4) {
-  int64_t t = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (t >= n) return;
-  Part me = srt[t];
+  const int64_t gt = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t t = gt / kNearLanes;
+  const int sub = (int)(gt % kNearLanes);
+  const bool active = t < n;  // lane groups never straddle the end (kThreads is a multiple of kNearLanes)
   R ph = 0, ex = 0, ey = 0, ez = 0;
-  int cx = (int)floor(me.x / g.cwx), cy = (int)floor(me.y / g.cwy);
-  cx = min(max(cx, 0), g.ncx - 1);
-  cy = min(max(cy, 0), g.ncy - 1);
-  int xlo = -1, xhi = 1, ylo = -1, yhi = 1;
-  bool xall = g.ncx < 3, yall = g.ncy < 3;
-  if (xall) { xlo = 0; xhi = g.ncx - 1; }
-  if (yall) { ylo = 0; yhi = g.ncy - 1; }
-  // three source families: direct (mirror sign +1), bottom images, top images
-  for (int fam = 0; fam < 3; ++fam) {
-    double zt, qf;  // z of the point whose neighbours are searched; strength factor
-    if (fam == 0) { zt = me.z; qf = 1.0; }
-    else if (fam == 1) { if (g.gamma_b == 0.0 || me.z >= g.r_cut) continue; zt = -me.z; qf = g.gamma_b; }
-    else { if (g.gamma_t == 0.0 || g.H - me.z >= g.r_cut) continue; zt = 2.0 * g.H - me.z; qf = g.gamma_t; }
-    int zlo = (int)floor((zt - g.r_cut) / g.cwz), zhi = (int)floor((zt + g.r_cut) / g.cwz);
-    zlo = max(zlo, 0);
-    zhi = min(zhi, g.ncz - 1);
-    for (int cz = zlo; cz <= zhi; ++cz) {
-      for (int oy = ylo; oy <= yhi; ++oy) {
-        int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
-        for (int ox = xlo; ox <= xhi; ++ox) {
-          int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
-          int c = (cz * g.ncy + yy) * g.ncx + xx;
-          for (int s = off[c]; s < off[c + 1]; ++s) {
-            if (fam == 0 && s == t) continue;
-            Part o = srt[s];
-            double dx = me.x - o.x, dy = me.y - o.y;
-            dx -= g.Lx * rint(dx / g.Lx);
-            dy -= g.Ly * rint(dy / g.Ly);
-            double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
-            near_pair<R>(g, dx, dy, me.z - zs, qf * o.q, ph, ex, ey, ez);
+  if (active) {
+    const Part me = srt[t];
+    int cx = (int)floor(me.x / g.cwx), cy = (int)floor(me.y / g.cwy);
+    cx = min(max(cx, 0), g.ncx - 1);
+    cy = min(max(cy, 0), g.ncy - 1);
+    int xlo = -1, xhi = 1, ylo = -1, yhi = 1;
+    const bool xall = g.ncx < 3, yall = g.ncy < 3;
+    if (xall) { xlo = 0; xhi = g.ncx - 1; }
+    if (yall) { ylo = 0; yhi = g.ncy - 1; }
+    int visit = 0;  // running index of the visited cells; this lane takes visit % kNearLanes == sub
+    // three source families: direct (mirror sign +1), bottom images, top images
+    for (int fam = 0; fam < 3; ++fam) {
+      double zt, qf;  // z of the point whose neighbours are searched; strength factor
+      if (fam == 0) { zt = me.z; qf = 1.0; }
+      else if (fam == 1) { if (g.gamma_b == 0.0 || me.z >= g.r_cut) continue; zt = -me.z; qf = g.gamma_b; }
+      else { if (g.gamma_t == 0.0 || g.H - me.z >= g.r_cut) continue; zt = 2.0 * g.H - me.z; qf = g.gamma_t; }
+      int zlo = (int)floor((zt - g.r_cut) / g.cwz), zhi = (int)floor((zt + g.r_cut) / g.cwz);
+      zlo = max(zlo, 0);
+      zhi = min(zhi, g.ncz - 1);
+      for (int cz = zlo; cz <= zhi; ++cz) {
+        for (int oy = ylo; oy <= yhi; ++oy) {
+          const int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
+          for (int ox = xlo; ox <= xhi; ++ox, ++visit) {
+            if (visit % kNearLanes != sub) continue;
+            const int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
+            const int c = (cz * g.ncy + yy) * g.ncx + xx;
+            for (int s = off[c]; s < off[c + 1]; ++s) {
+              if (fam == 0 && s == t) continue;
+              const Part o = srt[s];
+              double dx = me.x - o.x, dy = me.y - o.y;
+              dx -= g.Lx * rint(dx / g.Lx);
+              dy -= g.Ly * rint(dy / g.Ly);
+              const double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
+              near_pair<R>(g, dx, dy, me.z - zs, qf * o.q, ph, ex, ey, ez);
+            }
           }
         }
       }
     }
   }
-  const double c = 1.0 / (4.0 * kPi * g.eps);
-  near4[idx[t]] = make_double4(c * (double)ph, c * (double)ex, c * (double)ey, c * (double)ez);
+#pragma unroll
+  for (int o = 1; o < kNearLanes; o <<= 1) {
+    ph += __shfl_xor(ph, o, 64);
+    ex += __shfl_xor(ex, o, 64);
+    ey += __shfl_xor(ey, o, 64);
+    ez += __shfl_xor(ez, o, 64);
+  }
+  if (active && sub == 0) {
+    const double c = 1.0 / (4.0 * kPi * g.eps);
+    near4[idx[t]] = make_double4(c * (double)ph, c * (double)ex, c * (double)ey, c * (double)ez);
+  }
 }
 
 // Pointwise near-field potential at the origin (gauge of Sec. 5.2.2): kernel
@@ -391,7 +413,7 @@ hipError_t launch_bin(dpse_plan* p, int64_t n) {
 
 template <typename R>
 hipError_t launch_near(dpse_plan* p, int64_t n) {
-  int nb = (int)((n + kThreads - 1) / kThreads);
+  int nb = (int)((n * kNearLanes + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_near<R>, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.nsrt,
                      (const int*)p->w.nsrt_idx, (const int*)p->w.cell_off, p->w.near4);
   return hipGetLastError();
