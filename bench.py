@@ -42,6 +42,51 @@ def stage_bytes(p, info_band_frac, s):
     }
 
 
+SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4)]
+INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4)]
+COLUMN_BLOCKS = [2048, 1024, 4096]
+
+
+def kernel_name(stage, tiles, mixed):
+    """Name (as rocprofv3 prints it, spaces removed) of the single kernel of a
+    grid stage for the tuned launch shapes, or None for multi-kernel stages."""
+    r = "float" if mixed else "double"
+    if stage == "spread":
+        i = tiles[0]
+        t, pz = SPREAD_SHAPES[i]
+        return f"k_spread{'_gather' if i >= 6 else ''}<{r},{t},{pz}>"
+    if stage == "interp":
+        i = tiles[1]
+        t, pz = INTERP_SHAPES[i]
+        return f"k_interp{'_gather' if i >= 5 else ''}<{r},{t},{pz}>"
+    if stage == "column":
+        return f"k_column<{r},{COLUMN_BLOCKS[tiles[2]]}>"
+    return None
+
+
+def profiled_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload, or None when there is none or a kernel source
+    has changed since the counters were taken."""
+    import glob
+    import hashlib
+    if kernel is None:
+        return None
+    files = glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_jump_*.txt"))
+    if not files:
+        return None
+    src = os.path.join(ROOT, "paper_2101_07088_amd", "csrc")
+    found = None
+    for line in open(files[0]):
+        f = line.split()
+        if len(f) == 3 and f[0] == "source_sha256":
+            if hashlib.sha256(open(os.path.join(src, f[1]), "rb").read()).hexdigest()[:16] != f[2]:
+                return None
+        elif len(f) >= 10 and f[0] == "kernel" and f[1] == kernel:
+            found = float(f[9])
+    return found
+
+
 def band_fraction(p, info):
     z = [0.5 * (info["z_lo"] + info["z_hi"]) + 0.5 * (info["z_hi"] - info["z_lo"]) * math.cos(math.pi * j / (p.Nz - 1))
          for j in range(p.Nz)]
@@ -300,6 +345,8 @@ def main(argv=None):
     dom = max(sb, key=lambda k: r["stages"][k])
     t_dom = r["stages"][dom] * 1e-3
     achieved = sb[dom] / t_dom / 1e9
+    dom_kernel = kernel_name(dom, r["tiles"], head == "mixed")
+    traffic = profiled_traffic(dom_kernel)
     line = {
         "metric": "charge-force evals/s at <=1e-5 rel RMS force err vs FP64; p50/p99 solve ms",
         "value": value, "unit": "charge-force evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -312,8 +359,9 @@ def main(argv=None):
         "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
         "tiles": {"spread": r["tiles"][0], "interp": r["tiles"][1], "column": r["tiles"][2]},
         "accuracy": acc,
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": dom_kernel or dom, "stage": dom, "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "algorithmic_bytes": sb[dom], "traffic": traffic},
     }
     for prec, rr in res.items():
         line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / a.steps)
