@@ -571,7 +571,16 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     double z = zn[j];
     double k = s_k[m];
     if (k > 0.0 && s_keep[m] && z >= -g.H_E && z <= g.H + g.H_E) {
-      double e1 = exp(k * (z - g.H)), e2 = exp(-k * z);
+      // the exponentials in the storage precision of Psi (FP32 in the mixed
+      // path: no overflow, |k z| <= pi n_g / 2 + k H), the sums in FP64
+      double e1, e2;
+      if (sizeof(R) == 8) {
+        e1 = exp(k * (z - g.H));
+        e2 = exp(-k * z);
+      } else {
+        e1 = (double)expf((float)(k * (z - g.H)));
+        e2 = (double)expf((float)(-k * z));
+      }
       double2 al = s_ab[m][0], be = s_ab[m][1];
       ps_x += al.x * e1 + be.x * e2;
       ps_y += al.y * e1 + be.y * e2;
