@@ -155,7 +155,8 @@ def bench_batch(dp, torch, steps, n_sys=64, n_branches=8):
     """Uneven batch: 64 independent slabs (N log-uniform in [1024, 65536],
     L in {32,64,128}, H in {16,32,64}, eps_b, eps_t in {0.05,1,20}, xi=1.5,
     h=0.25, r_cut=2), mixed precision, one graph launch per step; against
-    the same 64 solves one after another on one stream without a graph."""
+    the same 64 solves one after another on one stream without a graph, in
+    mixed precision and in FP64 (the plain single-system path)."""
     import workloads as W
     from paper_2101_07088_amd.batch import BatchRunner
     systems = W.batch_systems(n_sys)
@@ -179,11 +180,17 @@ def bench_batch(dp, torch, steps, n_sys=64, n_branches=8):
     t_seq = timed(seq, max(2, steps // 4))
     seq.close()
     del seq
+    seq64 = BatchRunner(tens, precision=dp.DPSE_FP64, n_branches=1, use_graph=False)
+    t_seq64 = timed(seq64, max(2, steps // 4))
+    seq64.close()
+    del seq64
+    out.update({"sequential_fp64_evals_per_s": n_total / t_seq64, "sequential_fp64_ms": 1e3 * t_seq64})
     br = BatchRunner(tens, precision=dp.DPSE_MIXED, n_branches=n_branches, use_graph=True)
     t_b = timed(br, steps)
     out.update({"evals_per_s": n_total / t_b, "ms_per_batch": 1e3 * t_b,
                 "sequential_evals_per_s": n_total / t_seq, "sequential_ms": 1e3 * t_seq,
-                "speedup_vs_sequential": t_seq / t_b, "arena_bytes": br.workspace_bytes})
+                "speedup_vs_sequential": t_seq / t_b, "speedup_vs_sequential_fp64": t_seq64 / t_b,
+                "arena_bytes": br.workspace_bytes})
     # accuracy of the mixed batch against FP64 single solves on a sample of systems
     errs = []
     for k in range(0, n_sys, 16):
@@ -295,6 +302,7 @@ def main(argv=None):
                     help="also time the 64-system uneven batch")
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the serving stream")
+    ap.add_argument("--batch-branches", type=int, default=8)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
@@ -368,7 +376,7 @@ def main(argv=None):
         line[f"{prec}_p50_ms"] = float(np.percentile(rr["lat_ms"], 50))
         line[f"{prec}_p99_ms"] = float(np.percentile(rr["lat_ms"], 99))
     if a.batch:
-        line["batch"] = bench_batch(dp, torch, a.steps)
+        line["batch"] = bench_batch(dp, torch, a.steps, n_branches=a.batch_branches)
         print(f"[bench] batch: {line['batch']}", file=sys.stderr, flush=True)
     if a.serve:
         line["serving"] = bench_serve(dp, torch, a.serve_rate, a.serve_duration, a.serve_warmup)
