@@ -32,8 +32,9 @@ namespace {
 constexpr int kThreads = 256;
 // KE (a template parameter) = complex elements per LDS buffer = modes per
 // block x 2(Nz-1); one of kColumnKE, chosen per grid by the autotuner.
-constexpr int kColumnKE[] = {2048, 1024, 4096};
-constexpr int kNumColumn = 3;
+constexpr int kColumnKE[] = {2048, 1024, 4096, 2048, 4096};
+constexpr int kColumnNT[] = {256, 256, 256, 512, 512};  // threads per workgroup
+constexpr int kNumColumn = 5;
 constexpr int kMaxMB = 32;    // modes per block: 8 MB chain threads <= kThreads
 // dynamic LDS per block: 160 KB per workgroup less a margin for the static
 // arrays of the kernel (under 3 KB)
@@ -104,8 +105,8 @@ __global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __res
   }
 }
 
-template <typename R, int KE>
-__global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
+template <typename R, int KE, int NT>
+__global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                      const typename CT<R>::T* __restrict__ fx_o,
                                                      typename CT<R>::T* __restrict__ psi,
                                                      typename CT<R>::T* __restrict__ psiz,
@@ -136,7 +137,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   const int m0 = blockIdx.x * MB;
   const int tid = threadIdx.x;
   const double Rz = g.zR;
-  for (int i = tid; i < kCtabRows * N; i += kThreads) lco[i] = ctab[i];
+  for (int i = tid; i < kCtabRows * N; i += NT) lco[i] = ctab[i];
   const double* ca = lco;
   const double* cb = lco + N;
   const double* cc = lco + 2 * N;
@@ -156,32 +157,32 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   // the plan-time chain multipliers of the block's modes (N MB values), and
   // the functional weights W when they fit the spare storage, are fetched
   // into registers now and put in LDS once the buffers they share are free
-  constexpr int kCp = KE / (2 * kThreads) + 1;  // >= N MB / kThreads
-  constexpr int kWr = 12;                       // W staged when 10 (N+2) <= kWr kThreads
+  constexpr int kCp = KE / (2 * NT) + 1;  // >= N MB / NT
+  constexpr int kWr = 3072 / NT;                // W staged when 10 (N+2) <= 3072
   double cpr[kCp], wr[kWr];
 #pragma unroll
   for (int q = 0; q < kCp; ++q) {
-    const int t = tid + q * kThreads, row = t >> logMB, m = t & (MB - 1);
+    const int t = tid + q * NT, row = t >> logMB, m = t & (MB - 1);
     cpr[q] = (row < N && m0 + m < nmodes) ? cpiv[(size_t)row * nmodes + m0 + m] : 0.0;
   }
-  const bool w_lds = kNumFun * NU <= kWr * kThreads && kNumFun * NU <= 2 * (N - 2) * MB;
+  const bool w_lds = kNumFun * NU <= kWr * NT && kNumFun * NU <= 2 * (N - 2) * MB;
   if (w_lds) {
 #pragma unroll
     for (int q = 0; q < kWr; ++q) {
-      const int t = tid + q * kThreads;
+      const int t = tid + q * NT;
       wr[q] = t < kNumFun * NU ? W[t] : 0.0;
     }
   }
 
-  for (int i = tid; i < M / 2; i += kThreads) tw[i] = twz[i];
+  for (int i = tid; i < M / 2; i += NT) tw[i] = twz[i];
   // 1. even extension of the node values in bit-reversed order, then FFT;
   //    all global loads of the thread are issued before the LDS stores
   {
-    constexpr int kPer = KE / kThreads;  // M * MB == KE
+    constexpr int kPer = KE / NT;  // M * MB == KE
     C va[kPer], vb[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int t = tid + q * kThreads;
+      const int t = tid + q * NT;
       const int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
       const int c = j < N ? j : M - j;
       va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int t = tid + q * kThreads;
+      const int t = tid + q * NT;
       const int j = t >> logMB, m = t & (MB - 1);
       const int pos = bitrev(j, logM) * MB + m;
       A[pos] = make_double2((double)vb[q].x, (double)vb[q].y);
@@ -201,8 +202,8 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     }
   }
   __syncthreads();
-  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(A, logM, logMB, 1, MB, tw, false, tid);
-  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(B, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(A, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(B, logM, logMB, 1, MB, tw, false, tid);
 
   // spare storage beyond index N of each buffer (N-2 complex = 2N-4 doubles per mode)
   double* spA = reinterpret_cast<double*>(A + N * MB);  // chain pivots
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   double* s_fun = lco + kCtabRows * N;  // [MB][10][6]
 #pragma unroll
   for (int q = 0; q < kCp; ++q) {
-    const int t = tid + q * kThreads, row = t >> logMB, m = t & (MB - 1);
+    const int t = tid + q * NT, row = t >> logMB, m = t & (MB - 1);
     if (row < N) spare(spA, m, row) = cpr[q];
   }
   __syncthreads();
@@ -354,13 +355,13 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   if (w_lds) {
 #pragma unroll
     for (int q = 0; q < kWr; ++q) {
-      const int t = tid + q * kThreads;
+      const int t = tid + q * NT;
       if (t < kNumFun * NU) spA[t] = wr[q];
     }
   }
   __syncthreads();
   auto functionals = [&](const double* Wsrc) {
-    for (int t = tid; t < MB * 20; t += kThreads) {
+    for (int t = tid; t < MB * 20; t += NT) {
       const int pr = t >> 1, part = t & 1;
       const int m = pr / 10, f = pr - 10 * m;
       const double* Wf = Wsrc + f * NU;
@@ -459,7 +460,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   __syncthreads();
 
   // 5. final series of psi_i* into A: y_n = Y[n].(P) + y_0 Y[n].(h1) + y'_0 Y[n].(h2)
-  for (int t = tid; t < N * MB; t += kThreads) {
+  for (int t = tid; t < N * MB; t += NT) {
     const int n = t >> logMB, m = t & (MB - 1);
     double2 yP = make_double2(0.0, 0.0);
     double yh = 0.0;
@@ -495,7 +496,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   {
     const int lane = tid & 63, wv = tid >> 6;
     const double ir = 1.0 / Rz;
-    for (int ch = wv; ch < 2 * MB; ch += kThreads / 64) {
+    for (int ch = wv; ch < 2 * MB; ch += NT / 64) {
       const int m = ch & (MB - 1), q = ch >> logMB;  // q: parity of the output index j
       // outputs j = q, q+2, ... <= N-1; entry t (from the top) is j = jt - 2t
       const int jt = (N - 1) - (((N - 1) - q) & 1);
@@ -536,11 +537,11 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
   // 7. inverse DCT-I of A (series) and B (derivative series): v_j = 1/2 FFT(e)[j]
   //    with e the even extension of (2 c_0, c_1, ..., c_{N-2}, 2 c_{N-1})
   {
-    constexpr int kPer = kElems / kThreads;  // M * MB == kElems
+    constexpr int kPer = kElems / NT;  // M * MB == kElems
     double2 ra[kPer], rb[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      int t = tid + q * kThreads;
+      int t = tid + q * NT;
       int j = t >> logMB, m = t & (MB - 1);
       int n = j < N ? j : M - j;
       double f = (n == 0 || n == N - 1) ? 2.0 : 1.0;
@@ -551,7 +552,7 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      int t = tid + q * kThreads;
+      int t = tid + q * NT;
       int j = t >> logMB, m = t & (MB - 1);
       int pos = bitrev(j, logM) * MB + m;
       A[pos] = ra[q];
@@ -559,11 +560,11 @@ __global__ void __launch_bounds__(kThreads) k_column(Geom g, const typename CT<R
     }
     __syncthreads();
   }
-  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(A, logM, logMB, 1, MB, tw, false, tid);
-  fft_lds_r22<double2, true, kElems / 4 / kThreads, kThreads>(B, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(A, logM, logMB, 1, MB, tw, false, tid);
+  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(B, logM, logMB, 1, MB, tw, false, tid);
 
   // 8. add the correction at the window nodes and the k = 0 linear mode; write out
-  for (int t = tid; t < N * MB; t += kThreads) {
+  for (int t = tid; t < N * MB; t += NT) {
     int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
     if (mi >= nmodes) continue;
     double2 v = A[j * MB + m], d = B[j * MB + m];
@@ -609,7 +610,7 @@ size_t column_lds(const Geom& g, int KE) {
   return (size_t)(2 * KE + M / 2) * sizeof(double2) + (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
 }
 
-template <typename R, int KE>
+template <typename R, int KE, int NT>
 void column_as(dpse_plan* p) {
   using C = typename CT<R>::T;
   const Geom& g = p->g;
@@ -617,7 +618,7 @@ void column_as(dpse_plan* p) {
   const int MB = KE / M;
   const int nmodes = g.Ny * g.nkx;
   const int nb = (nmodes + MB - 1) / MB;
-  hipLaunchKernelGGL((k_column<R, KE>), dim3(nb), dim3(kThreads), column_lds(g, KE), p->stream, g,
+  hipLaunchKernelGGL((k_column<R, KE, NT>), dim3(nb), dim3(NT), column_lds(g, KE), p->stream, g,
                      (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
                      (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal);
 }
@@ -636,12 +637,14 @@ hipError_t launch_pivots(dpse_plan* p, hipStream_t s) {
 }
 
 int column_block(int i) { return kColumnKE[i]; }
+int column_threads(int i) { return kColumnNT[i]; }
 
 // A block of KE / M modes needs M <= KE, at most kMaxMB modes and its LDS.
 bool column_valid(const Geom& g, int i) {
   if (i < 0 || i >= kNumColumn) return false;
   const int KE = kColumnKE[i], M = 2 * (g.Nz - 1);
-  return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && column_lds(g, KE) <= kMaxLds;
+  return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && 8 * (KE / M) <= kColumnNT[i] &&
+         column_lds(g, KE) <= kMaxLds;
 }
 
 template <typename R>
@@ -649,9 +652,11 @@ hipError_t launch_column(dpse_plan* p) {
   int c = p->column_cfg;
   if (!column_valid(p->g, c)) c = column_valid(p->g, 0) ? 0 : (column_valid(p->g, 1) ? 1 : 2);
   switch (c) {
-    case 0: column_as<R, 2048>(p); break;
-    case 1: column_as<R, 1024>(p); break;
-    default: column_as<R, 4096>(p); break;
+    case 0: column_as<R, 2048, 256>(p); break;
+    case 1: column_as<R, 1024, 256>(p); break;
+    case 2: column_as<R, 4096, 256>(p); break;
+    case 3: column_as<R, 2048, 512>(p); break;
+    default: column_as<R, 4096, 512>(p); break;
   }
   return hipGetLastError();
 }
@@ -661,9 +666,12 @@ hipError_t launch_column(dpse_plan* p) {
 // (which may be captured into a graph).
 // A candidate whose limit cannot be raised is left out of column_valid().
 hipError_t prepare_kernels() {
-  const void* fns[kNumColumn][2] = {{(const void*)k_column<double, 2048>, (const void*)k_column<float, 2048>},
-                                    {(const void*)k_column<double, 1024>, (const void*)k_column<float, 1024>},
-                                    {(const void*)k_column<double, 4096>, (const void*)k_column<float, 4096>}};
+  const void* fns[kNumColumn][2] = {
+      {(const void*)k_column<double, 2048, 256>, (const void*)k_column<float, 2048, 256>},
+      {(const void*)k_column<double, 1024, 256>, (const void*)k_column<float, 1024, 256>},
+      {(const void*)k_column<double, 4096, 256>, (const void*)k_column<float, 4096, 256>},
+      {(const void*)k_column<double, 2048, 512>, (const void*)k_column<float, 2048, 512>},
+      {(const void*)k_column<double, 4096, 512>, (const void*)k_column<float, 4096, 512>}};
   bool any = false;
   for (int i = 0; i < kNumColumn; ++i) {
     bool ok = true;
