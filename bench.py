@@ -206,6 +206,31 @@ def bench_batch(dp, torch, steps, n_sys=64, n_branches=8):
     return out
 
 
+def bench_uniform(dp, torch, steps):
+    """The jump workload's charges and box with equal permittivities (eps_b =
+    eps_t = eps = 1), mixed precision: the general solver on 256^2 x 129
+    against the uniform-permittivity solver on 256^2 x 65 (its smaller z
+    domain needs about half the nodes for the same accuracy) and on 256^2 x
+    129; the force difference between them is the method error."""
+    import workloads as W
+    p, pos, q = W.config_jump(0)
+    pu = p.copy(eps_b=1.0, eps_t=1.0)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    out = {}
+    forces = {}
+    for name, prm in (("general_Nz129", pu), ("fast_Nz65", pu.copy(uniform_fast=True, Nz=65)),
+                      ("fast_Nz129", pu.copy(uniform_fast=True))):
+        r = time_path(dp, torch, prm, tpos, tq, dp.DPSE_MIXED, steps, 3)
+        out[name] = {"ms": 1e3 * r["wall_s"] / steps, "evals_per_s": len(q) / (r["wall_s"] / steps)}
+        forces[name] = r["F"]
+    ref = forces["general_Nz129"]
+    for name in ("fast_Nz65", "fast_Nz129"):
+        out[name]["rel_rms_force_vs_general"] = rel_rms(forces[name], ref)
+    out["speedup_fast_Nz65"] = out["general_Nz129"]["ms"] / out["fast_Nz65"]["ms"]
+    return out
+
+
 def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_slots=8, max_queue=256):
     """Serving stream: Poisson arrivals of solves from n_traj Brownian-like
     trajectories (N log-uniform in [512, 262144], box and permittivities
@@ -303,6 +328,8 @@ def main(argv=None):
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
                     help="also run the serving stream")
     ap.add_argument("--batch-branches", type=int, default=8)
+    ap.add_argument("--uniform", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the uniform-permittivity solver against the general one")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
@@ -375,6 +402,9 @@ def main(argv=None):
         line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / a.steps)
         line[f"{prec}_p50_ms"] = float(np.percentile(rr["lat_ms"], 50))
         line[f"{prec}_p99_ms"] = float(np.percentile(rr["lat_ms"], 99))
+    if a.uniform:
+        line["uniform_eps"] = bench_uniform(dp, torch, a.steps)
+        print(f"[bench] uniform eps: {line['uniform_eps']}", file=sys.stderr, flush=True)
     if a.batch:
         line["batch"] = bench_batch(dp, torch, a.steps, n_branches=a.batch_branches)
         print(f"[bench] batch: {line['batch']}", file=sys.stderr, flush=True)

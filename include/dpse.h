@@ -71,8 +71,13 @@ enum {
 
 /* Flags (bitwise or). */
 enum {
-  DPSE_GAUGE_NONE = 1, /* skip the phi(0) = 0 gauge constant (U and F unaffected for neutral sets) */
-  DPSE_KMAX_GT = 2     /* cap the harmonic correction at |k| <= min(pi/h, 4.2/g_t) instead of pi/h */
+  DPSE_GAUGE_NONE = 1,  /* skip the phi(0) = 0 gauge constant (U and F unaffected for neutral sets) */
+  DPSE_KMAX_GT = 2,     /* cap the harmonic correction at |k| <= min(pi/h, 4.2/g_t) instead of pi/h */
+  DPSE_UNIFORM_FAST = 4 /* equal permittivities (eps_bottom == eps == eps_top, else DPSE_EINVAL):
+                           the free-space solve of Sec. 3.1.1 on the Chebyshev domain [-H_E, H + H_E],
+                           with no wall group, images or harmonic correction, and the k = 0 slope
+                           that cancels the field outside the (neutral) sources; about half the
+                           z nodes of the general solver for the same accuracy */
 };
 
 /* Parameters of one slab system. Lengths share one unit. */

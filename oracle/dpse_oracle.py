@@ -68,8 +68,14 @@ def derive(p) -> Dict[str, object]:
     g_t = math.sqrt(1.0 / (4.0 * p.xi ** 2) + p.g_w ** 2)          # eq. gt
     n_g = p.n_g if p.n_g else 2 * math.ceil(4.3 * g_t / h)
     H_E = n_g * h / 2.0                                             # eq. He
-    a = -3.0 * H_E
-    b = p.H + 3.0 * H_E
+    fast = getattr(p, "uniform_fast", False)
+    if fast and not (p.eps_b == p.eps == p.eps_t):
+        raise ValueError("the uniform-permittivity solver needs eps_b == eps == eps_t")
+    # Chebyshev domain: [-3 H_E, H + 3 H_E] with walls (Sec. 5.2.2); with no
+    # jump the sources (Gaussians of support H_E) fill [-H_E, H + H_E] and the
+    # free-space solve of Sec. 3.1.1 needs no more
+    a = -H_E if fast else -3.0 * H_E
+    b = p.H + (H_E if fast else 3.0 * H_E)
     c = 0.5 * (a + b)
     R = 0.5 * (b - a)
     N = p.Nz
@@ -100,7 +106,7 @@ def derive(p) -> Dict[str, object]:
     # derivative multipliers vanish on Nyquist indices
     dkx = np.where(NXI == -(p.Nx // 2), 0.0, KX)
     dky = np.where(NYI == -(p.Ny // 2), 0.0, KY)
-    return dict(h=h, g_t=g_t, n_g=n_g, H_E=H_E, a=a, b=b, c=c, R=R, s=s, z=z,
+    return dict(h=h, g_t=g_t, n_g=n_g, H_E=H_E, a=a, b=b, c=c, R=R, s=s, z=z, fast=fast,
                 w=w, gamma_b=gamma_b, gamma_t=gamma_t, tau_b=tau_b, tau_t=tau_t,
                 xi_e=xi_e, kx=KX, ky=KY, kabs=kabs, keep=keep, dkx=dkx, dky=dky)
 
@@ -114,6 +120,9 @@ def groups_and_images(p, d, pos, q):
     H_E = d["H_E"]
     low = z < 2.0 * H_E
     high = z > p.H - 2.0 * H_E
+    if d["fast"]:  # no walls to correct for: one group, no images
+        low = np.zeros_like(low)
+        high = np.zeros_like(high)
     c_o = low | high
     ipos, iq = [], []
     if d["gamma_b"] != 0.0:
@@ -521,14 +530,27 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
     dpsi_c = kk * (alpha[None] * e1 - beta[None] * e2)
     psi_c[:, ~act] = 0.0
     dpsi_c[:, ~act] = 0.0
-    # step 5: k = 0 linear mode (eqs. CE, ai1, ai2; mean of the two)
-    dk0_oa = series_dz_at(y_o[:, 0, 0], -1.0, R)
-    dk0_ob = series_dz_at(y_o[:, 0, 0], 1.0, R)
-    A_b = -tb * dk0_oa
-    A_t = -tt * dk0_ob
-    A_i1 = (p.eps_b * (tb * d_o0[0, 0] + A_b) - p.eps * d_i0[0, 0]) / p.eps
-    A_i2 = (p.eps_t * (tt * d_oH[0, 0] + A_t) - p.eps * d_iH[0, 0]) / p.eps
-    A_i = 0.5 * (A_i1 + A_i2)
+    if d["fast"]:
+        # no jumps: the Robin BVPs on [-H_E, H + H_E] are the free-space
+        # solutions (Sec. 3.1.1), there is nothing to correct; at k = 0 the
+        # field of the neutral set vanishes outside the sources, so the slope
+        # A_i cancels psi_i*' at both ends of the domain (mean of the two)
+        alpha[:] = 0.0
+        beta[:] = 0.0
+        psi_c[:] = 0.0
+        dpsi_c[:] = 0.0
+        A_i1 = -series_dz_at(y_i[:, 0, 0], -1.0, R)
+        A_i2 = -series_dz_at(y_i[:, 0, 0], 1.0, R)
+        A_i = 0.5 * (A_i1 + A_i2)
+    else:
+        # step 5: k = 0 linear mode (eqs. CE, ai1, ai2; mean of the two)
+        dk0_oa = series_dz_at(y_o[:, 0, 0], -1.0, R)
+        dk0_ob = series_dz_at(y_o[:, 0, 0], 1.0, R)
+        A_b = -tb * dk0_oa
+        A_t = -tt * dk0_ob
+        A_i1 = (p.eps_b * (tb * d_o0[0, 0] + A_b) - p.eps * d_i0[0, 0]) / p.eps
+        A_i2 = (p.eps_t * (tt * d_oH[0, 0] + A_t) - p.eps * d_iH[0, 0]) / p.eps
+        A_i = 0.5 * (A_i1 + A_i2)
     # step 6: potential and z-derivative at the nodes (series plus correction)
     Psi = cheb_eval_nodes(y_i, N) + psi_c
     Psi_z = cheb_eval_nodes(npcheb.chebder(y_i, axis=0), N) / R + dpsi_c

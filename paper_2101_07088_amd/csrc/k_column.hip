@@ -76,6 +76,7 @@ __device__ inline void mode_wave(const Geom& g, int mi, double& kk, int& keep) {
   const long long rhs = (long long)g.Nx * g.Ny * (long long)g.Nx * g.Ny;
   keep = (lhs <= rhs) ? 1 : 0;
   if ((g.flags & DPSE_KMAX_GT) && !(kk <= 4.2 / g.g_t)) keep = 0;
+  if (g.flags & DPSE_UNIFORM_FAST) keep = 0;  // nothing to correct without jumps
 }
 
 // Plan-time factorisation of the per-mode chains (they depend on kappa only):
@@ -445,12 +446,18 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
       be = make_double2(((e - eb) * E * Rt.x - (e + et) * Rb.x) / D, ((e - eb) * E * Rt.y - (e + et) * Rb.y) / D);
     }
     if (m0 + m == 0) {
-      const double e = g.eps, tb = g.tau_b, tt = g.tau_t;
-      const double2 ea = fin_o(FUN_EA), ebd = fin_o(FUN_EB);
-      double Ab = -tb * ea.x, At = -tt * ebd.x;
-      double A1 = (g.eps_b * (tb * do0.x + Ab) - e * di0.x) / e;
-      double A2 = (g.eps_t * (tt * doH.x + At) - e * diH.x) / e;
-      Ai = 0.5 * (A1 + A2);
+      if (g.flags & DPSE_UNIFORM_FAST) {
+        // free space (Sec. 3.1.1): the field of the neutral set vanishes
+        // outside the sources, so A_i cancels psi_i*' at both domain ends
+        Ai = -0.5 * (fin_i(FUN_EA).x + fin_i(FUN_EB).x);
+      } else {
+        const double e = g.eps, tb = g.tau_b, tt = g.tau_t;
+        const double2 ea = fin_o(FUN_EA), ebd = fin_o(FUN_EB);
+        double Ab = -tb * ea.x, At = -tt * ebd.x;
+        double A1 = (g.eps_b * (tb * do0.x + Ab) - e * di0.x) / e;
+        double A2 = (g.eps_t * (tt * doH.x + At) - e * diH.x) / e;
+        Ai = 0.5 * (A1 + A2);
+      }
       scal[3] = Ai;
     }
     s_ab[m][0] = al;

@@ -78,9 +78,10 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     if (!(x < g.Lx)) x = 0.0;
     y -= g.Ly * floor(y / g.Ly);
     if (!(y < g.Ly)) y = 0.0;
+    const bool fast = (g.flags & DPSE_UNIFORM_FAST) != 0;  // no walls: one group, no images
     double hmin = fmin(z, g.H - z);
-    if (g.r_cut >= g.H + hmin || 2.0 * g.H_E >= g.H + hmin) st |= 2;
-    bool low = z < 2.0 * g.H_E, high = z > g.H - 2.0 * g.H_E;
+    if (!fast && (g.r_cut >= g.H + hmin || 2.0 * g.H_E >= g.H + hmin)) st |= 2;
+    bool low = !fast && z < 2.0 * g.H_E, high = !fast && z > g.H - 2.0 * g.H_E;
     ext[i] = Part{x, y, z, qq};
     meta[i] = ((low || high) ? GRP_WALL : GRP_INNER) | (int)(i << 2);
     if (low && g.gamma_b != 0.0) {

@@ -59,7 +59,9 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     return DPSE_EINVAL;
   if (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
   if (p->precision != DPSE_FP64 && p->precision != DPSE_MIXED) return DPSE_EINVAL;
-  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT)) return DPSE_EINVAL;
+  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST)) return DPSE_EINVAL;
+  const bool fast = (p->flags & DPSE_UNIFORM_FAST) != 0;
+  if (fast && !(p->eps_bottom == p->eps && p->eps_top == p->eps)) return DPSE_EINVAL;
   double h = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(h - hy) > 1e-12 * h) return DPSE_EINVAL;
   double g_t = std::sqrt(1.0 / (4.0 * p->xi * p->xi) + p->g_w * p->g_w);
@@ -75,16 +77,20 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     rc += 4.0 * p->g_w;  // r_cut = r_nf + n_sigma g_w (Sec. 5.1)
   }
   if (!(rc > 0.0) || rc >= 0.5 * std::fmin(p->Lx, p->Ly)) return DPSE_EINVAL;
-  // position-independent necessary conditions of Sec. 4.2 / 5.3 (h_min <= H/2)
-  if (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H) return DPSE_EINVAL;
+  // position-independent necessary conditions of Sec. 4.2 / 5.3 (h_min <= H/2);
+  // they concern the images, which the uniform-permittivity solver has none of
+  if (!fast && (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H)) return DPSE_EINVAL;
+  // Chebyshev domain: [-3 H_E, H + 3 H_E] with walls (Sec. 5.2.2); the
+  // free-space solve without jumps (Sec. 3.1.1) needs only the sources' span
+  const double zdom = fast ? H_E : 3.0 * H_E;
 
   std::memset(info, 0, sizeof(*info));
   info->h = h;
   info->g_t = g_t;
   info->H_E = H_E;
   info->n_sigma = H_E / g_t;
-  info->z_lo = -3.0 * H_E;
-  info->z_hi = p->H + 3.0 * H_E;
+  info->z_lo = -zdom;
+  info->z_hi = p->H + zdom;
   info->r_cut = rc;
   info->xi_e = 1.0 / std::sqrt(4.0 * p->g_w * p->g_w + 1.0 / (p->xi * p->xi));
   info->support = ng;
@@ -96,7 +102,7 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     g->eps = p->eps; g->eps_b = p->eps_bottom; g->eps_t = p->eps_top;
     g->xi = p->xi; g->g_w = p->g_w;
     g->h = h; g->inv_h = 1.0 / h; g->g_t = g_t; g->H_E = H_E;
-    g->za = -3.0 * H_E; g->zb = p->H + 3.0 * H_E;
+    g->za = -zdom; g->zb = p->H + zdom;
     g->zc = 0.5 * (g->za + g->zb); g->zR = 0.5 * (g->zb - g->za);
     g->gamma_b = (p->eps - p->eps_bottom) / (p->eps + p->eps_bottom);
     g->gamma_t = (p->eps - p->eps_top) / (p->eps + p->eps_top);
@@ -129,6 +135,10 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     for (int j = N - 1; j >= 0; --j) {
       double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
       if (z < 3.0 * H_E) bot_begin = j;
+    }
+    if (fast) {  // one group: no wall band
+      top_end = 0;
+      bot_begin = N;
     }
     g->top_end = top_end;
     g->bot_begin = bot_begin;

@@ -67,3 +67,13 @@ def test_derive_rejects_invalid_parameters(change):
     with pytest.raises(dp.DpseError) as e:
         dp.derive(p)
     assert e.value.status == 1
+
+
+def test_uniform_fast_flag_validation():
+    """The uniform-permittivity solver needs equal permittivities and uses the
+    domain [-H_E, H + H_E]."""
+    p, _, _ = config_small(0)
+    info = dp.derive(p.copy(uniform_fast=True))
+    assert abs(info["z_lo"] + info["H_E"]) < 1e-12 and abs(info["z_hi"] - (p.H + info["H_E"])) < 1e-12
+    with pytest.raises(dp.DpseError):
+        dp.derive(p.copy(uniform_fast=True, eps_b=0.5))

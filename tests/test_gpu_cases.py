@@ -174,3 +174,14 @@ def test_every_tile_shape_and_autotune(precision):
             tried += 1
     assert tried >= 8
     plan.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_uniform_fast_path_against_oracle(precision, tol):
+    """The uniform-permittivity solver against the oracle's, on the small
+    workload (32 x 32 x 33) and a 128 x 128 x 33 box."""
+    _need_gpu()
+    p, pos, q = W.config_small(0)
+    check(p.copy(uniform_fast=True), pos, q, tol, precision=precision, label="uniform fast small")
+    p2, pos2, q2 = small_jump(31, 200, L=32.0, H=8.0, eb=1.0, et=1.0)
+    check(p2.copy(uniform_fast=True), pos2, q2, tol, precision=precision, label="uniform fast 128x128x33")

@@ -56,6 +56,9 @@ CASES = {
     "small": lambda: W.config_small(0),
     "jump_tiles": lambda: jump_tiles(),
     "rect_box": lambda: jump_tiles(seed=2, n_pairs=60, eps_b=0.5, eps_t=0.05, Lx=16.0, Ly=8.0, H=6.0),
+    # the uniform-permittivity solver (domain [-H_E, H + H_E], no wall group)
+    "uniform_fast": lambda: (lambda t: (t[0].copy(eps_b=1.0, eps_t=1.0, uniform_fast=True), t[1], t[2]))(
+        jump_tiles(seed=3, n_pairs=90)),
 }
 
 

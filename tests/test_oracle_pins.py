@@ -336,3 +336,60 @@ def test_permittivity_scaling():
     U3, phi3, F3, _ = O.solve(p.copy(eps=3.0, eps_b=3 * p.eps_b, eps_t=3 * p.eps_t), pos, q)
     assert abs(3 * U3 - U) < 1e-12 * abs(U)
     assert np.abs(3 * F3 - F).max() < 1e-12 * np.abs(F).max()
+
+
+# --- the uniform-permittivity solver (no wall group, no images, no correction) ---
+
+def _fast_grid(L, H, nz=None):
+    p = _paper_grid(L, H, 1.0, 1.0)
+    d = O.derive(p)
+    # the z rule of Sec. 5.1 on the smaller domain [-H_E, H + H_E]
+    nz = nz or int(math.ceil(math.pi * (H + 2 * d["H_E"]) / (2 * d["h"])))
+    return p.copy(uniform_fast=True, Nz=nz)
+
+
+def test_fast_uniform_matches_ewald2d():
+    pos, q = charges(3, 4, 4, 4.0, 4.0, 0.3, 1.7)
+    p = _fast_grid(4.0, 2.0)
+    d = O.derive(p)
+    assert abs(d["a"] + d["H_E"]) < 1e-15 and abs(d["b"] - (2.0 + d["H_E"])) < 1e-15
+    U, phi, F, I = O.solve(p, pos, q)
+    Ut, pt, Et, p0, _ = truth.ewald2d(4.0, 4.0, 2.0, 1.0, 1.0, 1.0, pos, q, probes=[[0, 0, 0]])
+    Ft = q[:, None] * Et
+    assert np.sqrt(((F - Ft) ** 2).sum() / (Ft ** 2).sum()) < 3e-4
+    assert abs(U - Ut) < 5e-4 * 0.5 * np.sum(np.abs(q * pt))
+    assert np.abs(phi - (pt - p0[0])).max() < 2e-3 * np.abs(pt - p0[0]).mean()
+    # nothing corrected, one group
+    assert not np.any(I["c_o"]) and np.all(I["alpha"] == 0) and len(I["img_q"]) == 0
+    # the field of the neutral set vanishes at both ends: the two end slopes agree
+    assert abs(I["A_i1"] - I["A_i2"]) < 1e-3 * abs(I["A_i"]) + 1e-8
+    # and the general algorithm on its own domain reaches the same answer
+    Ug, phig, Fg, _ = O.solve(_paper_grid(4.0, 2.0, 1.0, 1.0), pos, q)
+    assert np.sqrt(((F - Fg) ** 2).sum() / (Fg ** 2).sum()) < 5e-4
+
+
+def test_fast_uniform_spectral_convergence_and_energy():
+    pos, q = charges(7, 4, 4, 4.0, 4.0, 0.3, 1.7)
+    _, _, Et = truth.ewald2d(4.0, 4.0, 2.0, 1.0, 1.0, 1.0, pos, q)
+    Ft = q[:, None] * Et
+    errs = []
+    for nz in (17, 25, 41):
+        _, _, F, _ = O.solve(_fast_grid(4.0, 2.0, nz=nz), pos, q)
+        errs.append(np.sqrt(((F - Ft) ** 2).sum() / (Ft ** 2).sum()))
+    assert errs[0] > 3 * errs[1] and errs[1] > errs[2] and errs[2] < 3e-4
+    # energy/force consistency (eqs. w1, w2)
+    p = _fast_grid(4.0, 2.0)
+    rng = np.random.default_rng(1)
+    dX = rng.standard_normal(pos.shape)
+    dX /= np.linalg.norm(dX, axis=1, keepdims=True)
+    d0 = 1e-4
+    Up = O.solve(p, pos + 0.5 * d0 * dX, q)[0]
+    Um = O.solve(p, pos - 0.5 * d0 * dX, q)[0]
+    W1 = -(Up - Um) / d0
+    W2 = float(np.sum(O.solve(p, pos, q)[2] * dX))
+    assert abs(W1 - W2) < 5e-4 * abs(W1)
+
+
+def test_fast_uniform_needs_equal_permittivities():
+    with pytest.raises(ValueError):
+        O.derive(_paper_grid(4.0, 2.0, 0.5, 1.0).copy(uniform_fast=True))

@@ -28,6 +28,8 @@ class SlabParams:
     Lengths share one unit; the Poisson equation is eps*Lap(phi) = -rho, so a
     point charge q at distance r in a uniform medium has potential q/(4*pi*eps*r).
     ``n_g = 0`` means the support is derived as 2*ceil(4.3*g_t/h).
+    ``uniform_fast`` selects the solver for equal permittivities inside and
+    outside (no wall group, no images, no correction, z domain [-H_E, H+H_E]).
     """
 
     Lx: float
@@ -45,6 +47,7 @@ class SlabParams:
     n_g: int = 0
     gauge: bool = True
     kmax_gt: bool = False
+    uniform_fast: bool = False
 
     def copy(self, **kw) -> "SlabParams":
         return dataclasses.replace(self, **kw)
