@@ -152,7 +152,11 @@ int dpse_plan_bind(dpse_plan* plan, void* workspace, int64_t bytes, void* stream
 /* Copies the derived quantities of a plan into *info. */
 int dpse_plan_info(const dpse_plan* plan, dpse_info* info);
 
-/* Enqueues one solve (Sec. 5.2.2 steps 1-7 plus the near field).
+/* Enqueues one solve (Sec. 5.2.2 steps 1-7 plus the near field). The near
+ * field needs only the binned charges: it runs on a stream private to the
+ * plan, forked from the plan's stream after binning and joined back before
+ * the gauge constant, concurrently with the far-field stages. */
+/* Arguments of dpse_solve:
  *   n      number of charges, 1 <= n <= max_n;
  *   pos    device, n x 3 row-major float64 (x, y, z); x, y are taken modulo Lx, Ly;
  *   q      device, n float64 charges;
@@ -169,7 +173,8 @@ int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
  * captures the solve's kernels into a graph (no allocation or memset node:
  * buffers are cleared by kernels) and instantiates it; later calls with the
  * same arguments only launch it, which removes the per-kernel launch cost for
- * small systems. Stage timing is not recorded for graph solves. Same
+ * small systems. Stage timing is not recorded for graph solves, and the near
+ * field runs on the capturing stream instead of the plan's side stream. Same
  * arguments, results and errors as dpse_solve. */
 int dpse_solve_graph(dpse_plan* plan, int64_t n, const double* pos, const double* q,
                      double* energy, double* phi, double* force);

@@ -141,7 +141,11 @@ struct dpse_plan {
   int spread_cfg = -1;
   int interp_cfg = -1;
   int column_cfg = -1;   // modes per column block (kColumnKE of k_column.hip)
-  // per-stage timing: one row of DPSE_NUM_STAGES + 1 events per recorded solve
+  // the near field runs on `side`, forked from and joined back into `stream`
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool capturing = false;  // inside a graph capture: no fork
+  // per-stage timing: one row of 2 DPSE_NUM_STAGES events (start, end) per recorded solve
   bool timing = false;
   std::vector<hipEvent_t> events;
   int timed_solves = 0;
@@ -158,7 +162,9 @@ template <typename R> hipError_t launch_column(dpse_plan* p);
 template <typename R> hipError_t launch_fft_inverse(dpse_plan* p);
 template <typename R> hipError_t launch_interp(dpse_plan* p, int64_t n);
 template <typename R> hipError_t launch_near(dpse_plan* p, int64_t n);
-template <typename R> hipError_t launch_gauge(dpse_plan* p, int64_t n);
+template <typename R> hipError_t launch_gauge_far(dpse_plan* p);
+hipError_t launch_near_origin(dpse_plan* p, int64_t n);
+hipError_t launch_gauge_final(dpse_plan* p, int64_t n);
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
                            double* phi, double* force);
 

@@ -420,11 +420,18 @@ hipError_t launch_near(dpse_plan* p, int64_t n) {
   return hipGetLastError();
 }
 
-// near part of the gauge; the far part (scal[4]) is written by the grid kernels
-hipError_t launch_gauge_near(dpse_plan* p, int64_t n) {
+// Near part of the gauge: per-block partials at the origin (independent of
+// the far field, so it can run beside it).
+hipError_t launch_near_origin(dpse_plan* p, int64_t n) {
   int nb = blocks_for(n, p->npartials);
   hipLaunchKernelGGL(k_near_origin, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.ext,
                      p->w.partials);
+  return hipGetLastError();
+}
+
+// Gauge constant from the near partials and the far per-node partials.
+hipError_t launch_gauge_final(dpse_plan* p, int64_t n) {
+  int nb = blocks_for(n, p->npartials);
   hipLaunchKernelGGL(k_gauge_final, dim3(1), dim3(64), 0, p->stream, p->g, nb, (const double*)p->w.partials,
                      (const double*)(p->w.partials + 2 * p->npartials), p->w.scal);
   return hipGetLastError();

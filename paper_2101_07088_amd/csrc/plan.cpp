@@ -211,6 +211,12 @@ size_t carve_tables(dpse_plan* p, char* base) {
 void free_all(dpse_plan* p) {
   if (p->graph_exec) (void)hipGraphExecDestroy(p->graph_exec);
   p->graph_exec = nullptr;
+  if (p->side) (void)hipStreamSynchronize(p->side);
+  if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
+  if (p->join_ev) (void)hipEventDestroy(p->join_ev);
+  if (p->side) (void)hipStreamDestroy(p->side);
+  p->side = nullptr;
+  p->fork_ev = p->join_ev = nullptr;
   for (void* a : p->allocs) (void)hipFree(a);
   p->allocs.clear();
 }
@@ -406,6 +412,9 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
   int zero4[4] = {0, 0, 0, 0};
   if (p->bound) H2D(w.status, zero4, sizeof(zero4));
   if (e == hipSuccess) e = dpse::prepare_kernels();
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
   // factorise the per-mode chains once (they depend on the plan only), on a
   // private stream so that work already queued on other streams is not waited for
   if (e == hipSuccess) {
@@ -469,6 +478,56 @@ int dpse_plan_info(const dpse_plan* plan, dpse_info* info) {
 static const char* kStageNames[DPSE_NUM_STAGES] = {
     "prep", "bin", "spread", "fft_forward", "column", "fft_inverse", "interp", "near", "gauge", "finalize"};
 
+}  // extern "C"
+
+// One solve: prep and binning, then the near field on the plan's side stream
+// (it needs only the cell list) while the far-field stages run on the plan's
+// stream, joined before the gauge constant and the outputs.
+template <typename R>
+static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,
+                               double* phi, double* force, hipEvent_t* ev) {
+  hipError_t e = hipSuccess;
+  hipStream_t main = p->stream;
+  auto start = [&](int st, hipStream_t s) {
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[2 * st], s);
+  };
+  auto end = [&](int st, hipStream_t s) {
+    if (ev && e == hipSuccess) e = hipEventRecord(ev[2 * st + 1], s);
+  };
+  auto run = [&](hipError_t (*f)(dpse_plan*)) {
+    if (e == hipSuccess) e = f(p);
+  };
+  start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
+  start(1, main); if (e == hipSuccess) e = dpse::launch_bin(p, n); end(1, main);
+  // fork the near field (stage 7) and its part of the gauge; inside a graph
+  // capture they stay on the capturing stream (see dpse_solve_graph)
+  const bool fork = !p->capturing;
+  hipStream_t ns = fork ? p->side : main;
+  if (fork && e == hipSuccess) e = hipEventRecord(p->fork_ev, main);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
+  p->stream = ns;
+  start(7, ns);
+  if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
+  if (e == hipSuccess) e = dpse::launch_near_origin(p, n);
+  end(7, ns);
+  if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
+  p->stream = main;
+  start(2, main); run(dpse::launch_spread<R>); end(2, main);
+  start(3, main); run(dpse::launch_fft_forward<R>); end(3, main);
+  start(4, main); run(dpse::launch_column<R>); end(4, main);
+  start(5, main); run(dpse::launch_fft_inverse<R>); end(5, main);
+  start(6, main); if (e == hipSuccess) e = dpse::launch_interp<R>(p, n); end(6, main);
+  start(8, main);
+  run(dpse::launch_gauge_far<R>);
+  if (fork && e == hipSuccess) e = hipStreamWaitEvent(main, p->join_ev, 0);
+  if (e == hipSuccess) e = dpse::launch_gauge_final(p, n);
+  end(8, main);
+  start(9, main); if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force); end(9, main);
+  return e;
+}
+
+extern "C" {
+
 static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* q,
                       double* energy, double* phi, double* force) {
   if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
@@ -478,45 +537,19 @@ static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* 
     if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
   }
   p->last_n = n;
-  const bool mixed = p->prm.precision == DPSE_MIXED;
   hipEvent_t* ev = nullptr;
   if (p->timing) {
-    size_t need = (size_t)(p->timed_solves + 1) * (DPSE_NUM_STAGES + 1);
+    size_t need = (size_t)(p->timed_solves + 1) * (2 * DPSE_NUM_STAGES);
     while (p->events.size() < need) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return DPSE_EHIP;
       p->events.push_back(e);
     }
-    ev = p->events.data() + (size_t)p->timed_solves * (DPSE_NUM_STAGES + 1);
+    ev = p->events.data() + (size_t)p->timed_solves * (2 * DPSE_NUM_STAGES);
     p->timed_solves++;
   }
-  int stage = 0;
-  hipError_t e = hipSuccess;
-  auto mark = [&]() {
-    if (ev && e == hipSuccess) e = hipEventRecord(ev[stage], p->stream);
-    ++stage;
-  };
-  mark();
-  e = e == hipSuccess ? dpse::launch_prep(p, n, pos, q) : e; mark();
-  e = e == hipSuccess ? dpse::launch_bin(p, n) : e; mark();
-  if (mixed) {
-    e = e == hipSuccess ? dpse::launch_spread<float>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_fft_forward<float>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_column<float>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_fft_inverse<float>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_interp<float>(p, n) : e; mark();
-    e = e == hipSuccess ? dpse::launch_near<float>(p, n) : e; mark();
-    e = e == hipSuccess ? dpse::launch_gauge<float>(p, n) : e; mark();
-  } else {
-    e = e == hipSuccess ? dpse::launch_spread<double>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_fft_forward<double>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_column<double>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_fft_inverse<double>(p) : e; mark();
-    e = e == hipSuccess ? dpse::launch_interp<double>(p, n) : e; mark();
-    e = e == hipSuccess ? dpse::launch_near<double>(p, n) : e; mark();
-    e = e == hipSuccess ? dpse::launch_gauge<double>(p, n) : e; mark();
-  }
-  e = e == hipSuccess ? dpse::launch_finalize(p, n, q, energy, phi, force) : e; mark();
+  hipError_t e = p->prm.precision == DPSE_MIXED ? solve_stages<float>(p, n, pos, q, energy, phi, force, ev)
+                                                : solve_stages<double>(p, n, pos, q, energy, phi, force, ev);
   return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
 }
 
@@ -547,6 +580,7 @@ int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q
     bool timing = p->timing;
     p->stream = cs;
     p->timing = false;
+    p->capturing = true;
     hipGraph_t graph = nullptr;
     int st = DPSE_OK;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) st = DPSE_EHIP;
@@ -554,6 +588,7 @@ int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     p->stream = keep;
     p->timing = timing;
+    p->capturing = false;
     if (own_stream) (void)hipStreamDestroy(cs);
     if (st != DPSE_OK || ec != hipSuccess || graph == nullptr) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -613,10 +648,12 @@ int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n
     bool timing = p->timing;
     p->stream = st[b];
     p->timing = false;
+    p->capturing = true;
     status = solve_impl(p, n[i], pos[i], q[i], energy ? energy[i] : nullptr, phi ? phi[i] : nullptr,
                         force ? force[i] : nullptr);
     p->stream = keep;
     p->timing = timing;
+    p->capturing = false;
   }
   // join
   for (int b = 0; b < n_branches && status == DPSE_OK; ++b) {
@@ -802,10 +839,10 @@ int dpse_stage_times(dpse_plan* p, double* ms, int max_stages, int* n_solves) {
   const int ns = DPSE_NUM_STAGES;
   std::vector<double> acc(ns, 0.0);
   for (int s = 0; s < p->timed_solves; ++s) {
-    hipEvent_t* ev = p->events.data() + (size_t)s * (ns + 1);
+    hipEvent_t* ev = p->events.data() + (size_t)s * (2 * ns);
     for (int k = 0; k < ns; ++k) {
       float t = 0.0f;
-      if (hipEventElapsedTime(&t, ev[k], ev[k + 1]) != hipSuccess) return DPSE_EHIP;
+      if (hipEventElapsedTime(&t, ev[2 * k], ev[2 * k + 1]) != hipSuccess) return DPSE_EHIP;
       acc[k] += t;
     }
   }
