@@ -44,7 +44,7 @@ def stage_bytes(p, info_band_frac, s):
 
 SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4)]
 INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4)]
-COLUMN_BLOCKS = [2048, 1024, 4096]
+COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512)]  # (KE, threads)
 
 
 def kernel_name(stage, tiles, mixed):
@@ -60,7 +60,8 @@ def kernel_name(stage, tiles, mixed):
         t, pz = INTERP_SHAPES[i]
         return f"k_interp{'_gather' if i >= 5 else ''}<{r},{t},{pz}>"
     if stage == "column":
-        return f"k_column<{r},{COLUMN_BLOCKS[tiles[2]]}>"
+        ke, nt = COLUMN_SHAPES[tiles[2]]
+        return f"k_column<{r},{ke},{nt}>"
     return None
 
 

@@ -106,6 +106,18 @@ __global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __res
   }
 }
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8)
+// and every XCD has an L2 of its own. Neighbouring mode blocks share the
+// 128-byte lines of each z row of the spectra and of the pivots, so the
+// block index is remapped to give every XCD one contiguous run of mode
+// blocks, taken in dispatch order: the lines two blocks share then meet in
+// one L2 instead of being fetched from HBM by two. A bijection on [0, nb).
+__device__ inline int xcd_block(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
+  return x * per + min(x, extra) + b / kXcd;
+}
+
 template <typename R, int KE, int NT>
 __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                      const typename CT<R>::T* __restrict__ fx_o,
@@ -135,7 +147,7 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
   const int logMB = ilog2d(KE) - logM;
   const int NU = N + 2;
   const int nmodes = g.Ny * g.nkx;
-  const int m0 = blockIdx.x * MB;
+  const int m0 = xcd_block(blockIdx.x, gridDim.x) * MB;
   const int tid = threadIdx.x;
   const double Rz = g.zR;
   for (int i = tid; i < kCtabRows * N; i += NT) lco[i] = ctab[i];
@@ -631,7 +643,7 @@ void column_as(dpse_plan* p) {
 }
 }  // namespace
 
-bool g_column_ok[kNumColumn] = {true, true, true};
+bool g_column_ok[kNumColumn] = {};  // set by prepare_kernels
 
 int column_candidates() { return kNumColumn; }
 
