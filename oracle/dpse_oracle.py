@@ -24,7 +24,17 @@ Readings of points the paper leaves open (the HIP path takes the same ones):
     z < 2H_E, top image for z > H-2H_E; zero-strength images skipped;
   * near field: strict r < r_cut, minimal image in x,y, one image per wall for
     every charge (its own included);
-  * A_i(0) is the mean of its two formulas; gauge constant added to phi directly.
+  * A_i(0) is the mean of its two formulas; gauge constant added to phi directly;
+  * wall charges: sigma_b, sigma_t are given by their values at the x,y grid
+    points and enter only the correction (eqs. mm2, mm4) and A_i (eqs. ai1,
+    ai2); the wall integral of eq. Ufinal is taken by reciprocity: with
+    phi_s the potential of the walls alone (the correction with m_phi = 0 and
+    m_E = +sigma_b, -sigma_t, plus its k = 0 slope) and B_i the gauge constant,
+    int sigma phi = sum_k q_k phi_s(z_k) + int sigma phi_s + B_i int sigma,
+    where phi_s(z_k) is the S-bar average of phi_s on the grid (phi_s is
+    harmonic, so the average is the point value) and int sigma phi_s is the
+    trapezoid sum over the wall grid points. ``wall_energy_literal`` takes the
+    integral as written instead (pins only).
 """
 from __future__ import annotations
 
@@ -447,43 +457,97 @@ def _near_targets(p, d, pos, q, tt):
     return out
 
 
-def near_at_origin(p, d, pos, q):
-    """Pointwise near-field potential at x = 0 (Sec. 5.2.2, gauge paragraph):
-    kernel G^(n)(r; g_w, xi) of eq. Gnear over charges and their first images,
-    truncated at r_cut."""
+def near_at_points(p, d, pos, q, pts):
+    """Pointwise near-field potential at the points pts [m, 3] (Sec. 5.2.2,
+    gauge paragraph): kernel G^(n)(r; g_w, xi) of eq. Gnear over the charges
+    and their first images, truncated at r_cut, minimal image in x, y."""
     xi_p = 1.0 / math.sqrt(2.0 * p.g_w ** 2 + 1.0 / p.xi ** 2)
-    tot = 0.0
+    pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+    tot = np.zeros(len(pts))
     srcs = [(pos[:, 2], q)]
     if d["gamma_b"] != 0.0:
         srcs.append((-pos[:, 2], d["gamma_b"] * q))
     if d["gamma_t"] != 0.0:
         srcs.append((2 * p.H - pos[:, 2], d["gamma_t"] * q))
-    dx = -pos[:, 0] - p.Lx * np.round(-pos[:, 0] / p.Lx)
-    dy = -pos[:, 1] - p.Ly * np.round(-pos[:, 1] / p.Ly)
+    dx = pts[:, None, 0] - pos[None, :, 0]
+    dy = pts[:, None, 1] - pos[None, :, 1]
+    dx -= p.Lx * np.round(dx / p.Lx)
+    dy -= p.Ly * np.round(dy / p.Ly)
     for zs, qs in srcs:
-        r = np.sqrt(dx * dx + dy * dy + zs * zs)
-        m = r < p.r_cut
-        rr = r[m]
+        dz = pts[:, None, 2] - zs[None, :]
+        r = np.sqrt(dx * dx + dy * dy + dz * dz)
+        ti, sj = np.nonzero(r < p.r_cut)
+        rr = r[ti, sj]
         if p.g_w > 0.0:
             G = (scipy.special.erf(rr / (math.sqrt(2.0) * p.g_w)) - scipy.special.erf(xi_p * rr)) / rr
         else:
             G = scipy.special.erfc(xi_p * rr) / rr
-        tot += float(np.sum(qs[m] * G))
+        np.add.at(tot, ti, qs[sj] * G)
     return tot / (FOUR_PI * p.eps)
+
+
+def near_at_origin(p, d, pos, q):
+    """Pointwise near-field potential at x = 0 (the gauge point)."""
+    return float(near_at_points(p, d, pos, q, np.zeros((1, 3)))[0])
+
+
+def gamma_half(p, r2):
+    """The kernel gamma^{1/2} of eq. lapsplit (std 1/(2 xi)): averaging the
+    far-field grid with it gives the pointwise far-field potential."""
+    xi = p.xi
+    return (8.0 * xi ** 3 / (2.0 * math.pi) ** 1.5) * np.exp(-2.0 * xi * xi * r2)
+
+
+# ---------------------------------------------------------------------------
+# Wall charges (Sec. 2 eqs. rho, cbc2, cbc4; Sec. 4.3.3 eqs. mm2, mm4;
+# Sec. 4.3.4 eqs. ai1, ai2; eq. Ufinal)
+# ---------------------------------------------------------------------------
+
+def wall_densities(p, sigma_b, sigma_t):
+    """The wall densities at the x,y grid points [Ny, Nx] (None: no charge)
+    and their Fourier coefficients with the normalisation of fft_xy."""
+    sb = np.zeros((p.Ny, p.Nx)) if sigma_b is None else np.asarray(sigma_b, dtype=np.float64)
+    st = np.zeros((p.Ny, p.Nx)) if sigma_t is None else np.asarray(sigma_t, dtype=np.float64)
+    if sb.shape != (p.Ny, p.Nx) or st.shape != (p.Ny, p.Nx):
+        raise ValueError("wall densities are sampled on the Ny x Nx grid points")
+    return sb, st, np.fft.rfft2(sb) / (p.Nx * p.Ny), np.fft.rfft2(st) / (p.Nx * p.Ny)
+
+
+def wall_energy_literal(p, pos, q, phi, sigma_b, sigma_t, inter):
+    """U of eq. Ufinal with the wall integrals as written: the pointwise
+    potential at every wall grid point is the gamma^{1/2} average of the
+    far-field grid, plus the pointwise near field of the charges and their
+    images, plus B_i; the integrals are trapezoid sums h^2 sum sigma phi."""
+    d = inter["derived"]
+    sb, st, _, _ = wall_densities(p, sigma_b, sigma_t)
+    X, Y = np.meshgrid(np.arange(p.Nx) * d["h"], np.arange(p.Ny) * d["h"])
+    wall = 0.0
+    for zw, sig in ((0.0, sb), (p.H, st)):
+        pts = np.stack([X.ravel(), Y.ravel(), np.full(X.size, zw)], axis=1)
+        far = interp(p, d, inter["grids"][:1], pts, kernel_r2=lambda rr: gamma_half(p, rr))[:, 0]
+        near = near_at_points(p, d, pos, q, pts)
+        wall += d["h"] ** 2 * float(np.sum(sig.ravel() * (far + near + inter["B_i"])))
+    return 0.5 * float(np.sum(q * phi)) + 0.5 * wall
 
 
 # ---------------------------------------------------------------------------
 # The whole solve (Sec. 5.2.2 steps 1-7, field paragraph, gauge paragraph)
 # ---------------------------------------------------------------------------
 
-def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarray]]:
+def solve(p, pos, q, timings=None, near_rows=None, sigma_b=None, sigma_t=None
+          ) -> Tuple[float, np.ndarray, np.ndarray, Dict[str, np.ndarray]]:
     """The whole solve. ``timings`` (a dict) receives wall seconds of the far
-    and near parts; ``near_rows`` is passed to near_field (timing samples only)."""
+    and near parts; ``near_rows`` is passed to near_field (timing samples only);
+    ``sigma_b``, ``sigma_t`` are wall charge densities at the x,y grid points."""
     import time
     t_start = time.perf_counter()
     pos = np.asarray(pos, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
     d = derive(p)
+    walls = sigma_b is not None or sigma_t is not None
+    if walls and d["fast"]:
+        raise ValueError("wall charges need the correction solve; the uniform-permittivity solver has none")
+    sb, st, sbh, sth = wall_densities(p, sigma_b, sigma_t)
     N = p.Nz
     R = d["R"]
     # step 1: groups and images
@@ -507,9 +571,9 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
     # step 4: mismatches (eqs. mm1-mm4 with psi_b* = tau_b psi_o*, psi_t* = tau_t psi_o*)
     tb, tt = d["tau_b"], d["tau_t"]
     mphi_b = v_i0 - tb * v_o0
-    mE_b = p.eps * d_i0 - p.eps_b * tb * d_o0
+    mE_b = p.eps * d_i0 - p.eps_b * tb * d_o0 + sbh     # eq. mm2
     mphi_t = v_iH - tt * v_oH
-    mE_t = p.eps * d_iH - p.eps_t * tt * d_oH
+    mE_t = p.eps * d_iH - p.eps_t * tt * d_oH - sth     # eq. mm4
     kabs = d["kabs"]
     act = d["keep"] & (kabs > 0.0)
     alpha = np.zeros_like(v_i0)
@@ -548,8 +612,8 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
         dk0_ob = series_dz_at(y_o[:, 0, 0], 1.0, R)
         A_b = -tb * dk0_oa
         A_t = -tt * dk0_ob
-        A_i1 = (p.eps_b * (tb * d_o0[0, 0] + A_b) - p.eps * d_i0[0, 0]) / p.eps
-        A_i2 = (p.eps_t * (tt * d_oH[0, 0] + A_t) - p.eps * d_iH[0, 0]) / p.eps
+        A_i1 = (p.eps_b * (tb * d_o0[0, 0] + A_b) - p.eps * d_i0[0, 0] - sbh[0, 0].real) / p.eps
+        A_i2 = (p.eps_t * (tt * d_oH[0, 0] + A_t) - p.eps * d_iH[0, 0] + sth[0, 0].real) / p.eps
         A_i = 0.5 * (A_i1 + A_i2)
     # step 6: potential and z-derivative at the nodes (series plus correction)
     Psi = cheb_eval_nodes(y_i, N) + psi_c
@@ -568,10 +632,7 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
     t_near = time.perf_counter() - t_near
     # gauge phi(0) = 0 (Sec. 5.2.2): pointwise near + gamma^{1/2}-averaged far at the origin
     if p.gauge:
-        xi = p.xi
-        def g_half(r2):
-            return (8.0 * xi ** 3 / (2.0 * math.pi) ** 1.5) * np.exp(-2.0 * xi * xi * r2)
-        far0 = interp(p, d, grids[:1], np.zeros((1, 3)), kernel_r2=g_half)[0, 0]
+        far0 = interp(p, d, grids[:1], np.zeros((1, 3)), kernel_r2=lambda rr: gamma_half(p, rr))[0, 0]
         near0 = near_at_origin(p, d, pos, q)
         B_i = -(far0 + near0)
     else:
@@ -583,6 +644,37 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
     E = far[:, 1:] + near[:, 1:]
     F = q[:, None] * E
     U = 0.5 * float(np.sum(q * phi))
+    wall_terms = {}
+    if walls:
+        # the walls alone: the correction with m_phi = 0, m_E = +sigma_b, -sigma_t
+        # and the k = 0 slope of eqs. ai1, ai2 without charges (mean of the two)
+        al_s = np.zeros_like(alpha)
+        be_s = np.zeros_like(beta)
+        if np.any(act):
+            zk = np.zeros(int(np.count_nonzero(act)), dtype=complex)
+            a_, b_, _, _ = correction_coeffs(p, kabs[act], zk, sbh[act], zk, -sth[act])
+            al_s[act] = a_
+            be_s[act] = b_
+        A_s = (sth[0, 0].real - sbh[0, 0].real) / (2.0 * p.eps)
+        Psi_s = al_s[None] * e1 + be_s[None] * e2
+        Psi_s[:, ~act] = 0.0
+        Psi_s[:, 0, 0] += A_s * z
+        phi_s = ifft_xy(Psi_s, p)
+        phi_s_q = interp(p, d, phi_s[None], pos)[:, 0]
+        Eh = np.exp(-kabs * p.H)
+        on_b = np.where(act, al_s * Eh + be_s, 0.0)
+        on_t = np.where(act, al_s + be_s * Eh, 0.0)
+        on_t[0, 0] = A_s * p.H
+        phi_s_b = ifft_xy(on_b[None], p)[0]
+        phi_s_t = ifft_xy(on_t[None], p)[0]
+        hh = d["h"] ** 2
+        W_ss = hh * float(np.sum(sb * phi_s_b + st * phi_s_t))
+        Q_s = hh * float(np.sum(sb + st))
+        E_qs = float(np.sum(q * phi_s_q))
+        U += 0.5 * (E_qs + W_ss + B_i * Q_s)
+        wall_terms = dict(sigma_b_hat=sbh, sigma_t_hat=sth, alpha_s=al_s, beta_s=be_s, A_s=A_s,
+                          phi_s=phi_s, phi_s_q=phi_s_q, phi_s_b=phi_s_b, phi_s_t=phi_s_t,
+                          E_qs=E_qs, W_ss=W_ss, Q_s=Q_s)
     if timings is not None:
         timings["near"] = t_near
         timings["far"] = time.perf_counter() - t_start - t_near
@@ -590,5 +682,5 @@ def solve(p, pos, q, timings=None, near_rows=None) -> Tuple[float, np.ndarray, n
                  y_o=y_o, y_i=y_i, mphi_b=mphi_b, mE_b=mE_b, mphi_t=mphi_t, mE_t=mE_t,
                  alpha=alpha, beta=beta, A_i=A_i, A_i1=A_i1, A_i2=A_i2, Psi=Psi,
                  Psi_z=Psi_z, grids=grids, far=far, near=near, B_i=B_i, far0=far0,
-                 near0=near0, c_o=c_o, img_pos=ipos, img_q=iq, derived=d)
+                 near0=near0, c_o=c_o, img_pos=ipos, img_q=iq, derived=d, **wall_terms)
     return U, phi, F, inter

@@ -393,3 +393,105 @@ def test_fast_uniform_spectral_convergence_and_energy():
 def test_fast_uniform_needs_equal_permittivities():
     with pytest.raises(ValueError):
         O.derive(_paper_grid(4.0, 2.0, 0.5, 1.0).copy(uniform_fast=True))
+
+
+# --- wall charges (Sec. 2 eqs. cbc2, cbc4; Sec. 4.3.3 eqs. mm2, mm4; ai1, ai2; eq. Ufinal)
+
+def _wall_box(eps_b, eps_t, eps=1.0, N=32, Nz=33, L=8.0, H=4.0):
+    p = SlabParams(Lx=L, Ly=L, H=H, eps=eps, eps_b=eps_b, eps_t=eps_t, xi=1.0, Nx=N, Ny=N, Nz=Nz, r_cut=2.0)
+    pos, q = charges(1, 4, 4, L, L, 1.0, H - 1.0)
+    h = L / N
+    X, Y = np.meshgrid(np.arange(N) * h, np.arange(N) * h)
+    return p, pos, q, X, Y
+
+
+@pytest.mark.parametrize("eps_side", [1.0, 0.05, 20.0])
+def test_wall_sheet_matches_textbook_single_interface(eps_side):
+    """A sheet s cos(k x) on the bottom wall with no jump at the top: inside the
+    slab the potential is s/(k (eps + eps_b)) e^{-k z} cos(k x), the textbook
+    field of a charged interface between two half-spaces; mirrored for a sheet
+    on the top wall (potential s/(k (eps + eps_t)) e^{-k (H - z)} cos(k x))."""
+    k = 2.0 * math.pi * 2 / 8.0
+    s = 0.3
+    p, pos, q, X, Y = _wall_box(eps_side, 1.0)
+    _, _, _, I = O.solve(p, pos, q, sigma_b=s * np.cos(k * X))
+    z = I["derived"]["z"]
+    ins = (z >= 0) & (z <= p.H)
+    ref = s / ((p.eps + eps_side) * k) * np.exp(-k * z)[:, None, None] * np.cos(k * X)[None]
+    assert np.abs(I["phi_s"][ins] - ref[ins]).max() < 1e-12
+    p, pos, q, X, Y = _wall_box(1.0, eps_side)
+    _, _, _, I = O.solve(p, pos, q, sigma_t=s * np.cos(k * Y))
+    ref = s / ((p.eps + eps_side) * k) * np.exp(-k * (p.H - z))[:, None, None] * np.cos(k * Y)[None]
+    assert np.abs(I["phi_s"][ins] - ref[ins]).max() < 1e-12
+
+
+@pytest.mark.parametrize("eps_b,eps_t", [(0.05, 20.0), (1.0, 1.0), (20.0, 0.05)])
+def test_wall_capacitor_field(eps_b, eps_t):
+    """Uniform +s on the bottom wall and -s on the top: the field inside is the
+    parallel-plate field s/eps along +z whatever the outer permittivities, and
+    every charge's force changes by exactly q s / eps along z (up to the
+    truncation of the interpolation kernel)."""
+    s = 0.2
+    p, pos, q, X, Y = _wall_box(eps_b, eps_t, eps=2.0, Nz=65)   # nodes fine enough for the kernel's mass
+    N = p.Nx
+    _, _, F0, _ = O.solve(p, pos, q)
+    _, _, F1, I = O.solve(p, pos, q, sigma_b=np.full((N, N), s), sigma_t=np.full((N, N), -s))
+    assert abs(I["A_s"] - (-s / p.eps)) < 1e-14
+    dF = F1 - F0
+    assert np.abs(dF[:, :2]).max() < 1e-10
+    assert np.allclose(dF[:, 2], q * s / p.eps, rtol=1e-4, atol=0)
+
+
+def test_wall_energy_reciprocity_matches_literal_integral():
+    """The energy with wall charges by reciprocity (the oracle's route) equals
+    eq. Ufinal with the wall integrals taken as written: the pointwise
+    potential (gamma^{1/2} average of the far field, pointwise near field of
+    the charges and their images, gauge constant) summed over the wall grid
+    points. The wall part is about a third of U here."""
+    import workloads as W
+    p, pos, q, sb, st = W.config_charged_walls(0, g_w=1e-2)
+    U, phi, F, I = O.solve(p, pos, q, sigma_b=sb, sigma_t=st)
+    Ul = O.wall_energy_literal(p, pos, q, phi, sb, st, I)
+    wall = 0.5 * (I["E_qs"] + I["W_ss"] + I["B_i"] * I["Q_s"])
+    assert abs(wall) > 0.2 * abs(U)
+    assert abs(U - Ul) < 1e-5 * abs(U)
+
+
+def _rate_of_work(p, pos, q, sb, st, seed=7, d0=1e-4, walls=True):
+    rng = np.random.default_rng(seed)
+    dX = rng.normal(size=pos.shape)
+    dX /= np.linalg.norm(dX, axis=1)[:, None]
+    kw = dict(sigma_b=sb, sigma_t=st)
+    U, phi, F, _ = O.solve(p, pos, q, **kw)
+    up = O.solve(p, pos + 0.5 * d0 * dX, q, **kw)
+    um = O.solve(p, pos - 0.5 * d0 * dX, q, **kw)
+    if walls:
+        W1 = -(up[0] - um[0]) / d0
+    else:  # the particle term of eq. Ufinal alone
+        W1 = -(0.5 * np.sum(q * up[1]) - 0.5 * np.sum(q * um[1])) / d0
+    W2 = float(np.sum(F * dX))
+    return W1, W2
+
+
+def test_wall_energy_is_the_potential_of_the_forces():
+    """The charged-wall energy test of Sec. 6.3 (eqs. w1, w2): the rate of work
+    of the forces equals the finite-difference rate of work of the energy at
+    least as closely as the paper's own table (tests/golden/energslabEw.txt),
+    and leaving out the wall integral of eq. Ufinal breaks it."""
+    import workloads as W
+    for gw, printed in _rows("energslabEw.txt"):
+        gw, printed = float(gw), float(printed)
+        if gw not in (1e-2, 1e-10):
+            continue
+        p, pos, q, sb, st = W.config_charged_walls(0, g_w=gw)
+        W1, W2 = _rate_of_work(p, pos, q, sb, st)
+        assert abs(W1 - W2) <= printed * abs(W1), (gw, W1, W2)
+    p, pos, q, sb, st = W.config_charged_walls(0, g_w=1e-2)
+    W1, W2 = _rate_of_work(p, pos, q, sb, st, walls=False)
+    assert abs(W1 - W2) > 1e-2 * abs(W2)
+
+
+def test_walls_rejected_by_the_uniform_solver():
+    p, pos, q, X, Y = _wall_box(1.0, 1.0)
+    with pytest.raises(ValueError):
+        O.solve(p.copy(uniform_fast=True), pos, q, sigma_b=np.zeros((p.Ny, p.Nx)))

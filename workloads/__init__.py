@@ -116,6 +116,36 @@ def scaled_jump(seed: int, L: float, H: float, n_pairs: int, eps_b: float = 0.05
     return p, pos, q
 
 
+def gaussian_walls(p: SlabParams, s: float, sign_b: float = 1.0, sign_t: float = -1.0,
+                   center: Tuple[float, float] | None = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Wall charge densities sampled at the x,y grid points [Ny, Nx]: a
+    Gaussian of standard deviation s and unit total charge times sign on each
+    wall, sigma = sign/(2 pi s^2) exp(-r^2/(2 s^2)) with r the periodic
+    distance to ``center`` (the box centre by default). The charged-wall test
+    of the paper takes +-1/2 of that on the two walls."""
+    h = p.Lx / p.Nx
+    cx, cy = center if center is not None else (0.5 * p.Lx, 0.5 * p.Ly)
+    dx = np.arange(p.Nx) * h - cx
+    dy = np.arange(p.Ny) * h - cy
+    dx -= p.Lx * np.round(dx / p.Lx)
+    dy -= p.Ly * np.round(dy / p.Ly)
+    g = np.exp(-(dy[:, None] ** 2 + dx[None, :] ** 2) / (2.0 * s * s)) / (2.0 * math.pi * s * s)
+    return sign_b * g, sign_t * g
+
+
+def config_charged_walls(seed: int = 0, g_w: float = 1e-2, n: int = 10, Nx: int = 32, Nz: int = 129):
+    """The charged-wall energy test: box 2 x 2 x 1, eps = 1, eps_b = 1/20,
+    eps_t = 1/50, xi = 6.8, n unit charges of alternating sign uniform in
+    [0,2)^2 x [4.5 g_w, 1 - 4.5 g_w], Gaussian wall densities of s = 0.2 and
+    total charge +1/2 (bottom) and -1/2 (top) at the box centre, r_cut = 0.53.
+    Returns (params, pos, q, sigma_b, sigma_t)."""
+    p = SlabParams(Lx=2.0, Ly=2.0, H=1.0, eps=1.0, eps_b=1.0 / 20.0, eps_t=1.0 / 50.0, xi=6.8,
+                   Nx=Nx, Ny=Nx, Nz=Nz, r_cut=0.53, g_w=g_w)
+    pos, q = charges(seed, n // 2, n // 2, 2.0, 2.0, 4.5 * g_w, 1.0 - 4.5 * g_w)
+    sb, st = gaussian_walls(p, 0.2)
+    return p, pos, q, 0.5 * sb, 0.5 * st
+
+
 def batch_systems(n_sys: int = 64, seed0: int = 1000) -> List[Tuple[SlabParams, np.ndarray, np.ndarray]]:
     """Uneven independent slabs: N log-uniform in [1024, 65536] (even, +-1),
     L in {32,64,128}, H in {16,32,64}, eps_b, eps_t drawn from {0.05,1,20}
