@@ -9,7 +9,9 @@
  *   - the averaged potential phibar_k at each charge     (eq. pbar), and
  *   - the force F_k = q_k Ebar(z_k)                      (eq. fqE),
  * with the Poisson equation eps*Lap(phi) = -rho (eq. poiss) and the jump
- * conditions of eqs. cbc1-cbc4 (no wall charges). The method is the paper's
+ * conditions of eqs. cbc1-cbc4, with optional fixed charge densities on the
+ * walls (eq. rho; dpse_plan_set_walls), whose wall integral then joins U as
+ * in eq. Ufinal. The method is the paper's
  * Ewald split (Sec. 3.2) into a localized near field summed over pairs
  * (Sec. 4.2) and a smooth far field solved on a grid that is Fourier in x,y
  * and Chebyshev in z, with images of charges near the walls and a harmonic
@@ -17,7 +19,8 @@
  * Sec. 5.2.2 steps 1-7, per-mode boundary value solver of App. A).
  *
  * Units: a point charge q at distance r in a uniform medium has potential
- * q/(4 pi eps r). The set of charges must be exactly neutral (Sec. 7).
+ * q/(4 pi eps r). The charges and the wall charge densities together must
+ * be exactly neutral (eq. elecneu).
  *
  * Conventions fixed by this library where the paper is silent:
  *   - g_w = 0 gives point charges; the self potential of each charge is
@@ -55,7 +58,7 @@ enum {
   DPSE_EINVAL = 1,      /* invalid argument or parameters                        */
   DPSE_ENOMEM = 2,      /* device allocation failed                              */
   DPSE_EHIP = 3,        /* a HIP runtime call failed                             */
-  DPSE_ENONNEUTRAL = 4, /* |sum q| > 1e-12 sum |q|  (device-detected)            */
+  DPSE_ENONNEUTRAL = 4, /* |sum q + int sigma| > 1e-12 (sum |q| + int |sigma|)  (device-detected) */
   DPSE_EOUTSIDE = 5,    /* a charge with z outside (n_sigma g_w, H - n_sigma g_w), or a non-finite coordinate (device-detected) */
   DPSE_ECONSTRAINT = 6, /* r_cut >= H + h_min or 2 H_E >= H + h_min, h_min the smallest distance of a charge to a wall (Sec. 4.2, 5.3; device-detected) */
   DPSE_ETOOMANY = 7     /* n larger than the plan's max_n                        */
@@ -151,6 +154,31 @@ int dpse_plan_bind(dpse_plan* plan, void* workspace, int64_t bytes, void* stream
 
 /* Copies the derived quantities of a plan into *info. */
 int dpse_plan_info(const dpse_plan* plan, dpse_info* info);
+
+/* Fixed charge densities sigma_b on the bottom wall (z = 0) and sigma_t on
+ * the top wall (z = H) of a plan (Sec. 2 eq. rho and the jump conditions
+ * cbc2, cbc4). Each solve then adds them to the displacement mismatches of
+ * the harmonic correction (Sec. 4.3.3 eqs. mm2, mm4) and to the slope of the
+ * k = 0 mode (Sec. 4.3.4 eqs. ai1, ai2), and the energy gains the wall
+ * integral of eq. Ufinal, 1/2 int (sigma_b phi(x,y,0) + sigma_t phi(x,y,H)),
+ * taken by reciprocity: with phi_s the potential of the walls alone (their
+ * correction, harmonic in the slab) and B the gauge constant,
+ *   int sigma phi = sum_k q_k phi_s(z_k) + int sigma phi_s + B int sigma,
+ * the first sum from the S-bar averages of phi_s at the charges, the second
+ * from the wall modes (both FP64). Neutrality becomes sum q + int sigma = 0.
+ *   sigma_b, sigma_t  device, [Ny][Nx] float64 (x fastest): the densities at
+ *                     the grid points (i h, j h); NULL = no charge on that
+ *                     wall; both NULL removes the wall charges.
+ * The densities must be resolved by the grid (the correction keeps only the
+ * modes the plan corrects). The call copies what it needs (the caller's
+ * buffers may be reused once the plan's stream has passed it), enqueues its
+ * kernels on the plan's stream and uses the workspace, so the plan must be
+ * bound; the wall data (the transforms and the FP32 or FP64 grid of phi_s,
+ * Nz Ny Nx reals) is allocated once and kept with the plan. Captured graphs
+ * of dpse_solve_graph are re-captured; batch graphs keep the wall state of
+ * their creation. DPSE_EINVAL for an unbound plan or a DPSE_UNIFORM_FAST plan
+ * (it has no correction), DPSE_ENOMEM, DPSE_EHIP. */
+int dpse_plan_set_walls(dpse_plan* plan, const double* sigma_b, const double* sigma_t);
 
 /* Enqueues one solve (Sec. 5.2.2 steps 1-7 plus the near field). The near
  * field needs only the binned charges: it runs on a stream private to the
@@ -249,11 +277,15 @@ const char* dpse_status_string(int status);
  *   DPSE_STAGE_GRIDS  phi, Ex, Ey, Ez on the grid, [Nz][Ny][Nx][4]
  *   DPSE_STAGE_FAR    far-field averages at the charges (phi, Ex, Ey, Ez), [n][4], caller order
  *   DPSE_STAGE_NEAR   near-field sums at the charges (phi, Ex, Ey, Ez), [n][4], caller order
- *   DPSE_STAGE_SCALARS (B_i, A_i, far part at the origin, near part at the origin), FP64 */
+ *   DPSE_STAGE_SCALARS (B_i, A_i, far part at the origin, near part at the origin), FP64
+ *   DPSE_STAGE_WALL_HAT   x,y transforms of sigma_b then sigma_t, complex [2][Ny][Nx/2+1], FP64
+ *   DPSE_STAGE_WALL_PHI   potential of the wall charges alone on the grid, [Nz][Ny][Nx]
+ *   DPSE_STAGE_WALL_SCALARS (int sigma, int |sigma|, int sigma phi_s, k = 0 slope of phi_s), FP64
+ * (the wall entries after dpse_plan_set_walls) */
 enum {
   DPSE_STAGE_F_I = 0, DPSE_STAGE_F_O = 1, DPSE_STAGE_FH_I = 2, DPSE_STAGE_PSI = 3,
   DPSE_STAGE_PSIZ = 4, DPSE_STAGE_GRIDS = 5, DPSE_STAGE_FAR = 6, DPSE_STAGE_NEAR = 7,
-  DPSE_STAGE_SCALARS = 8
+  DPSE_STAGE_SCALARS = 8, DPSE_STAGE_WALL_HAT = 9, DPSE_STAGE_WALL_PHI = 10, DPSE_STAGE_WALL_SCALARS = 11
 };
 int dpse_debug_copy(dpse_plan* plan, int which, void* dst, int64_t bytes,
                     int32_t* elem_bytes, int64_t* count);

@@ -115,6 +115,16 @@ struct Tables {
   double* cpiv = nullptr;
 };
 
+// Fixed wall charge densities (dpse_plan_set_walls), one allocation per plan.
+struct Walls {
+  double* stage = nullptr;   // sigma_b then sigma_t at the grid points, [2][Ny][Nx]
+  double2* hat = nullptr;    // their x,y transforms, [2][Ny][nkx] (fft_xy normalisation)
+  void* phis = nullptr;      // R [Nz][Ny][Nx]: potential of the walls alone at the nodes
+  double* scal = nullptr;    // 0 int sigma, 1 int |sigma|, 2 int sigma phi_s, 3 k = 0 slope A_s
+  double* part = nullptr;    // block partials of the wall reductions [kWallParts]
+};
+constexpr int kWallParts = 256;
+
 }  // namespace dpse
 
 struct dpse_plan {
@@ -123,6 +133,9 @@ struct dpse_plan {
   dpse::Geom g;
   dpse::Tables t;
   dpse::Workspace w;
+  dpse::Walls walls;
+  bool walls_on = false;               // wall charges set (dpse_plan_set_walls)
+  int walls_version = 0;               // bumped by every dpse_plan_set_walls
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t max_n = 0;
@@ -134,7 +147,7 @@ struct dpse_plan {
   bool bound = false;                  // a workspace is attached
   bool owns_workspace = false;
   hipGraphExec_t graph_exec = nullptr; // captured solve (dpse_solve_graph)
-  const void* graph_sig[7] = {};
+  const void* graph_sig[8] = {};
   hipStream_t graph_stream = nullptr;
   // tile shapes of spreading and interpolation: index into the candidate
   // lists of k_grid.hip, or -1 for the default rule (dpse_plan_autotune)
@@ -180,6 +193,16 @@ int column_candidates();
 hipError_t launch_pivots(dpse_plan* p, hipStream_t s);
 int column_block(int i);
 bool column_valid(const Geom& g, int i);
+
+// Wall charges: the x,y transforms of the staged densities (FP64), the
+// potential of the walls alone at the nodes into the workspace's psi/psiz
+// (the inverse transforms then give its grid), the wall scalars, the copy of
+// that grid into Walls::phis, and the per-solve sum of q phi_s at the charges.
+hipError_t launch_wall_transforms(dpse_plan* p);
+template <typename R> hipError_t launch_wall_modes(dpse_plan* p);
+template <typename R> hipError_t launch_wall_keep_phi(dpse_plan* p);
+template <typename R> hipError_t launch_wall_energy(dpse_plan* p, int64_t n);
+int wall_energy_blocks(const dpse_plan* p, int64_t n);
 
 // Sets kernel attributes once (before any stream capture).
 hipError_t prepare_kernels();

@@ -22,6 +22,8 @@
 //     derivative (coefficient recurrence), plus the analytic correction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dpse_internal.h"
 #include "fft_lds.h"
 
@@ -126,7 +128,8 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
                                                      const double* __restrict__ zn,
                                                      const double* __restrict__ ctab,
                                                      const double2* __restrict__ twz,
-                                                     const double* __restrict__ cpiv, double* scal) {
+                                                     const double* __restrict__ cpiv, double* scal,
+                                                     const double2* __restrict__ wall_hat) {
   using C = typename CT<R>::T;
   extern __shared__ double2 smem2[];
   constexpr int kElems = KE;
@@ -450,6 +453,13 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
       double2 meb = make_double2(e * di0.x - eb * tb * do0.x, e * di0.y - eb * tb * do0.y);
       double2 mpt = make_double2(viH.x - tt * voH.x, viH.y - tt * voH.y);
       double2 met = make_double2(e * diH.x - et * tt * doH.x, e * diH.y - et * tt * doH.y);
+      if (wall_hat) {  // wall charges: + sigma_b in mm2, - sigma_t in mm4
+        const double2 sb = wall_hat[m0 + m], st = wall_hat[nmodes + m0 + m];
+        meb.x += sb.x;
+        meb.y += sb.y;
+        met.x -= st.x;
+        met.y -= st.y;
+      }
       double2 Rb = make_double2((eb * k * mpb.x - meb.x) / k, (eb * k * mpb.y - meb.y) / k);
       double2 Rt = make_double2(-(met.x + et * k * mpt.x) / k, -(met.y + et * k * mpt.y) / k);
       double E = exp(-k * g.H);
@@ -468,6 +478,10 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
         double Ab = -tb * ea.x, At = -tt * ebd.x;
         double A1 = (g.eps_b * (tb * do0.x + Ab) - e * di0.x) / e;
         double A2 = (g.eps_t * (tt * doH.x + At) - e * diH.x) / e;
+        if (wall_hat) {  // wall charges in eqs. ai1, ai2
+          A1 -= wall_hat[0].x / e;
+          A2 += wall_hat[nmodes].x / e;
+        }
         Ai = 0.5 * (A1 + A2);
       }
       scal[3] = Ai;
@@ -639,7 +653,112 @@ void column_as(dpse_plan* p) {
   const int nb = (nmodes + MB - 1) / MB;
   hipLaunchKernelGGL((k_column<R, KE, NT>), dim3(nb), dim3(NT), column_lds(g, KE), p->stream, g,
                      (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
-                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal);
+                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal,
+                     p->walls_on ? (const double2*)p->walls.hat : nullptr);
+}
+
+// Harmonic correction of the walls alone for a mode with k > 0: the closed
+// form of the column kernel with m_phi = 0, m_E^b = sigma_b, m_E^t = -sigma_t,
+// so R_b = -sigma_b / k and R_t = sigma_t / k.
+__device__ inline void wall_coeffs(const Geom& g, double k, double2 sb, double2 st, double2& al, double2& be) {
+  const double e = g.eps, eb = g.eps_b, et = g.eps_t;
+  const double E = exp(-k * g.H);
+  const double D = (e + eb) * (e + et) - (eb - e) * (et - e) * E * E;
+  const double2 Rb = make_double2(-sb.x / k, -sb.y / k), Rt = make_double2(st.x / k, st.y / k);
+  al = make_double2((Rb.x * (et - e) * E + (e + eb) * Rt.x) / D, (Rb.y * (et - e) * E + (e + eb) * Rt.y) / D);
+  be = make_double2(((e - eb) * E * Rt.x - (e + et) * Rb.x) / D, ((e - eb) * E * Rt.y - (e + et) * Rb.y) / D);
+}
+
+// k = 0 slope of the walls alone: the mean of eqs. ai1 and ai2 without charges.
+__device__ inline double wall_slope(const Geom& g, const double2* hat, int nmodes) {
+  return 0.5 * (hat[nmodes].x - hat[0].x) / g.eps;
+}
+
+// Potential of the walls alone per mode at every node into psi (the correction
+// at the window nodes -H_E <= z <= H + H_E of corrected modes, A_s z at
+// k = 0, zero elsewhere); psiz is cleared.
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_wall_modes(Geom g, const double2* __restrict__ hat,
+                                                         const double* __restrict__ zn,
+                                                         typename CT<R>::T* __restrict__ psi,
+                                                         typename CT<R>::T* __restrict__ psiz) {
+  using C = typename CT<R>::T;
+  const int nmodes = g.Ny * g.nkx;
+  const int64_t total = (int64_t)g.Nz * nmodes;
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < total; i += (int64_t)gridDim.x * kThreads) {
+    const int c = (int)(i / nmodes), mi = (int)(i - (int64_t)c * nmodes);
+    const double z = zn[c];
+    double kk;
+    int keep;
+    mode_wave(g, mi, kk, keep);
+    double2 v = make_double2(0.0, 0.0);
+    if (mi == 0) {
+      v.x = wall_slope(g, hat, nmodes) * z;
+    } else if (kk > 0.0 && keep && z >= -g.H_E && z <= g.H + g.H_E) {
+      double2 al, be;
+      wall_coeffs(g, kk, hat[mi], hat[nmodes + mi], al, be);
+      const double e1 = exp(kk * (z - g.H)), e2 = exp(-kk * z);
+      v = make_double2(al.x * e1 + be.x * e2, al.y * e1 + be.y * e2);
+    }
+    C a, zero;
+    a.x = (R)v.x;
+    a.y = (R)v.y;
+    zero.x = (R)0;
+    zero.y = (R)0;
+    psi[i] = a;
+    psiz[i] = zero;
+  }
+}
+
+// Wall scalars, one block: ws[0] = int sigma = Lx Ly (sigma_b^(0) + sigma_t^(0)),
+// ws[1] = int |sigma| (trapezoid sum of the staged densities), ws[2] =
+// int (sigma_b phi_s(.,0) + sigma_t phi_s(.,H)) = Lx Ly sum_k Re(conj(sigma^) phi_s^)
+// over the full spectrum (the half spectrum with columns 0 < kx < Nx/2 twice),
+// ws[3] = the k = 0 slope A_s. Fixed summation order.
+__global__ void __launch_bounds__(kThreads) k_wall_scalars(Geom g, const double2* __restrict__ hat,
+                                                           const double* __restrict__ stage, double* ws) {
+  __shared__ double sa[kThreads], sb_[kThreads];
+  const int nmodes = g.Ny * g.nkx;
+  const double As = wall_slope(g, hat, nmodes);
+  double acc = 0.0, aab = 0.0;
+  for (int mi = threadIdx.x; mi < nmodes; mi += kThreads) {
+    double kk;
+    int keep;
+    mode_wave(g, mi, kk, keep);
+    const int kxi = mi % g.nkx;
+    const double cw = (kxi == 0 || kxi == g.Nx / 2) ? 1.0 : 2.0;
+    const double2 sb = hat[mi], st = hat[nmodes + mi];
+    double2 p0 = make_double2(0.0, 0.0), pH = make_double2(0.0, 0.0);
+    if (mi == 0) {
+      pH.x = As * g.H;
+    } else if (kk > 0.0 && keep) {
+      double2 al, be;
+      wall_coeffs(g, kk, sb, st, al, be);
+      const double E = exp(-kk * g.H);
+      p0 = make_double2(al.x * E + be.x, al.y * E + be.y);
+      pH = make_double2(al.x + be.x * E, al.y + be.y * E);
+    }
+    acc += cw * (sb.x * p0.x + sb.y * p0.y + st.x * pH.x + st.y * pH.y);
+  }
+  const int64_t ns = 2LL * g.Ny * g.Nx;
+  for (int64_t i = threadIdx.x; i < ns; i += kThreads) aab += fabs(stage[i]);
+  sa[threadIdx.x] = acc;
+  sb_[threadIdx.x] = aab;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sa[threadIdx.x] += sa[threadIdx.x + s];
+      sb_[threadIdx.x] += sb_[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double area = g.Lx * g.Ly;
+    ws[0] = area * (hat[0].x + hat[nmodes].x);
+    ws[1] = g.h * g.h * sb_[0];
+    ws[2] = area * sa[0];
+    ws[3] = As;
+  }
 }
 }  // namespace
 
@@ -703,7 +822,22 @@ hipError_t prepare_kernels() {
   return any ? hipSuccess : hipErrorInvalidValue;
 }
 
+template <typename R>
+hipError_t launch_wall_modes(dpse_plan* p) {
+  using C = typename CT<R>::T;
+  const Geom& g = p->g;
+  const int64_t total = (int64_t)g.Nz * g.Ny * g.nkx;
+  const int nb = (int)std::min<int64_t>((total + kThreads - 1) / kThreads, 8192);
+  hipLaunchKernelGGL(k_wall_modes<R>, dim3(nb), dim3(kThreads), 0, p->stream, g, (const double2*)p->walls.hat,
+                     (const double*)p->t.z, (C*)p->w.psi, (C*)p->w.psiz);
+  hipLaunchKernelGGL(k_wall_scalars, dim3(1), dim3(kThreads), 0, p->stream, g, (const double2*)p->walls.hat,
+                     (const double*)p->walls.stage, p->walls.scal);
+  return hipGetLastError();
+}
+
 template hipError_t launch_column<double>(dpse_plan*);
 template hipError_t launch_column<float>(dpse_plan*);
+template hipError_t launch_wall_modes<double>(dpse_plan*);
+template hipError_t launch_wall_modes<float>(dpse_plan*);
 
 }  // namespace dpse

@@ -291,6 +291,35 @@ hipError_t launch_fft_inverse(dpse_plan* p) {
   return hipGetLastError();
 }
 
+// x,y transforms (FP64, the normalisation of the forward transform) of the
+// two staged wall densities, planes 0 (bottom) and 1 (top).
+hipError_t launch_wall_transforms(dpse_plan* p) {
+  launch_x_rows<double>(p, (const double*)p->walls.stage, (double2*)p->walls.hat, 0, 2);
+  launch_y_planes<double>(p, (double2*)p->walls.hat, 0, 2);
+  return hipGetLastError();
+}
+
+namespace {
+// The potential channel of the interleaved field grid [G][4] into out [G].
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_keep_phi(int64_t G, const R* __restrict__ u4, R* __restrict__ out) {
+  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < G; i += (int64_t)gridDim.x * kThreads)
+    out[i] = u4[4 * i];
+}
+}  // namespace
+
+template <typename R>
+hipError_t launch_wall_keep_phi(dpse_plan* p) {
+  const Geom& g = p->g;
+  const int64_t G = (int64_t)g.Nz * g.Ny * g.Nx;
+  const int nb = (int)((G + kThreads - 1) / kThreads < 8192 ? (G + kThreads - 1) / kThreads : 8192);
+  hipLaunchKernelGGL(k_keep_phi<R>, dim3(nb), dim3(kThreads), 0, p->stream, G, (const R*)p->w.u4,
+                     (R*)p->walls.phis);
+  return hipGetLastError();
+}
+
+template hipError_t launch_wall_keep_phi<double>(dpse_plan*);
+template hipError_t launch_wall_keep_phi<float>(dpse_plan*);
 template hipError_t launch_fft_forward<double>(dpse_plan*);
 template hipError_t launch_fft_forward<float>(dpse_plan*);
 template hipError_t launch_fft_inverse<double>(dpse_plan*);

@@ -104,9 +104,12 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
   }
 }
 
-__global__ void k_check_neutral(const double* scal, int* status) {
+// Neutrality of the charges and the wall charges together (eq. elecneu);
+// ws = the wall scalars (int sigma, int |sigma|), or null without walls.
+__global__ void k_check_neutral(const double* scal, const double* ws, int* status) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    if (!(fabs(scal[0]) <= 1e-12 * scal[1])) atomicOr(status, 4);
+    const double net = scal[0] + (ws ? ws[0] : 0.0), tot = scal[1] + (ws ? ws[1] : 0.0);
+    if (!(fabs(net) <= 1e-12 * tot)) atomicOr(status, 4);
   }
 }
 
@@ -352,10 +355,19 @@ __global__ void __launch_bounds__(kThreads) k_finalize(Geom g, int64_t n, const 
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-__global__ void k_energy_final(int nb, const double* partials, double* energy, double* scal) {
+// U = 1/2 sum q phibar (eq. Ufinal), plus with wall charges half their
+// integral by reciprocity: sum q phi_s(z_k) (nbw partials in wpart), int sigma
+// phi_s (ws[2]) and B_i int sigma (scal[2] ws[0]).
+__global__ void k_energy_final(int nb, const double* partials, double* energy, double* scal, int nbw,
+                               const double* wpart, const double* ws) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0.0;
   for (int i = 0; i < nb; ++i) s += partials[i];
+  if (wpart) {
+    double sw = 0.0;
+    for (int i = 0; i < nbw; ++i) sw += wpart[i];
+    s += sw + ws[2] + scal[2] * ws[0];
+  }
   scal[6] = 0.5 * s;
   if (energy) *energy = 0.5 * s;
 }
@@ -387,7 +399,8 @@ hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double*
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
                      w.n_img, w.scal, w.status);
-  hipLaunchKernelGGL(k_check_neutral, dim3(1), dim3(64), 0, s, (const double*)w.scal, w.status);
+  hipLaunchKernelGGL(k_check_neutral, dim3(1), dim3(64), 0, s, (const double*)w.scal,
+                     p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
   return hipGetLastError();
 }
 
@@ -443,8 +456,13 @@ hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* ene
   hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, q,
                      (const double4*)p->w.far4, (const double4*)p->w.near4, (const double*)p->w.scal, phi,
                      force, p->w.partials + p->npartials);
+  // the wall energy partials exist when the solve launched k_wall_energy
+  const bool wall = p->walls_on && energy;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nb,
-                     (const double*)(p->w.partials + p->npartials), energy, p->w.scal);
+                     (const double*)(p->w.partials + p->npartials), energy, p->w.scal,
+                     wall ? wall_energy_blocks(p, n) : 0,
+                     wall ? (const double*)(p->w.partials + 4 * p->npartials) : nullptr,
+                     wall ? (const double*)p->walls.scal : nullptr);
   return hipGetLastError();
 }
 

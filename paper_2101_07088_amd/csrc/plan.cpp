@@ -3,6 +3,7 @@
 // (Sec. 5.2.2 steps 1-7 of the paper plus the near field of Sec. 4.2).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -191,7 +192,9 @@ size_t carve_workspace(dpse_plan* p, char* base) {
   for (char** gp : cgrids) c.take(gp, C * 2 * rs);
   c.take((char**)&w.u4, 4 * G * rs);
   c.take(&w.far4, max_n); c.take(&w.near4, max_n);
-  c.take(&w.scal, 16); c.take(&w.partials, 4 * (size_t)p->npartials);
+  // partials: near part at the origin, finalize, far part at the origin per
+  // node (two blocks of npartials: Nz <= 2 npartials), wall energy
+  c.take(&w.scal, 16); c.take(&w.partials, 5 * (size_t)p->npartials);
   return (c.off + 255) & ~size_t(255);
 }
 
@@ -522,7 +525,10 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(main, p->join_ev, 0);
   if (e == hipSuccess) e = dpse::launch_gauge_final(p, n);
   end(8, main);
-  start(9, main); if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force); end(9, main);
+  start(9, main);
+  if (p->walls_on && energy && e == hipSuccess) e = dpse::launch_wall_energy<R>(p, n);
+  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force);
+  end(9, main);
   return e;
 }
 
@@ -562,9 +568,10 @@ int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q
                      double* phi, double* force) {
   if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
   if (n > p->max_n) return DPSE_ETOOMANY;
-  const void* sig[7] = {(const void*)(intptr_t)n, pos, q, energy, phi, force, (const void*)p->w.ext};
+  const void* sig[8] = {(const void*)(intptr_t)n, pos, q, energy, phi, force, (const void*)p->w.ext,
+                        (const void*)(intptr_t)(p->walls_on ? p->walls_version : -1)};
   bool same = p->graph_exec != nullptr && p->graph_stream == p->stream;
-  for (int i = 0; i < 7 && same; ++i) same = p->graph_sig[i] == sig[i];
+  for (int i = 0; i < 8 && same; ++i) same = p->graph_sig[i] == sig[i];
   if (!same) {
     if (p->graph_exec) {
       (void)hipGraphExecDestroy(p->graph_exec);
@@ -600,7 +607,7 @@ int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q
       p->graph_exec = nullptr;
       return DPSE_EHIP;
     }
-    for (int i = 0; i < 7; ++i) p->graph_sig[i] = sig[i];
+    for (int i = 0; i < 8; ++i) p->graph_sig[i] = sig[i];
     p->graph_stream = p->stream;
   }
   p->last_n = n;
@@ -754,6 +761,60 @@ static void drop_graph(dpse_plan* p) {
   }
 }
 
+int dpse_plan_set_walls(dpse_plan* p, const double* sigma_b, const double* sigma_t) {
+  if (!p) return DPSE_EINVAL;
+  if (!sigma_b && !sigma_t) {
+    p->walls_on = false;
+    p->walls_version++;
+    drop_graph(p);
+    return DPSE_OK;
+  }
+  if (!p->bound || (p->g.flags & DPSE_UNIFORM_FAST)) return DPSE_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  const Geom& g = p->g;
+  const bool mixed = p->prm.precision == DPSE_MIXED;
+  const size_t rs = mixed ? 4 : 8;
+  const size_t plane = (size_t)g.Ny * g.Nx, G = (size_t)g.Nz * plane, nm = (size_t)g.Ny * g.nkx;
+  dpse::Walls& wl = p->walls;
+  if (!wl.stage) {  // first use: one allocation kept with the plan
+    auto carve = [&](char* base) {
+      Carver c{base};
+      c.take(&wl.stage, 2 * plane);
+      c.take(&wl.hat, 2 * nm);
+      c.take((char**)&wl.phis, G * rs);
+      c.take(&wl.scal, 8);
+      c.take(&wl.part, (size_t)dpse::kWallParts);
+      return c.off;
+    };
+    const size_t bytes = carve(nullptr);
+    void* mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      wl = dpse::Walls{};
+      return DPSE_ENOMEM;
+    }
+    p->allocs.push_back(mem);
+    carve((char*)mem);
+  }
+  hipStream_t s = p->stream;
+  hipError_t e = sigma_b ? hipMemcpyAsync(wl.stage, sigma_b, plane * sizeof(double), hipMemcpyDeviceToDevice, s)
+                         : dpse::fill_double(wl.stage, 0.0, (int64_t)plane, s);
+  if (e == hipSuccess)
+    e = sigma_t ? hipMemcpyAsync(wl.stage + plane, sigma_t, plane * sizeof(double), hipMemcpyDeviceToDevice, s)
+                : dpse::fill_double(wl.stage + plane, 0.0, (int64_t)plane, s);
+  // transforms, the wall potential per mode (through the workspace's psi,
+  // psiz and the inverse transforms) and its grid, the wall scalars
+  if (e == hipSuccess) e = dpse::launch_wall_transforms(p);
+  if (e == hipSuccess) e = mixed ? dpse::launch_wall_modes<float>(p) : dpse::launch_wall_modes<double>(p);
+  if (e == hipSuccess) e = mixed ? dpse::launch_fft_inverse<float>(p) : dpse::launch_fft_inverse<double>(p);
+  if (e == hipSuccess) e = mixed ? dpse::launch_wall_keep_phi<float>(p) : dpse::launch_wall_keep_phi<double>(p);
+  if (e != hipSuccess) return DPSE_EHIP;
+  p->walls_on = true;
+  p->walls_version++;
+  drop_graph(p);
+  return DPSE_OK;
+}
+
 int dpse_plan_set_tiles(dpse_plan* p, const int32_t* choice) {
   if (!p || !choice) return DPSE_EINVAL;
   for (int s = 0; s < DPSE_NUM_TUNED; ++s)
@@ -889,8 +950,12 @@ int dpse_debug_copy(dpse_plan* p, int which, void* dst, int64_t bytes, int32_t* 
     case DPSE_STAGE_FAR: src = p->w.far4; cnt = 4 * p->last_n; eb = 8; break;
     case DPSE_STAGE_NEAR: src = p->w.near4; cnt = 4 * p->last_n; eb = 8; break;
     case DPSE_STAGE_SCALARS: src = p->w.scal; cnt = 8; eb = 8; break;
+    case DPSE_STAGE_WALL_HAT: src = p->walls.hat; cnt = 4 * (int64_t)g.Ny * g.nkx; eb = 8; break;
+    case DPSE_STAGE_WALL_PHI: src = p->walls.phis; cnt = G; break;
+    case DPSE_STAGE_WALL_SCALARS: src = p->walls.scal; cnt = 4; eb = 8; break;
     default: return DPSE_EINVAL;
   }
+  if (!src) return DPSE_EINVAL;  // wall data before dpse_plan_set_walls
   if (cnt * eb > bytes) return DPSE_EINVAL;
   if (hipMemcpy(dst, src, cnt * eb, hipMemcpyDeviceToHost) != hipSuccess) return DPSE_EHIP;
   if (which == DPSE_STAGE_F_O) {

@@ -33,6 +33,9 @@ class Stage(enum.IntEnum):
     FAR = 6
     NEAR = 7
     SCALARS = 8
+    WALL_HAT = 9
+    WALL_PHI = 10
+    WALL_SCALARS = 11
 
 
 class DpseError(RuntimeError):
@@ -95,6 +98,7 @@ def _lib():
         L.dpse_plan_autotune.argtypes = [vp, i64, pd, pd, ctypes.c_int, ctypes.POINTER(i32),
                                          ctypes.POINTER(ctypes.c_double)]
         L.dpse_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32)]
+        L.dpse_plan_set_walls.argtypes = [vp, pd, pd]
         L.dpse_sync.argtypes = [vp]
         L.dpse_plan_destroy.argtypes = [vp]
         L.dpse_debug_copy.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -107,7 +111,7 @@ def _lib():
                      "dpse_sync", "dpse_plan_destroy", "dpse_debug_copy", "dpse_set_timing",
                      "dpse_stage_times", "dpse_workspace_size", "dpse_plan_create_unbound", "dpse_plan_bind",
                      "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy",
-                     "dpse_plan_autotune", "dpse_plan_set_tiles"):
+                     "dpse_plan_autotune", "dpse_plan_set_tiles", "dpse_plan_set_walls"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -238,6 +242,22 @@ class Plan:
         ch = (ctypes.c_int32 * 3)(*[int(c) for c in choice])
         _check(_lib().dpse_plan_set_tiles(self._h, ch), "dpse_plan_set_tiles")
 
+    def set_walls(self, sigma_b=None, sigma_t=None):
+        """dpse_plan_set_walls: fixed charge densities on the bottom and top
+        walls, float64 [Ny, Nx] HIP tensors of their values at the x,y grid
+        points (None: no charge on that wall; both None removes them)."""
+        torch = self._torch
+        ptrs = []
+        for sg in (sigma_b, sigma_t):
+            if sg is None:
+                ptrs.append(None)
+                continue
+            assert sg.dtype == torch.float64 and sg.is_cuda and sg.is_contiguous()
+            assert tuple(sg.shape) == (self.params.Ny, self.params.Nx)
+            ptrs.append(sg.data_ptr())
+        _check(_lib().dpse_plan_set_walls(self._h, ptrs[0], ptrs[1]), "dpse_plan_set_walls")
+        self._walls = (sigma_b, sigma_t)  # kept alive until the stream has copied them
+
     def sync(self) -> int:
         """Waits for the stream; raises DpseError for a device-detected error."""
         st = _lib().dpse_sync(self._h)
@@ -254,7 +274,8 @@ class Plan:
         G = p.Nz * p.Ny * p.Nx
         sizes = {Stage.F_I: G, Stage.F_O: G, Stage.FH_I: 2 * p.Nz * p.Ny * nkx, Stage.PSI: 2 * p.Nz * p.Ny * nkx,
                  Stage.PSIZ: 2 * p.Nz * p.Ny * nkx, Stage.GRIDS: 4 * G, Stage.FAR: 4 * self.max_n,
-                 Stage.NEAR: 4 * self.max_n, Stage.SCALARS: 8}
+                 Stage.NEAR: 4 * self.max_n, Stage.SCALARS: 8, Stage.WALL_HAT: 4 * p.Ny * nkx,
+                 Stage.WALL_PHI: G, Stage.WALL_SCALARS: 4}
         buf = np.empty(sizes[stage] * 8, dtype=np.uint8)
         eb = ctypes.c_int32()
         cnt = ctypes.c_int64()
@@ -262,8 +283,11 @@ class Plan:
                                       ctypes.byref(cnt)), "dpse_debug_copy")
         dt = np.float64 if eb.value == 8 else np.float32
         a = buf[: cnt.value * eb.value].view(dt).astype(np.float64)
-        if stage in (Stage.F_I, Stage.F_O):
+        if stage in (Stage.F_I, Stage.F_O, Stage.WALL_PHI):
             return a.reshape(p.Nz, p.Ny, p.Nx)
+        if stage == Stage.WALL_HAT:
+            c = a.reshape(2, p.Ny, nkx, 2)
+            return c[..., 0] + 1j * c[..., 1]
         if stage in (Stage.FH_I, Stage.PSI, Stage.PSIZ):
             c = a.reshape(p.Nz, p.Ny, nkx, 2)
             return c[..., 0] + 1j * c[..., 1]

@@ -77,3 +77,10 @@ def test_uniform_fast_flag_validation():
     assert abs(info["z_lo"] + info["H_E"]) < 1e-12 and abs(info["z_hi"] - (p.H + info["H_E"])) < 1e-12
     with pytest.raises(dp.DpseError):
         dp.derive(p.copy(uniform_fast=True, eps_b=0.5))
+
+
+def test_set_walls_rejects_a_null_plan():
+    """dpse_plan_set_walls validates its plan on the host (no GPU needed)."""
+    import ctypes
+    from paper_2101_07088_amd.native import _lib
+    assert _lib().dpse_plan_set_walls(None, None, None) == 1

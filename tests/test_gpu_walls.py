@@ -1,0 +1,203 @@
+"""GPU parity of the wall charge densities (dpse_plan_set_walls) with the
+FP64 oracle: the wall transforms, the potential of the walls alone and the
+wall scalars stage by stage, then U, phi-bar and F of whole solves (FP64 bar
+1e-9, mixed 1e-5) on the charged-wall energy test of Sec. 6.3, a larger slab
+with Gaussian wall densities, and counterions neutralised by uniformly
+charged walls; plus the neutrality check, removal of the walls, graph
+re-capture, a solve without the energy output, and the uniform solver's
+refusal."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import dpse_oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def rel_rms(a, b):
+    return float(np.sqrt(np.sum(np.abs(a - b) ** 2) / np.sum(np.abs(b) ** 2)))
+
+
+def rel_max(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def energy_test():
+    return W.config_charged_walls(0, g_w=1e-2)
+
+
+def gaussian_slab(seed=4):
+    """64 x 64 x 65 grid (several tiles, ragged mode blocks), 300 pairs, both
+    walls with jumps, Gaussian wall densities of s = 2 and charge +-3."""
+    p = W.SlabParams(Lx=16.0, Ly=16.0, H=8.0, eps=1.0, eps_b=0.05, eps_t=20.0, xi=1.0, Nx=64, Ny=64, Nz=65,
+                     r_cut=3.0)
+    pos, q = W.charges(seed, 300, 300, 16.0, 16.0, 0.5, 7.5)
+    sb, st = W.gaussian_walls(p, 2.0, center=(5.0, 11.0))
+    return p, pos, q, 3.0 * sb, 3.0 * st
+
+
+def counterions(seed=5):
+    """Sec. 7 charged-wall setting: only positive ions inside, both walls at
+    sigma = -N/(2 Lx Ly) (uniform), so charges and walls are neutral together."""
+    p = W.SlabParams(Lx=16.0, Ly=16.0, H=8.0, eps=1.0, eps_b=0.2, eps_t=5.0, xi=1.0, Nx=64, Ny=64, Nz=33,
+                     r_cut=3.0)
+    pos, _ = W.charges(seed, 100, 100, 16.0, 16.0, 0.5, 7.5)
+    q = np.ones(len(pos))
+    sig = np.full((p.Ny, p.Nx), -len(q) / (2.0 * p.Lx * p.Ly))
+    return p, pos, q, sig, sig.copy()
+
+
+CASES = {"energy_test": energy_test, "gaussian_slab": gaussian_slab, "counterions": counterions}
+
+
+def solve_walls(p, pos, q, sb, st, precision):
+    import paper_2101_07088_amd as dp
+    plan = dp.Plan(p, max_n=len(q), precision=precision)
+    plan.set_walls(dev(sb), dev(st))
+    U, phi, F = plan.solve(dev(pos), dev(q))
+    assert plan.sync_status() == 0
+    return plan, float(U.cpu()[0]), phi.cpu().numpy(), F.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", [0, 1])
+def test_walls_match_oracle(case, precision):
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q, sb, st = CASES[case]()
+    U0, phi0, F0, I = O.solve(p, pos, q, sigma_b=sb, sigma_t=st)
+    plan, U, phi, F = solve_walls(p, pos, q, sb, st, precision)
+    eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
+    eU = abs(U - U0) / abs(U0)
+    S = dp.Stage
+    hat = plan.debug(S.WALL_HAT)
+    e_hat = max(rel_max(hat[0], I["sigma_b_hat"]), rel_max(hat[1], I["sigma_t_hat"]))
+    e_phis = rel_max(plan.debug(S.WALL_PHI), I["phi_s"])
+    ws = plan.debug(S.WALL_SCALARS)
+    qabs = np.sum(np.abs(sb) + np.abs(st)) * (p.Lx / p.Nx) ** 2
+    e_Q = max(abs(ws[0] - I["Q_s"]), abs(ws[1] - qabs)) / qabs
+
+    def rel0(a, b):  # relative error, or the value itself where the oracle's is 0
+        return abs(a - b) / abs(b) if b != 0.0 else abs(a)
+    e_W = rel0(ws[2], I["W_ss"])
+    e_A = rel0(ws[3], I["A_s"])
+    print(f"[case] walls {case} prec={precision}: F {eF:.2e} phi {ep:.2e} U {eU:.2e} | hat {e_hat:.1e} "
+          f"phi_s {e_phis:.1e} Q {e_Q:.1e} W_ss {e_W:.1e} A_s {e_A:.1e}", flush=True)
+    tol = 1e-9 if precision == 0 else 1e-5
+    assert e_hat < 1e-12 and e_Q < 1e-12 and e_W < 1e-10 and e_A < 1e-12
+    # phi_s at the nodes up to H_E outside the slab continues the wall
+    # correction analytically (Sec. 4.3.3): e^{k H_E} (about 1e8 at the
+    # highest corrected k here) multiplies the rounding noise of the wall
+    # transforms at large k, which numpy's FFT and the HIP FFT round
+    # differently; the charges weight those nodes by e^{-H_E^2/(2 g_t^2)} at
+    # most, so the solve's outputs keep the 1e-9 bar
+    assert e_phis < (1e-9 if precision == 0 else 5e-6)   # mixed: an FP32 grid
+    assert eF < tol and ep < tol and eU < tol
+    plan.close()
+
+
+def test_walls_neutrality_and_removal():
+    """Charges neutral only with the walls: accepted with them, DPSE_ENONNEUTRAL
+    without; removing the walls gives a fresh plan's result (to the rounding
+    of the interpolation's atomic sums)."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q, sb, st = counterions()
+    plan = dp.Plan(p, max_n=len(q))
+    tp, tq = dev(pos), dev(q)
+    plan.solve(tp, tq)
+    assert plan.sync_status() == 4
+    plan.set_walls(dev(sb), dev(st))
+    plan.solve(tp, tq)
+    assert plan.sync_status() == 0
+    plan.set_walls(dev(sb), None)  # half the compensating charge
+    plan.solve(tp, tq)
+    assert plan.sync_status() == 4
+    plan.close()
+    # removal: a neutral set with and then without walls equals a plan that never had them
+    p, pos, q, sb, st = gaussian_slab()
+    tp, tq = dev(pos), dev(q)
+    a = dp.Plan(p, max_n=len(q))
+    a.set_walls(dev(sb), dev(st))
+    Uw, _, Fw = a.solve(tp, tq)
+    assert a.sync_status() == 0
+    a.set_walls(None, None)
+    U1, phi1, F1 = a.solve(tp, tq)
+    assert a.sync_status() == 0
+    b = dp.Plan(p, max_n=len(q))
+    U2, phi2, F2 = b.solve(tp, tq)
+    assert b.sync_status() == 0
+    F1, F2, Fw = F1.cpu().numpy(), F2.cpu().numpy(), Fw.cpu().numpy()
+    assert rel_rms(F1, F2) < 1e-13 and rel_rms(phi1.cpu().numpy(), phi2.cpu().numpy()) < 1e-13
+    assert abs(float(U1.cpu()[0]) - float(U2.cpu()[0])) < 1e-12 * abs(float(U2.cpu()[0]))
+    assert rel_rms(Fw, F2) > 1e-3
+    a.close()
+    b.close()
+
+
+def test_walls_graph_recapture_and_no_energy():
+    """dpse_solve_graph follows dpse_plan_set_walls (re-capture), replays
+    equal the eager solve, and a solve with no energy output gives the same
+    forces and potentials."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    from paper_2101_07088_amd.native import _lib
+    p, pos, q, sb, st = gaussian_slab(seed=6)
+    n = len(q)
+    tp, tq = dev(pos), dev(q)
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    PH = torch.empty(n, dtype=torch.float64, device="cuda")
+    F = torch.empty((n, 3), dtype=torch.float64, device="cuda")
+    g = dp.Plan(p, max_n=n)
+    e = dp.Plan(p, max_n=n)
+    for rep, walls in enumerate([None, (sb, st), (2.0 * sb, 2.0 * st), None]):
+        for pl in (g, e):
+            if walls is None:
+                pl.set_walls(None, None)
+            else:
+                pl.set_walls(dev(walls[0]), dev(walls[1]))
+        for _ in range(2):
+            g.solve_graph(tp, tq, E, PH, F)
+            assert g.sync_status() == 0
+        Ue, phie, Fe = e.solve(tp, tq)
+        assert e.sync_status() == 0
+        eF = rel_rms(F.cpu().numpy(), Fe.cpu().numpy())
+        eU = abs(float(E.cpu()[0]) - float(Ue.cpu()[0])) / abs(float(Ue.cpu()[0]))
+        print(f"[case] walls graph rep {rep}: F {eF:.2e} U {eU:.2e}", flush=True)
+        assert eF < 1e-13 and eU < 1e-12
+        PH2 = torch.empty_like(PH)
+        F2 = torch.empty_like(F)
+        assert _lib().dpse_solve(e.handle, n, tp.data_ptr(), tq.data_ptr(), None, PH2.data_ptr(),
+                                 F2.data_ptr()) == 0
+        assert e.sync_status() == 0
+        assert rel_rms(F2.cpu().numpy(), Fe.cpu().numpy()) < 1e-13
+        assert rel_rms(PH2.cpu().numpy(), phie.cpu().numpy()) < 1e-13
+    g.close()
+    e.close()
+
+
+def test_walls_refused_by_the_uniform_solver_and_before_binding():
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q, sb, st = gaussian_slab()
+    fast = dp.Plan(p.copy(eps_b=1.0, eps_t=1.0, uniform_fast=True), max_n=len(q))
+    with pytest.raises(dp.DpseError):
+        fast.set_walls(dev(sb), dev(st))
+    fast.close()
+    ub = dp.Plan(p, max_n=len(q), own_workspace=False)
+    with pytest.raises(dp.DpseError):
+        ub.set_walls(dev(sb), dev(st))
+    ub.close()
