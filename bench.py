@@ -95,8 +95,10 @@ def band_fraction(p, info):
     return sum(1 for zz in z if zz < 3 * he or zz > p.H - 3 * he) / p.Nz
 
 
-def time_path(dp, torch, p, tpos, tq, precision, steps, warmup):
+def time_path(dp, torch, p, tpos, tq, precision, steps, warmup, walls=None):
     plan = dp.Plan(p, max_n=len(tq), precision=precision)
+    if walls is not None:
+        plan.set_walls(*walls)
     tiles, tile_ms = plan.autotune(tpos, tq, reps=3)   # plan-time tuning, outside the timed region
     E = torch.empty(1, dtype=torch.float64, device="cuda")
     PH = torch.empty(len(tq), dtype=torch.float64, device="cuda")
@@ -232,6 +234,41 @@ def bench_uniform(dp, torch, steps):
     return out
 
 
+def bench_walls(dp, torch, steps):
+    """The jump workload with fixed charge densities on both walls (Sec. 2
+    eq. rho): Gaussians of s = 4 centred in the box with total charge +64
+    (bottom) and -64 (top), mixed precision, energy requested: the solve with
+    the walls against the same solve without them, the one-time cost of
+    dpse_plan_set_walls, the force change the walls make and the mixed
+    path's force difference from the FP64 path with the walls."""
+    import workloads as W
+    p, pos, q = W.config_jump(0)
+    sb, st = W.gaussian_walls(p, 4.0)
+    walls = (torch.tensor(64.0 * sb, device="cuda"), torch.tensor(64.0 * st, device="cuda"))
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    r0 = time_path(dp, torch, p, tpos, tq, dp.DPSE_MIXED, steps, 3)
+    rw = time_path(dp, torch, p, tpos, tq, dp.DPSE_MIXED, steps, 3, walls=walls)
+    r64 = time_path(dp, torch, p, tpos, tq, dp.DPSE_FP64, steps, 3, walls=walls)
+    plan = dp.Plan(p, max_n=len(q), precision=dp.DPSE_MIXED)
+    plan.set_walls(*walls)
+    plan.sync()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.set_walls(*walls)
+    plan.sync()
+    t_set = (time.perf_counter() - t0) / reps
+    plan.close()
+    n = len(q)
+    return {"ms_no_walls": 1e3 * r0["wall_s"] / steps, "ms_walls": 1e3 * rw["wall_s"] / steps,
+            "evals_per_s_walls": n / (rw["wall_s"] / steps), "finalize_stage_ms_walls": rw["stages"]["finalize"],
+            "finalize_stage_ms_no_walls": r0["stages"]["finalize"], "set_walls_ms": 1e3 * t_set,
+            "status": rw["status"], "rel_rms_force_change_by_walls": rel_rms(rw["F"], r0["F"]),
+            "mixed_vs_fp64_rel_rms_force": rel_rms(rw["F"], r64["F"]),
+            "mixed_vs_fp64_rel_energy": abs(rw["U"] - r64["U"]) / abs(r64["U"])}
+
+
 def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_slots=8, max_queue=256):
     """Serving stream: Poisson arrivals of solves from n_traj Brownian-like
     trajectories (N log-uniform in [512, 262144], box and permittivities
@@ -331,6 +368,8 @@ def main(argv=None):
     ap.add_argument("--batch-branches", type=int, default=8)
     ap.add_argument("--uniform", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the uniform-permittivity solver against the general one")
+    ap.add_argument("--walls", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the solve with charged walls against the plain one")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
@@ -406,6 +445,9 @@ def main(argv=None):
     if a.uniform:
         line["uniform_eps"] = bench_uniform(dp, torch, a.steps)
         print(f"[bench] uniform eps: {line['uniform_eps']}", file=sys.stderr, flush=True)
+    if a.walls:
+        line["charged_walls"] = bench_walls(dp, torch, a.steps)
+        print(f"[bench] charged walls: {line['charged_walls']}", file=sys.stderr, flush=True)
     if a.batch:
         line["batch"] = bench_batch(dp, torch, a.steps, n_branches=a.batch_branches)
         print(f"[bench] batch: {line['batch']}", file=sys.stderr, flush=True)

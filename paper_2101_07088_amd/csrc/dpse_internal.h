@@ -121,9 +121,8 @@ struct Walls {
   double2* hat = nullptr;    // their x,y transforms, [2][Ny][nkx] (fft_xy normalisation)
   void* phis = nullptr;      // R [Nz][Ny][Nx]: potential of the walls alone at the nodes
   double* scal = nullptr;    // 0 int sigma, 1 int |sigma|, 2 int sigma phi_s, 3 k = 0 slope A_s
-  double* part = nullptr;    // block partials of the wall reductions [kWallParts]
+  double* part = nullptr;    // block partials of the wall term in the interpolation
 };
-constexpr int kWallParts = 256;
 
 }  // namespace dpse
 
@@ -136,6 +135,10 @@ struct dpse_plan {
   dpse::Walls walls;
   bool walls_on = false;               // wall charges set (dpse_plan_set_walls)
   int walls_version = 0;               // bumped by every dpse_plan_set_walls
+  // where the solve being enqueued leaves the partials of sum q phi_s-bar
+  // (the interpolation's gather shapes, else the per-charge kernel), or null
+  double* wall_part = nullptr;
+  int wall_nparts = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t max_n = 0;

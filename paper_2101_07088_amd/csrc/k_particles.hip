@@ -358,18 +358,24 @@ __global__ void __launch_bounds__(kThreads) k_finalize(Geom g, int64_t n, const 
 // U = 1/2 sum q phibar (eq. Ufinal), plus with wall charges half their
 // integral by reciprocity: sum q phi_s(z_k) (nbw partials in wpart), int sigma
 // phi_s (ws[2]) and B_i int sigma (scal[2] ws[0]).
+// One wave: lane-strided sums of the partials, then a fixed shuffle tree (the
+// order does not depend on timing).
 __global__ void k_energy_final(int nb, const double* partials, double* energy, double* scal, int nbw,
                                const double* wpart, const double* ws) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += partials[i];
-  if (wpart) {
-    double sw = 0.0;
-    for (int i = 0; i < nbw; ++i) sw += wpart[i];
-    s += sw + ws[2] + scal[2] * ws[0];
+  const int lane = threadIdx.x;
+  double s = 0.0, sw = 0.0;
+  for (int i = lane; i < nb; i += 64) s += partials[i];
+  if (wpart)
+    for (int i = lane; i < nbw; i += 64) sw += wpart[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_down(s, o, 64);
+    sw += __shfl_down(sw, o, 64);
   }
-  scal[6] = 0.5 * s;
-  if (energy) *energy = 0.5 * s;
+  if (lane == 0) {
+    if (wpart) s += sw + ws[2] + scal[2] * ws[0];
+    scal[6] = 0.5 * s;
+    if (energy) *energy = 0.5 * s;
+  }
 }
 
 inline int blocks_for(int64_t n, int cap) {
@@ -456,12 +462,11 @@ hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* ene
   hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, q,
                      (const double4*)p->w.far4, (const double4*)p->w.near4, (const double*)p->w.scal, phi,
                      force, p->w.partials + p->npartials);
-  // the wall energy partials exist when the solve launched k_wall_energy
-  const bool wall = p->walls_on && energy;
+  // the partials of the wall term, from the interpolation or the per-charge kernel
+  const bool wall = p->walls_on && energy && p->wall_part;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nb,
                      (const double*)(p->w.partials + p->npartials), energy, p->w.scal,
-                     wall ? wall_energy_blocks(p, n) : 0,
-                     wall ? (const double*)(p->w.partials + 4 * p->npartials) : nullptr,
+                     wall ? p->wall_nparts : 0, wall ? (const double*)p->wall_part : nullptr,
                      wall ? (const double*)p->walls.scal : nullptr);
   return hipGetLastError();
 }

@@ -500,6 +500,8 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   auto run = [&](hipError_t (*f)(dpse_plan*)) {
     if (e == hipSuccess) e = f(p);
   };
+  p->wall_part = nullptr;  // set by whichever kernel forms the wall term
+  p->wall_nparts = 0;
   start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
   start(1, main); if (e == hipSuccess) e = dpse::launch_bin(p, n); end(1, main);
   // fork the near field (stage 7) and its part of the gauge; inside a graph
@@ -526,7 +528,7 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   if (e == hipSuccess) e = dpse::launch_gauge_final(p, n);
   end(8, main);
   start(9, main);
-  if (p->walls_on && energy && e == hipSuccess) e = dpse::launch_wall_energy<R>(p, n);
+  if (p->walls_on && energy && !p->wall_part && e == hipSuccess) e = dpse::launch_wall_energy<R>(p, n);
   if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force);
   end(9, main);
   return e;
@@ -783,7 +785,9 @@ int dpse_plan_set_walls(dpse_plan* p, const double* sigma_b, const double* sigma
       c.take(&wl.hat, 2 * nm);
       c.take((char**)&wl.phis, G * rs);
       c.take(&wl.scal, 8);
-      c.take(&wl.part, (size_t)dpse::kWallParts);
+      // one partial per block of the gather interpolation (x,y tiles of 16,
+      // at least 4 nodes per block)
+      c.take(&wl.part, (size_t)(g.Nx / 16) * (g.Ny / 16) * ((g.Nz + 3) / 4));
       return c.off;
     };
     const size_t bytes = carve(nullptr);

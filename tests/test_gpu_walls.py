@@ -60,7 +60,16 @@ def counterions(seed=5):
     return p, pos, q, sig, sig.copy()
 
 
-CASES = {"energy_test": energy_test, "gaussian_slab": gaussian_slab, "counterions": counterions}
+def small_walls():
+    """The small workload (32 x 32 x 33, n_g = 18): no gather interpolation
+    shape fits, so the wall term comes from the per-charge kernel."""
+    p, pos, q = W.config_small(0)
+    sb, st = W.gaussian_walls(p, 3.0, center=(4.0, 9.0))
+    return p, pos, q, 2.0 * sb, 2.0 * st
+
+
+CASES = {"energy_test": energy_test, "gaussian_slab": gaussian_slab, "counterions": counterions,
+         "small_walls": small_walls}
 
 
 def solve_walls(p, pos, q, sb, st, precision):
