@@ -25,6 +25,9 @@ Readings of points the paper leaves open (the HIP path takes the same ones):
   * near field: strict r < r_cut, minimal image in x,y, one image per wall for
     every charge (its own included);
   * A_i(0) is the mean of its two formulas; gauge constant added to phi directly;
+  * one dielectric jump (``one_jump``): every charge is imaged across that
+    wall and the free-space solve of the uniform case runs on the span of
+    charges and images, [-H - H_E, H + H_E] or [-H_E, 2H + H_E];
   * wall charges: sigma_b, sigma_t are given by their values at the x,y grid
     points and enter only the correction (eqs. mm2, mm4) and A_i (eqs. ai1,
     ai2); the wall integral of eq. Ufinal is taken by reciprocity: with
@@ -78,14 +81,31 @@ def derive(p) -> Dict[str, object]:
     g_t = math.sqrt(1.0 / (4.0 * p.xi ** 2) + p.g_w ** 2)          # eq. gt
     n_g = p.n_g if p.n_g else 2 * math.ceil(4.3 * g_t / h)
     H_E = n_g * h / 2.0                                             # eq. He
-    fast = getattr(p, "uniform_fast", False)
-    if fast and not (p.eps_b == p.eps == p.eps_t):
+    uniform = getattr(p, "uniform_fast", False)
+    one = getattr(p, "one_jump", False)
+    if uniform and one:
+        raise ValueError("the uniform and the one-jump solvers exclude each other")
+    if uniform and not (p.eps_b == p.eps == p.eps_t):
         raise ValueError("the uniform-permittivity solver needs eps_b == eps == eps_t")
-    # Chebyshev domain: [-3 H_E, H + 3 H_E] with walls (Sec. 5.2.2); with no
-    # jump the sources (Gaussians of support H_E) fill [-H_E, H + H_E] and the
-    # free-space solve of Sec. 3.1.1 needs no more
-    a = -H_E if fast else -3.0 * H_E
-    b = p.H + (H_E if fast else 3.0 * H_E)
+    jump_b, jump_t = p.eps_b != p.eps, p.eps_t != p.eps
+    if one and jump_b == jump_t:
+        raise ValueError("the one-jump solver needs a jump at exactly one wall")
+    # free-space solve of Sec. 3.1.1 (no wall group, no correction) for no
+    # jump, and for one jump after imaging every charge across that wall
+    # (Sec. 4, opening; Sec. 1): the sources (Gaussians of support H_E) and
+    # images fill [-H_E, H + H_E], [-H - H_E, H + H_E] (bottom jump) or
+    # [-H_E, 2H + H_E] (top jump); with two jumps the domain is
+    # [-3 H_E, H + 3 H_E] (Sec. 5.2.2)
+    fast = uniform or one
+    one_side = ("b" if jump_b else "t") if one else None
+    if uniform:
+        a, b = -H_E, p.H + H_E
+    elif one_side == "b":
+        a, b = -p.H - H_E, p.H + H_E
+    elif one_side == "t":
+        a, b = -H_E, 2.0 * p.H + H_E
+    else:
+        a, b = -3.0 * H_E, p.H + 3.0 * H_E
     c = 0.5 * (a + b)
     R = 0.5 * (b - a)
     N = p.Nz
@@ -116,7 +136,7 @@ def derive(p) -> Dict[str, object]:
     # derivative multipliers vanish on Nyquist indices
     dkx = np.where(NXI == -(p.Nx // 2), 0.0, KX)
     dky = np.where(NYI == -(p.Ny // 2), 0.0, KY)
-    return dict(h=h, g_t=g_t, n_g=n_g, H_E=H_E, a=a, b=b, c=c, R=R, s=s, z=z, fast=fast,
+    return dict(h=h, g_t=g_t, n_g=n_g, H_E=H_E, a=a, b=b, c=c, R=R, s=s, z=z, fast=fast, one_side=one_side,
                 w=w, gamma_b=gamma_b, gamma_t=gamma_t, tau_b=tau_b, tau_t=tau_t,
                 xi_e=xi_e, kx=KX, ky=KY, kabs=kabs, keep=keep, dkx=dkx, dky=dky)
 
@@ -130,17 +150,21 @@ def groups_and_images(p, d, pos, q):
     H_E = d["H_E"]
     low = z < 2.0 * H_E
     high = z > p.H - 2.0 * H_E
-    if d["fast"]:  # no walls to correct for: one group, no images
+    if d["fast"]:  # no walls to correct for: one group
         low = np.zeros_like(low)
         high = np.zeros_like(high)
     c_o = low | high
+    img_b, img_t = low, high
+    if d["one_side"] is not None:  # one jump: every charge imaged across that wall
+        img_b = np.full_like(low, d["one_side"] == "b")
+        img_t = np.full_like(high, d["one_side"] == "t")
     ipos, iq = [], []
     if d["gamma_b"] != 0.0:
-        sel = np.nonzero(low)[0]
+        sel = np.nonzero(img_b)[0]
         ipos.append(np.stack([pos[sel, 0], pos[sel, 1], -z[sel]], axis=1))
         iq.append(d["gamma_b"] * q[sel])
     if d["gamma_t"] != 0.0:
-        sel = np.nonzero(high)[0]
+        sel = np.nonzero(img_t)[0]
         ipos.append(np.stack([pos[sel, 0], pos[sel, 1], 2.0 * p.H - z[sel]], axis=1))
         iq.append(d["gamma_t"] * q[sel])
     if ipos:

@@ -495,3 +495,56 @@ def test_walls_rejected_by_the_uniform_solver():
     p, pos, q, X, Y = _wall_box(1.0, 1.0)
     with pytest.raises(ValueError):
         O.solve(p.copy(uniform_fast=True), pos, q, sigma_b=np.zeros((p.Ny, p.Nx)))
+
+
+# --- one dielectric jump: images of every charge, then the free-space solve (Sec. 4 opening)
+
+def _one_jump(eps_b, eps_t, nz=65):
+    return SlabParams(Lx=4.0, Ly=4.0, H=2.0, eps=1.0, eps_b=eps_b, eps_t=eps_t, xi=2.0, Nx=32, Ny=32, Nz=nz,
+                      r_cut=1.5, one_jump=True)
+
+
+@pytest.mark.parametrize("eps_b,eps_t", [(0.05, 1.0), (1.0, 0.05), (20.0, 1.0)])
+def test_one_jump_matches_image_series(eps_b, eps_t):
+    """With a jump at one wall the exact solution is the charges plus one
+    image each (the image series of the Ewald2D reference has nothing else);
+    the one-jump solver reaches it to the method's accuracy, on the span of
+    charges and images, with every charge imaged and nothing corrected."""
+    pos, q = charges(3, 4, 4, 4.0, 4.0, 0.3, 1.7)
+    p = _one_jump(eps_b, eps_t)
+    d = O.derive(p)
+    if eps_b != 1.0:
+        assert abs(d["a"] + p.H + d["H_E"]) < 1e-14 and abs(d["b"] - p.H - d["H_E"]) < 1e-14
+    else:
+        assert abs(d["a"] + d["H_E"]) < 1e-14 and abs(d["b"] - 2 * p.H - d["H_E"]) < 1e-14
+    U, phi, F, I = O.solve(p, pos, q)
+    _, _, Et = truth.ewald2d(4.0, 4.0, 2.0, 1.0, eps_b, eps_t, pos, q)
+    Ft = q[:, None] * Et
+    assert np.sqrt(((F - Ft) ** 2).sum() / (Ft ** 2).sum()) < 2e-4
+    assert len(I["img_q"]) == len(q) and not np.any(I["c_o"]) and np.all(I["alpha"] == 0)
+
+
+def test_one_jump_top_is_the_mirror_of_bottom():
+    """Reflecting the charges (z -> H - z) and swapping the outer permittivities
+    maps the bottom-jump solve onto the top-jump one exactly: the two domains
+    and their Chebyshev nodes are mirror images."""
+    pos, q = charges(5, 5, 5, 4.0, 4.0, 0.3, 1.7)
+    U1, phi1, F1, _ = O.solve(_one_jump(0.05, 1.0), pos, q)
+    pm = pos.copy()
+    pm[:, 2] = 2.0 - pm[:, 2]
+    U2, phi2, F2, _ = O.solve(_one_jump(1.0, 0.05), pm, q)
+    Fm = F2.copy()
+    Fm[:, 2] *= -1
+    assert np.abs(Fm - F1).max() < 1e-10 * np.abs(F1).max()
+    # phi differs by the gauge point (the origin sits on the other wall) and by
+    # A_i H times the interpolation kernel's discrete mass, which the mirror
+    # turns the k = 0 slope's A_i z into (it varies at the truncation level)
+    assert np.abs((phi2 - phi2.mean()) - (phi1 - phi1.mean())).max() < 1e-6 * np.abs(phi1).max()
+
+
+def test_one_jump_needs_exactly_one_jump():
+    for eb, et in ((1.0, 1.0), (0.05, 20.0)):
+        with pytest.raises(ValueError):
+            O.derive(_one_jump(eb, et))
+    with pytest.raises(ValueError):
+        O.derive(_one_jump(0.05, 1.0).copy(uniform_fast=True))

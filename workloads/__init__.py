@@ -29,7 +29,9 @@ class SlabParams:
     point charge q at distance r in a uniform medium has potential q/(4*pi*eps*r).
     ``n_g = 0`` means the support is derived as 2*ceil(4.3*g_t/h).
     ``uniform_fast`` selects the solver for equal permittivities inside and
-    outside (no wall group, no images, no correction, z domain [-H_E, H+H_E]).
+    outside (no wall group, no images, no correction, z domain [-H_E, H+H_E]);
+    ``one_jump`` the solver for a jump at one wall only (every charge imaged
+    across it, then the free-space solve on the span of charges and images).
     """
 
     Lx: float
@@ -48,6 +50,7 @@ class SlabParams:
     gauge: bool = True
     kmax_gt: bool = False
     uniform_fast: bool = False
+    one_jump: bool = False
 
     def copy(self, **kw) -> "SlabParams":
         return dataclasses.replace(self, **kw)
