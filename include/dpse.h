@@ -76,11 +76,19 @@ enum {
 enum {
   DPSE_GAUGE_NONE = 1,  /* skip the phi(0) = 0 gauge constant (U and F unaffected for neutral sets) */
   DPSE_KMAX_GT = 2,     /* cap the harmonic correction at |k| <= min(pi/h, 4.2/g_t) instead of pi/h */
-  DPSE_UNIFORM_FAST = 4 /* equal permittivities (eps_bottom == eps == eps_top, else DPSE_EINVAL):
+  DPSE_UNIFORM_FAST = 4, /* equal permittivities (eps_bottom == eps == eps_top, else DPSE_EINVAL):
                            the free-space solve of Sec. 3.1.1 on the Chebyshev domain [-H_E, H + H_E],
                            with no wall group, images or harmonic correction, and the k = 0 slope
                            that cancels the field outside the (neutral) sources; about half the
                            z nodes of the general solver for the same accuracy */
+  DPSE_ONE_JUMP = 8     /* a jump at exactly one wall (eps_top == eps != eps_bottom or the
+                           reverse, else DPSE_EINVAL; not with DPSE_UNIFORM_FAST): every charge
+                           is imaged across that wall (Sec. 4 opening: for one interface the
+                           image construction is exact) and the free-space solve of
+                           DPSE_UNIFORM_FAST runs on the span of charges and images,
+                           [-H - H_E, H + H_E] (bottom) or [-H_E, 2H + H_E] (top); no wall
+                           group or correction. Shorter than the general domain when
+                           H < 4 H_E; no wall charges */
 };
 
 /* Parameters of one slab system. Lengths share one unit. */
@@ -94,7 +102,7 @@ typedef struct {
   double r_cut;                     /* near cutoff, 0 < r_cut < min(Lx, Ly)/2; 0 = derive from delta (eq. rnf) */
   double delta;                     /* tolerance used when r_cut == 0 (default 1e-4 if 0)    */
   int32_t precision;                /* DPSE_FP64 or DPSE_MIXED                               */
-  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT                        */
+  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP */
 } dpse_params;
 
 /* Derived quantities of a plan (Sec. 3.2 eq. gt, Sec. 5.1 eq. He, Sec. 5.2.2). */
@@ -103,7 +111,7 @@ typedef struct {
   double g_t;          /* std of the spreading Gaussian S-bar                     */
   double H_E;          /* support radius n_g h / 2                                */
   double n_sigma;      /* H_E / g_t                                               */
-  double z_lo, z_hi;   /* Chebyshev domain [-3 H_E, H + 3 H_E]                    */
+  double z_lo, z_hi;   /* Chebyshev domain ([-3 H_E, H + 3 H_E] with two jumps)   */
   double r_cut;        /* near cutoff actually used                              */
   double xi_e;         /* (4 g_w^2 + xi^-2)^(-1/2)                                */
   int32_t support;     /* n_g                                                      */

@@ -84,6 +84,10 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     bool low = !fast && z < 2.0 * g.H_E, high = !fast && z > g.H - 2.0 * g.H_E;
     ext[i] = Part{x, y, z, qq};
     meta[i] = ((low || high) ? GRP_WALL : GRP_INNER) | (int)(i << 2);
+    if (g.flags & DPSE_ONE_JUMP) {  // one jump: every charge imaged across that wall
+      low = true;
+      high = true;  // the wall without a jump has gamma = 0: no image
+    }
     if (low && g.gamma_b != 0.0) {
       int s = atomicAdd(n_img, 1);
       ext[n + s] = Part{x, y, -z, g.gamma_b * qq};

@@ -60,9 +60,15 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     return DPSE_EINVAL;
   if (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
   if (p->precision != DPSE_FP64 && p->precision != DPSE_MIXED) return DPSE_EINVAL;
-  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST)) return DPSE_EINVAL;
-  const bool fast = (p->flags & DPSE_UNIFORM_FAST) != 0;
-  if (fast && !(p->eps_bottom == p->eps && p->eps_top == p->eps)) return DPSE_EINVAL;
+  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP)) return DPSE_EINVAL;
+  const bool uniform = (p->flags & DPSE_UNIFORM_FAST) != 0;
+  const bool one = (p->flags & DPSE_ONE_JUMP) != 0;
+  if (uniform && one) return DPSE_EINVAL;
+  if (uniform && !(p->eps_bottom == p->eps && p->eps_top == p->eps)) return DPSE_EINVAL;
+  const bool jump_b = p->eps_bottom != p->eps, jump_t = p->eps_top != p->eps;
+  if (one && jump_b == jump_t) return DPSE_EINVAL;
+  // the free-space solve (no wall group, no correction) serves both
+  const bool fast = uniform || one;
   double h = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(h - hy) > 1e-12 * h) return DPSE_EINVAL;
   double g_t = std::sqrt(1.0 / (4.0 * p->xi * p->xi) + p->g_w * p->g_w);
@@ -81,17 +87,25 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   // position-independent necessary conditions of Sec. 4.2 / 5.3 (h_min <= H/2);
   // they concern the images, which the uniform-permittivity solver has none of
   if (!fast && (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H)) return DPSE_EINVAL;
-  // Chebyshev domain: [-3 H_E, H + 3 H_E] with walls (Sec. 5.2.2); the
-  // free-space solve without jumps (Sec. 3.1.1) needs only the sources' span
-  const double zdom = fast ? H_E : 3.0 * H_E;
+  // Chebyshev domain: [-3 H_E, H + 3 H_E] with two jumps (Sec. 5.2.2); the
+  // free-space solve (Sec. 3.1.1) needs only the span of the sources, and
+  // with one jump of its images too
+  double za = -3.0 * H_E, zb = p->H + 3.0 * H_E;
+  if (uniform) {
+    za = -H_E;
+    zb = p->H + H_E;
+  } else if (one) {
+    za = jump_b ? -p->H - H_E : -H_E;
+    zb = jump_b ? p->H + H_E : 2.0 * p->H + H_E;
+  }
 
   std::memset(info, 0, sizeof(*info));
   info->h = h;
   info->g_t = g_t;
   info->H_E = H_E;
   info->n_sigma = H_E / g_t;
-  info->z_lo = -zdom;
-  info->z_hi = p->H + zdom;
+  info->z_lo = za;
+  info->z_hi = zb;
   info->r_cut = rc;
   info->xi_e = 1.0 / std::sqrt(4.0 * p->g_w * p->g_w + 1.0 / (p->xi * p->xi));
   info->support = ng;
@@ -103,7 +117,7 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     g->eps = p->eps; g->eps_b = p->eps_bottom; g->eps_t = p->eps_top;
     g->xi = p->xi; g->g_w = p->g_w;
     g->h = h; g->inv_h = 1.0 / h; g->g_t = g_t; g->H_E = H_E;
-    g->za = -zdom; g->zb = p->H + zdom;
+    g->za = za; g->zb = zb;
     g->zc = 0.5 * (g->za + g->zb); g->zR = 0.5 * (g->zb - g->za);
     g->gamma_b = (p->eps - p->eps_bottom) / (p->eps + p->eps_bottom);
     g->gamma_t = (p->eps - p->eps_top) / (p->eps + p->eps_top);
@@ -116,12 +130,15 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     g->zmin_ok = 4.0 * p->g_w;
     g->zmax_ok = p->H - 4.0 * p->g_w;
     g->Nx = p->Nx; g->Ny = p->Ny; g->Nz = p->Nz; g->nkx = p->Nx / 2 + 1;
-    g->ng = ng; g->flags = p->flags;
+    // the one-jump solver runs the free-space path of the uniform solver
+    g->ng = ng; g->flags = p->flags | (one ? DPSE_UNIFORM_FAST : 0);
     g->B = std::min(dpse::kBin, std::min(p->Nx, p->Ny));
     g->nbx = p->Nx / g->B; g->nby = p->Ny / g->B;
-    g->zb_lo = -2.0 * H_E;
+    // z buckets of the particles (charges and images: centres within H_E of
+    // the domain's interior)
+    g->zb_lo = za + H_E;
     g->zb_w = 0.5 * H_E;
-    g->nzb = (int)std::ceil((p->H + 4.0 * H_E) / g->zb_w) + 1;
+    g->nzb = (int)std::ceil((zb - za - 2.0 * H_E) / g->zb_w) + 1;
     g->ncx = std::max(1, std::min(1024, (int)std::floor(p->Lx / rc)));
     g->ncy = std::max(1, std::min(1024, (int)std::floor(p->Ly / rc)));
     g->ncz = std::max(1, std::min(1024, (int)std::floor(p->H / rc)));

@@ -84,3 +84,18 @@ def test_set_walls_rejects_a_null_plan():
     import ctypes
     from paper_2101_07088_amd.native import _lib
     assert _lib().dpse_plan_set_walls(None, None, None) == 1
+
+
+def test_one_jump_flag_validation():
+    """The one-jump solver needs a jump at exactly one wall, excludes the
+    uniform solver, and spans the charges and their images."""
+    p, _, _ = config_small(0)
+    pb = p.copy(one_jump=True, eps_b=0.05, eps_t=p.eps)
+    info = dp.derive(pb)
+    assert abs(info["z_lo"] + p.H + info["H_E"]) < 1e-12 and abs(info["z_hi"] - (p.H + info["H_E"])) < 1e-12
+    info = dp.derive(p.copy(one_jump=True, eps_b=p.eps, eps_t=20.0))
+    assert abs(info["z_lo"] + info["H_E"]) < 1e-12 and abs(info["z_hi"] - (2 * p.H + info["H_E"])) < 1e-12
+    for bad in (p.copy(one_jump=True, eps_b=p.eps, eps_t=p.eps), p.copy(one_jump=True, eps_b=0.05, eps_t=20.0),
+                pb.copy(uniform_fast=True)):
+        with pytest.raises(dp.DpseError):
+            dp.derive(bad)

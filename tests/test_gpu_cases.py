@@ -185,3 +185,14 @@ def test_uniform_fast_path_against_oracle(precision, tol):
     check(p.copy(uniform_fast=True), pos, q, tol, precision=precision, label="uniform fast small")
     p2, pos2, q2 = small_jump(31, 200, L=32.0, H=8.0, eb=1.0, et=1.0)
     check(p2.copy(uniform_fast=True), pos2, q2, tol, precision=precision, label="uniform fast 128x128x33")
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-5)])
+def test_one_jump_path_against_oracle(precision, tol):
+    """The one-jump solver (every charge imaged across the jump wall, the
+    free-space solve on the span of charges and images) against the oracle's,
+    for a bottom and a top jump on a thin slab (H = 4, 64 x 64 x 65)."""
+    _need_gpu()
+    for eb, et, lab in ((0.05, 1.0, "bottom"), (1.0, 20.0, "top")):
+        p, pos, q = small_jump(32, 150, L=16.0, H=4.0, eb=eb, et=et)
+        check(p.copy(one_jump=True, Nz=65), pos, q, tol, precision=precision, label=f"one jump {lab} 64x64x65")

@@ -59,6 +59,9 @@ CASES = {
     # the uniform-permittivity solver (domain [-H_E, H + H_E], no wall group)
     "uniform_fast": lambda: (lambda t: (t[0].copy(eps_b=1.0, eps_t=1.0, uniform_fast=True), t[1], t[2]))(
         jump_tiles(seed=3, n_pairs=90)),
+    # one jump: every charge imaged across the bottom wall, domain [-H - H_E, H + H_E]
+    "one_jump": lambda: (lambda t: (t[0].copy(eps_b=0.05, eps_t=1.0, one_jump=True), t[1], t[2]))(
+        jump_tiles(seed=4, n_pairs=90)),
 }
 
 
