@@ -234,6 +234,28 @@ def bench_uniform(dp, torch, steps):
     return out
 
 
+def bench_one_jump(dp, torch, steps):
+    """A thin slab with a jump at the bottom wall only: the jump workload's
+    density and grid spacing in a 64 x 64 x 5 box (N = 2560, eps_b = 0.05,
+    eps_t = eps = 1), mixed precision. The general solver on [-3 H_E, H + 3 H_E]
+    (length 18.5) and the one-jump solver on [-H - H_E, H + H_E] (length 14.5)
+    at N_z = 33 and 65, against the general solver at N_z = 129 in FP64 (the
+    converged reference)."""
+    import workloads as W
+    p, pos, q = W.scaled_jump(0, 64.0, 5.0, 1280, eps_b=0.05, eps_t=1.0, Nz=65)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    ref = time_path(dp, torch, p.copy(Nz=129), tpos, tq, dp.DPSE_FP64, 3, 1)["F"]
+    out = {"n": len(q)}
+    for nz in (33, 65):
+        for name, prm in ((f"general_Nz{nz}", p.copy(Nz=nz)), (f"one_jump_Nz{nz}", p.copy(Nz=nz, one_jump=True))):
+            r = time_path(dp, torch, prm, tpos, tq, dp.DPSE_MIXED, steps, 3)
+            out[name] = {"ms": 1e3 * r["wall_s"] / steps, "evals_per_s": len(q) / (r["wall_s"] / steps),
+                         "rel_rms_force_vs_reference": rel_rms(r["F"], ref),
+                         "z_domain": [r["info"]["z_lo"], r["info"]["z_hi"]]}
+    return out
+
+
 def bench_walls(dp, torch, steps):
     """The jump workload with fixed charge densities on both walls (Sec. 2
     eq. rho): Gaussians of s = 4 centred in the box with total charge +64
@@ -367,7 +389,7 @@ def main(argv=None):
                     help="also run the serving stream")
     ap.add_argument("--batch-branches", type=int, default=8)
     ap.add_argument("--uniform", action=argparse.BooleanOptionalAction, default=True,
-                    help="also time the uniform-permittivity solver against the general one")
+                    help="also time the uniform-permittivity and one-jump solvers against the general one")
     ap.add_argument("--walls", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the solve with charged walls against the plain one")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -445,6 +467,9 @@ def main(argv=None):
     if a.uniform:
         line["uniform_eps"] = bench_uniform(dp, torch, a.steps)
         print(f"[bench] uniform eps: {line['uniform_eps']}", file=sys.stderr, flush=True)
+    if a.uniform:
+        line["one_jump"] = bench_one_jump(dp, torch, a.steps)
+        print(f"[bench] one jump: {line['one_jump']}", file=sys.stderr, flush=True)
     if a.walls:
         line["charged_walls"] = bench_walls(dp, torch, a.steps)
         print(f"[bench] charged walls: {line['charged_walls']}", file=sys.stderr, flush=True)
