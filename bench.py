@@ -58,7 +58,8 @@ def kernel_name(stage, tiles, mixed):
     if stage == "interp":
         i = tiles[1]
         t, pz = INTERP_SHAPES[i]
-        return f"k_interp{'_gather' if i >= 5 else ''}<{r},{t},{pz}>"
+        # the gather shapes carry the wall-term switch (off on this workload)
+        return f"k_interp_gather<{r},{t},{pz},false>" if i >= 5 else f"k_interp<{r},{t},{pz}>"
     if stage == "column":
         ke, nt = COLUMN_SHAPES[tiles[2]]
         return f"k_column<{r},{ke},{nt}>"
