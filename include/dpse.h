@@ -215,6 +215,38 @@ int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
 int dpse_solve_graph(dpse_plan* plan, int64_t n, const double* pos, const double* q,
                      double* energy, double* phi, double* force);
 
+/* Reuse of the far field between time steps (the paper's closing remark on
+ * reusing far-field work between Brownian-dynamics steps, Sec. 8): the near
+ * field (Sec. 4.2) of the charges at pos, plus each charge's far-field
+ * average (potential and field) and the gauge constant of the plan's last
+ * full solve (dpse_solve, dpse_solve_graph or a batch), held fixed:
+ *   phibar_k = phibar^f_k(last) + phibar^n_k(pos) + B(last) - self term,
+ *   F_k = q_k (Ebar^f_k(last) + Ebar^n_k(pos)), U = 1/2 sum q phibar plus the
+ *   wall terms of the last full solve.
+ * Costs the validation, the binning, the near field and the outputs, about a
+ * quarter of a full solve. The last full solve must have had the same n and
+ * the same charges q in the same order (the caller's contract), and the
+ * plan's workspace must not have served another plan since (the far-field
+ * averages live there; binding or dpse_plan_set_walls invalidates them).
+ * Same arguments, outputs and device errors as dpse_solve; DPSE_EINVAL
+ * without a full solve of this n to reuse. */
+int dpse_solve_near(dpse_plan* plan, int64_t n, const double* pos, const double* q,
+                    double* energy, double* phi, double* force);
+
+/* One Brownian-dynamics step of the non-Markovian Euler-Maruyama scheme of
+ * Leimkuhler and Matthews that the paper integrates with (Sec. 7, eq.
+ * leimkuhler), for forces computed by a solve:
+ *   pos_out = pos + mu_dt force + noise (w_prev + w_next),  noise = sqrt(kT mu dt / 2),
+ * all device, n x 3 row-major float64 (w_prev, w_next standard normal draws of
+ * the caller; pos_out must not alias pos, so that a rejected step leaves pos
+ * as it was). *escaped (device int32) receives the number of charges whose
+ * new height is not strictly inside the admissible range of dpse_solve
+ * (n_sigma g_w, H - n_sigma g_w); the paper discards such a step and retries
+ * it with new noise. x and y are left unwrapped (the solve takes them modulo
+ * the periods). Enqueued on the plan's stream. */
+int dpse_bd_step(dpse_plan* plan, int64_t n, const double* pos, const double* force, const double* w_prev,
+                 const double* w_next, double mu_dt, double noise, double* pos_out, int32_t* escaped);
+
 /* Enqueues n_sys independent solves (one per plan, each with its own sizes and
  * parameters) as one batch. Array arguments have n_sys entries with the
  * meaning of dpse_solve's. Plans may share a stream; the batch is ordered on

@@ -139,6 +139,9 @@ struct dpse_plan {
   // (the interpolation's gather shapes, else the per-charge kernel), or null
   double* wall_part = nullptr;
   int wall_nparts = 0;
+  // charges of the last full solve whose far-field averages (far4) and gauge
+  // constant (scal[2]) are still in the workspace, for dpse_solve_near; 0 = none
+  int64_t far_n = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t max_n = 0;
@@ -183,6 +186,8 @@ hipError_t launch_near_origin(dpse_plan* p, int64_t n);
 hipError_t launch_gauge_final(dpse_plan* p, int64_t n);
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
                            double* phi, double* force);
+hipError_t launch_bd_step(dpse_plan* p, int64_t n, const double* pos, const double* force, const double* w_prev,
+                          const double* w_next, double mu_dt, double noise, double* pos_out, int* escaped);
 
 // Tile-shape candidates of spreading (stage 0) and interpolation (stage 1):
 // count, shape of candidate i (x,y tile width T and z nodes per block P), and

@@ -382,6 +382,25 @@ __global__ void k_energy_final(int nb, const double* partials, double* energy, d
   }
 }
 
+// Brownian-dynamics step (eq. leimkuhler); counts charges leaving the
+// admissible heights.
+__global__ void __launch_bounds__(kThreads) k_bd_step(Geom g, int64_t n, const double* __restrict__ pos,
+                                                      const double* __restrict__ F,
+                                                      const double* __restrict__ wp,
+                                                      const double* __restrict__ wn, double mu_dt, double noise,
+                                                      double* __restrict__ out, int* escaped) {
+  const int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i >= n) return;
+  double v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t k = 3 * i + c;
+    v[c] = pos[k] + mu_dt * F[k] + noise * (wp[k] + wn[k]);
+    out[k] = v[c];
+  }
+  if (!(v[2] > g.zmin_ok && v[2] < g.zmax_ok)) atomicAdd(escaped, 1);
+}
+
 inline int blocks_for(int64_t n, int cap) {
   int64_t b = (n + kThreads - 1) / kThreads;
   if (b < 1) b = 1;
@@ -403,8 +422,10 @@ hipError_t fill_double(double* ptr, double value, int64_t count, hipStream_t s) 
 hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double* q) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
+  // only the accumulated sums (sum q, sum |q|) start from zero: the gauge
+  // constant scal[2] of the last full solve serves dpse_solve_near
   hipError_t e = fill_int(w.n_img, 0, 1, s);
-  if (e == hipSuccess) e = fill_double(w.scal, 0.0, 16, s);
+  if (e == hipSuccess) e = fill_double(w.scal, 0.0, 2, s);
   if (e != hipSuccess) return e;
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
@@ -472,6 +493,16 @@ hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* ene
                      (const double*)(p->w.partials + p->npartials), energy, p->w.scal,
                      wall ? p->wall_nparts : 0, wall ? (const double*)p->wall_part : nullptr,
                      wall ? (const double*)p->walls.scal : nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_bd_step(dpse_plan* p, int64_t n, const double* pos, const double* force, const double* w_prev,
+                          const double* w_next, double mu_dt, double noise, double* pos_out, int* escaped) {
+  hipError_t e = fill_int(escaped, 0, 1, p->stream);
+  if (e != hipSuccess) return e;
+  const int nb = (int)((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_bd_step, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, pos, force, w_prev, w_next, mu_dt,
+                     noise, pos_out, escaped);
   return hipGetLastError();
 }
 

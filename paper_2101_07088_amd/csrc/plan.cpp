@@ -481,6 +481,7 @@ int dpse_plan_bind(dpse_plan* p, void* workspace, int64_t bytes, void* stream) {
   carve_workspace(p, (char*)workspace);
   p->stream = (hipStream_t)stream;
   p->bound = true;
+  p->far_n = 0;
   if (p->graph_exec) {
     (void)hipGraphExecDestroy(p->graph_exec);
     p->graph_exec = nullptr;
@@ -551,6 +552,18 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   return e;
 }
 
+// Near-field-only solve: the far-field averages (far4), the gauge constant
+// (scal[2]) and the wall-term partials of the last full solve stay as they are.
+template <typename R>
+static hipError_t solve_near_stages(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,
+                                    double* phi, double* force) {
+  hipError_t e = dpse::launch_prep(p, n, pos, q);
+  if (e == hipSuccess) e = dpse::launch_bin(p, n);
+  if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
+  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force);
+  return e;
+}
+
 extern "C" {
 
 static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* q,
@@ -575,7 +588,34 @@ static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* 
   }
   hipError_t e = p->prm.precision == DPSE_MIXED ? solve_stages<float>(p, n, pos, q, energy, phi, force, ev)
                                                 : solve_stages<double>(p, n, pos, q, energy, phi, force, ev);
+  p->far_n = e == hipSuccess ? n : 0;
   return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
+}
+
+int dpse_solve_near(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy, double* phi,
+                    double* force) {
+  if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
+  if (n > p->max_n) return DPSE_ETOOMANY;
+  if (p->far_n != n) return DPSE_EINVAL;  // no full solve of these charges to reuse
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+    if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  }
+  p->last_n = n;
+  hipError_t e = p->prm.precision == DPSE_MIXED ? solve_near_stages<float>(p, n, pos, q, energy, phi, force)
+                                                : solve_near_stages<double>(p, n, pos, q, energy, phi, force);
+  return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
+}
+
+int dpse_bd_step(dpse_plan* p, int64_t n, const double* pos, const double* force, const double* w_prev,
+                 const double* w_next, double mu_dt, double noise, double* pos_out, int32_t* escaped) {
+  if (!p || n <= 0 || !pos || !force || !w_prev || !w_next || !pos_out || !escaped || pos_out == pos)
+    return DPSE_EINVAL;
+  if (!std::isfinite(mu_dt) || !std::isfinite(noise) || mu_dt < 0.0 || noise < 0.0) return DPSE_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  return dpse::launch_bd_step(p, n, pos, force, w_prev, w_next, mu_dt, noise, pos_out, escaped) == hipSuccess
+             ? DPSE_OK
+             : DPSE_EHIP;
 }
 
 int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q, double* energy,
@@ -782,6 +822,7 @@ static void drop_graph(dpse_plan* p) {
 
 int dpse_plan_set_walls(dpse_plan* p, const double* sigma_b, const double* sigma_t) {
   if (!p) return DPSE_EINVAL;
+  p->far_n = 0;  // the workspace's far field belongs to the old walls
   if (!sigma_b && !sigma_t) {
     p->walls_on = false;
     p->walls_version++;

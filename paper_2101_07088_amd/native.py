@@ -100,6 +100,8 @@ def _lib():
                                          ctypes.POINTER(ctypes.c_double)]
         L.dpse_plan_set_tiles.argtypes = [vp, ctypes.POINTER(i32)]
         L.dpse_plan_set_walls.argtypes = [vp, pd, pd]
+        L.dpse_solve_near.argtypes = [vp, i64, pd, pd, pd, pd, pd]
+        L.dpse_bd_step.argtypes = [vp, i64, pd, pd, pd, pd, ctypes.c_double, ctypes.c_double, pd, pd]
         L.dpse_sync.argtypes = [vp]
         L.dpse_plan_destroy.argtypes = [vp]
         L.dpse_debug_copy.argtypes = [vp, ctypes.c_int, vp, i64, ctypes.POINTER(i32), ctypes.POINTER(i64)]
@@ -112,7 +114,8 @@ def _lib():
                      "dpse_sync", "dpse_plan_destroy", "dpse_debug_copy", "dpse_set_timing",
                      "dpse_stage_times", "dpse_workspace_size", "dpse_plan_create_unbound", "dpse_plan_bind",
                      "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy",
-                     "dpse_plan_autotune", "dpse_plan_set_tiles", "dpse_plan_set_walls"):
+                     "dpse_plan_autotune", "dpse_plan_set_tiles", "dpse_plan_set_walls", "dpse_solve_near",
+                     "dpse_bd_step"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -211,6 +214,34 @@ class Plan:
         _check(_lib().dpse_solve(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
                                  force.data_ptr()), "dpse_solve")
         return energy, phi, force
+
+    def solve_near(self, pos, q, energy=None, phi=None, force=None):
+        """dpse_solve_near: the near field at pos with the far field and gauge
+        constant of the plan's last full solve of these charges held fixed."""
+        torch = self._torch
+        n = int(q.shape[0])
+        assert pos.dtype == torch.float64 and pos.is_contiguous() and tuple(pos.shape) == (n, 3)
+        dev = pos.device
+        if energy is None:
+            energy = torch.empty(1, dtype=torch.float64, device=dev)
+        if phi is None:
+            phi = torch.empty(n, dtype=torch.float64, device=dev)
+        if force is None:
+            force = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        _check(_lib().dpse_solve_near(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
+                                      force.data_ptr()), "dpse_solve_near")
+        return energy, phi, force
+
+    def bd_step(self, pos, force, w_prev, w_next, mu_dt: float, noise: float, pos_out, escaped):
+        """dpse_bd_step: pos_out = pos + mu_dt force + noise (w_prev + w_next);
+        escaped (int32 device tensor [1]) counts charges leaving the slab."""
+        torch = self._torch
+        for t in (pos, force, w_prev, w_next, pos_out):
+            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.shape == pos.shape
+        assert escaped.dtype == torch.int32 and escaped.is_cuda
+        _check(_lib().dpse_bd_step(self._h, int(pos.shape[0]), pos.data_ptr(), force.data_ptr(), w_prev.data_ptr(),
+                                   w_next.data_ptr(), float(mu_dt), float(noise), pos_out.data_ptr(),
+                                   escaped.data_ptr()), "dpse_bd_step")
 
     def bind(self, workspace, stream=None):
         """Attaches a caller-owned uint8 device tensor (kept referenced here)
