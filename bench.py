@@ -257,6 +257,51 @@ def bench_one_jump(dp, torch, steps):
     return out
 
 
+def bench_bd(dp, torch, steps):
+    """Brownian dynamics (Sec. 7, eq. leimkuhler) of the jump workload's
+    charges, mixed precision, kT = mu = 1, dt = 1e-3 (about 0.045 per axis
+    per step): steps per second (forces, step kernel, the host's check for
+    charges leaving the slab) with a full solve every step and with the far
+    field reused between full solves every 4 and 16 steps; and the force
+    error of the reuse steps against full solves at the same positions."""
+    import workloads as W
+    from paper_2101_07088_amd.bd import BrownianDynamics
+    p, pos, q = W.config_jump(0)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    out = {"n": len(q), "dt": 1e-3}
+    plan = dp.Plan(p, max_n=len(q), precision=dp.DPSE_MIXED)
+    plan.autotune(tpos, tq, reps=3)
+    for K in (1, 4, 16):
+        drv = BrownianDynamics(plan, tpos, tq, 1.0, 1.0, 1e-3, far_every=K, seed=11)
+        for _ in range(4):
+            drv.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            drv.step()
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        out[f"far_every_{K}"] = {"ms_per_step": 1e3 * t, "steps_per_s": 1.0 / t,
+                                 "evals_per_s": len(q) / t, "retries": drv.retries}
+    # accuracy of the reuse steps
+    ref = dp.Plan(p, max_n=len(q), precision=dp.DPSE_MIXED)
+    drv = BrownianDynamics(plan, tpos, tq, 1.0, 1.0, 1e-3, far_every=16, seed=12)
+    errs = []
+    for s in range(32):
+        before = drv.pos.clone()
+        drv.step()
+        if s % 16:
+            _, _, Ff = ref.solve(before, tq)
+            ref.sync()
+            errs.append(rel_rms(drv.force.cpu().numpy(), Ff.cpu().numpy()))
+    ref.close()
+    plan.close()
+    out["reuse_rel_rms_force_vs_full"] = {"mean": float(np.mean(errs)), "max": float(np.max(errs)),
+                                          "after_1_step": errs[0], "after_15_steps": errs[14]}
+    return out
+
+
 def bench_walls(dp, torch, steps):
     """The jump workload with fixed charge densities on both walls (Sec. 2
     eq. rho): Gaussians of s = 4 centred in the box with total charge +64
@@ -391,6 +436,8 @@ def main(argv=None):
     ap.add_argument("--batch-branches", type=int, default=8)
     ap.add_argument("--uniform", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the uniform-permittivity and one-jump solvers against the general one")
+    ap.add_argument("--bd", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time Brownian-dynamics steps with and without far-field reuse")
     ap.add_argument("--walls", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the solve with charged walls against the plain one")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -471,6 +518,9 @@ def main(argv=None):
     if a.uniform:
         line["one_jump"] = bench_one_jump(dp, torch, a.steps)
         print(f"[bench] one jump: {line['one_jump']}", file=sys.stderr, flush=True)
+    if a.bd:
+        line["brownian_dynamics"] = bench_bd(dp, torch, a.steps)
+        print(f"[bench] brownian dynamics: {line['brownian_dynamics']}", file=sys.stderr, flush=True)
     if a.walls:
         line["charged_walls"] = bench_walls(dp, torch, a.steps)
         print(f"[bench] charged walls: {line['charged_walls']}", file=sys.stderr, flush=True)
