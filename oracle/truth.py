@@ -150,3 +150,49 @@ def ewald2d(Lx, Ly, H, eps, eps_b, eps_t, pos, q, alpha=None, n_real=None, k_cut
     if probes is not None:
         return U, phi[:n_chg], E[:n_chg], phi[n_chg:], E[n_chg:]
     return U, phi, E
+
+
+def ewald3d(L, pos, q, eps=1.0, alpha=None, n_real=None, k_cut=None):
+    """Classical Ewald sum of point charges in a box L = (Lx, Ly, Lz)
+    periodic in all three directions, tin-foil boundary (no dipole term):
+    real-space erfc(alpha r)/r over images within n_real boxes, reciprocal
+    sum exp(-k^2/(4 alpha^2))/k^2 over |n_i| <= k_cut, self term -2 alpha/sqrt(pi).
+    Returns (U, phi[N], E[N,3]), each charge's own direct term excluded."""
+    L = np.asarray(L, dtype=np.float64)
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    n = len(q)
+    alpha = alpha or 5.0 / float(L.min())
+    n_real = n_real if n_real is not None else 2
+    k_cut = k_cut if k_cut is not None else 14
+    phi = np.zeros(n)
+    E = np.zeros((n, 3))
+    rng = range(-n_real, n_real + 1)
+    for a in rng:
+        for b in rng:
+            for c in rng:
+                sh = np.array([a, b, c]) * L
+                d = pos[:, None, :] - pos[None, :, :] + sh
+                r = np.linalg.norm(d, axis=2)
+                if a == 0 and b == 0 and c == 0:
+                    np.fill_diagonal(r, np.inf)
+                er = scipy.special.erfc(alpha * r) / r
+                phi += er @ q
+                g = (er + 2.0 * alpha / SQRT_PI * np.exp(-(alpha * r) ** 2)) / r ** 2
+                E += np.einsum("ij,ijk->ik", g * q[None, :], d)
+    V = float(np.prod(L))
+    ks = np.arange(-k_cut, k_cut + 1)
+    KX, KY, KZ = np.meshgrid(2 * math.pi * ks / L[0], 2 * math.pi * ks / L[1], 2 * math.pi * ks / L[2],
+                             indexing="ij")
+    K = np.stack([KX.ravel(), KY.ravel(), KZ.ravel()], 1)
+    K2 = (K ** 2).sum(1)
+    K, K2 = K[K2 > 0], K2[K2 > 0]
+    A = 4 * math.pi / V * np.exp(-K2 / (4 * alpha ** 2)) / K2
+    phase = pos @ K.T                                   # [N, M]
+    S = np.exp(1j * phase).T @ q                        # structure factor, [M]
+    phi += np.real(np.exp(-1j * phase) @ (A * S))
+    E += np.real((1j * np.exp(-1j * phase) * (A * S)[None, :]) @ K)
+    phi -= 2 * alpha / SQRT_PI * q
+    phi /= 4 * math.pi * eps
+    E /= 4 * math.pi * eps
+    return 0.5 * float(np.sum(q * phi)), phi, E
