@@ -81,7 +81,7 @@ enum {
                            with no wall group, images or harmonic correction, and the k = 0 slope
                            that cancels the field outside the (neutral) sources; about half the
                            z nodes of the general solver for the same accuracy */
-  DPSE_ONE_JUMP = 8     /* a jump at exactly one wall (eps_top == eps != eps_bottom or the
+  DPSE_ONE_JUMP = 8,    /* a jump at exactly one wall (eps_top == eps != eps_bottom or the
                            reverse, else DPSE_EINVAL; not with DPSE_UNIFORM_FAST): every charge
                            is imaged across that wall (Sec. 4 opening: for one interface the
                            image construction is exact) and the free-space solve of
@@ -89,6 +89,13 @@ enum {
                            [-H - H_E, H + H_E] (bottom) or [-H_E, 2H + H_E] (top); no wall
                            group or correction. Shorter than the general domain when
                            H < 4 H_E; no wall charges */
+  DPSE_TRIPLY = 16      /* triply periodic variant (Sec. 7 and its performance comparison): the box
+                           is periodic in z too, with period H (the permittivities must be equal,
+                           and the walls play no part); a uniform z grid of Nz nodes (a power of two
+                           in [32, 1024]), the far field solved by Fourier transforms in all three
+                           directions (psi^ = f^ / (eps |k|^2), psi^(0) = 0), the near field over
+                           minimal images in x, y and z; no gauge constant (the k = 0 mode is zero);
+                           needs H >= 4 H_E and r_cut < H / 2; not with the other solver flags */
 };
 
 /* Parameters of one slab system. Lengths share one unit. */
@@ -97,12 +104,12 @@ typedef struct {
   double eps, eps_bottom, eps_top;  /* permittivities; > 0                                   */
   double xi;                        /* Ewald splitting parameter (eq. gamreal); > 0          */
   double g_w;                       /* Gaussian charge width (eq. gcharge); >= 0             */
-  int32_t Nx, Ny, Nz;               /* grid; Nx, Ny powers of two in [32, 1024]; Nz - 1 a power of two in [32, 1024]; Lx/Nx == Ly/Ny */
+  int32_t Nx, Ny, Nz;               /* grid; Nx, Ny powers of two in [32, 1024]; Nz - 1 a power of two in [32, 1024] (Nz itself with DPSE_TRIPLY); Lx/Nx == Ly/Ny */
   int32_t support;                  /* n_g, even, <= 32; 0 = 2*ceil(4.3*g_t/h)               */
   double r_cut;                     /* near cutoff, 0 < r_cut < min(Lx, Ly)/2; 0 = derive from delta (eq. rnf) */
   double delta;                     /* tolerance used when r_cut == 0 (default 1e-4 if 0)    */
   int32_t precision;                /* DPSE_FP64 or DPSE_MIXED                               */
-  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP */
+  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY */
 } dpse_params;
 
 /* Derived quantities of a plan (Sec. 3.2 eq. gt, Sec. 5.1 eq. He, Sec. 5.2.2). */

@@ -80,19 +80,21 @@ def wavenumbers(p):
     return kx, ky, kz, dkx, dky, dkz
 
 
-def near_tp(p, d, pos, q):
-    """Near field [n, 4] with the minimal image in x, y and z, no walls."""
-    n = len(q)
+def near_tp(p, d, pos, q, targets=None):
+    """Near field [n, 4] with the minimal image in x, y and z, no walls
+    (only the rows of ``targets`` when given: sampled checks of large sets)."""
+    tt = np.arange(len(q)) if targets is None else np.asarray(targets)
+    n = len(tt)
     out = np.zeros((n, 4))
-    dx = pos[:, None, 0] - pos[None, :, 0]
-    dy = pos[:, None, 1] - pos[None, :, 1]
-    dz = pos[:, None, 2] - pos[None, :, 2]
+    dx = pos[tt, None, 0] - pos[None, :, 0]
+    dy = pos[tt, None, 1] - pos[None, :, 1]
+    dz = pos[tt, None, 2] - pos[None, :, 2]
     dx -= p.Lx * np.round(dx / p.Lx)
     dy -= p.Ly * np.round(dy / p.Ly)
     dz -= p.H * np.round(dz / p.H)
     r2 = dx * dx + dy * dy + dz * dz
     m = r2 < p.r_cut ** 2
-    np.fill_diagonal(m, False)
+    m[np.arange(n), tt] = False
     ti, sj = np.nonzero(m)
     r = np.sqrt(r2[ti, sj])
     G, e = O.near_kernel(r, p, d["xi_e"])
@@ -103,8 +105,10 @@ def near_tp(p, d, pos, q):
     return out / (O.FOUR_PI * p.eps)
 
 
-def solve_tp(p, pos, q):
-    """Returns (U, phi, F, intermediates) of the triply periodic solve."""
+def solve_tp(p, pos, q, near_targets=None):
+    """Returns (U, phi, F, intermediates) of the triply periodic solve; with
+    ``near_targets`` the near field (and so phi, F) only for those charges
+    (U is then not formed)."""
     d = derive_tp(p)
     pos = _wrap(pos, p)
     q = np.asarray(q, dtype=np.float64)
@@ -126,9 +130,10 @@ def solve_tp(p, pos, q):
         iz, iy, ix, r2 = _window(p, d, *pos[k])
         wgt = _sbar(d, r2) * w
         far[k] = np.tensordot(grids[np.ix_(np.arange(4), iz, iy, ix)], wgt, axes=([1, 2, 3], [0, 1, 2]))
-    near = near_tp(p, d, pos, q)
+    near = near_tp(p, d, pos, q, targets=near_targets)
+    tt = np.arange(len(q)) if near_targets is None else np.asarray(near_targets)
     self_c = 2.0 * d["xi_e"] / (O.FOUR_PI * p.eps * O.SQRT_PI)
-    phi = far[:, 0] + near[:, 0] - q * self_c
-    F = q[:, None] * (far[:, 1:] + near[:, 1:])
-    U = 0.5 * float(np.sum(q * phi))
+    phi = far[tt, 0] + near[:, 0] - q[tt] * self_c
+    F = q[tt, None] * (far[tt, 1:] + near[:, 1:])
+    U = 0.5 * float(np.sum(q * phi)) if near_targets is None else None
     return U, phi, F, dict(f=f, grids=grids, far=far, near=near, derived=d)

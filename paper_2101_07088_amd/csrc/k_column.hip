@@ -657,6 +657,87 @@ void column_as(dpse_plan* p) {
                      p->walls_on ? (const double2*)p->walls.hat : nullptr);
 }
 
+// Triply periodic variant: per block of MB = KE / Nz modes (k_x, k_y), the
+// periodic z transform of each column, psi^ = F^ / (eps |k|^2) (0 at k = 0),
+// psi_z^ = -i k_z psi^ (0 at the Nyquist k_z), and the inverse transforms, in
+// FP64 in both precisions. The nodes descend, z_c = (Nz - 1 - c) h_z, so in
+// node-index space the z derivative multiplies index frequency m by -i k_z,
+// k_z = 2 pi m / H (m signed); the 1/Nz of the z transform is folded in here.
+constexpr int kTpKE = 1024;  // complex LDS elements per buffer (two buffers: 32 KB)
+
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_tp_column(Geom g, const typename CT<R>::T* __restrict__ fx,
+                                                        typename CT<R>::T* __restrict__ psi,
+                                                        typename CT<R>::T* __restrict__ psiz,
+                                                        const double2* __restrict__ twz) {
+  using C = typename CT<R>::T;
+  extern __shared__ double2 smem2[];
+  double2* A = smem2;
+  double2* B = smem2 + kTpKE;
+  double2* tw = smem2 + 2 * kTpKE;
+  const int N = g.Nz, logN = ilog2d(N), MB = kTpKE / N, logMB = ilog2d(kTpKE) - logN;
+  const int nmodes = g.Ny * g.nkx;
+  const int m0 = xcd_block(blockIdx.x, gridDim.x) * MB;
+  const int tid = threadIdx.x;
+  constexpr int kPer = kTpKE / kThreads;
+  for (int i = tid; i < N / 2; i += kThreads) tw[i] = twz[i];
+  {
+    C v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * kThreads, j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
+      v[q].x = 0;
+      v[q].y = 0;
+      if (mi < nmodes) v[q] = fx[(size_t)j * nmodes + mi];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * kThreads, j = t >> logMB, m = t & (MB - 1);
+      A[bitrev(j, logN) * MB + m] = make_double2((double)v[q].x, (double)v[q].y);
+    }
+  }
+  __syncthreads();
+  fft_lds_r22<double2, true, kTpKE / 4 / kThreads, kThreads>(A, logN, logMB, 1, MB, tw, false, tid);
+  {
+    double2 a[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) a[q] = A[tid + q * kThreads];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * kThreads, f = t >> logMB, m = t & (MB - 1), mi = m0 + m;
+      const int kyi = mi / g.nkx, kxi = mi - kyi * g.nkx;
+      const int nx = kxi == g.Nx / 2 ? -(g.Nx / 2) : kxi;
+      const int ny = kyi < g.Ny / 2 ? kyi : kyi - g.Ny;
+      const int mz = f < N / 2 ? f : f - N;
+      const double kx = 2.0 * kPi * nx / g.Lx, ky = 2.0 * kPi * ny / g.Ly, kz = 2.0 * kPi * mz / g.H;
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      const double G = (k2 > 0.0 && mi < nmodes) ? 1.0 / (g.eps * k2 * N) : 0.0;
+      const double2 ps = make_double2(a[q].x * G, a[q].y * G);
+      const double d = f == N / 2 ? 0.0 : -kz;  // psi_z^ = i d psi^
+      const int pos = bitrev(f, logN) * MB + m;
+      A[pos] = ps;
+      B[pos] = make_double2(-d * ps.y, d * ps.x);
+    }
+  }
+  __syncthreads();
+  fft_lds_r22<double2, true, kTpKE / 4 / kThreads, kThreads>(A, logN, logMB, 1, MB, tw, true, tid);
+  fft_lds_r22<double2, true, kTpKE / 4 / kThreads, kThreads>(B, logN, logMB, 1, MB, tw, true, tid);
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int t = tid + q * kThreads, j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
+    if (mi >= nmodes) continue;
+    const double2 a = A[j * MB + m], b = B[j * MB + m];
+    C u, w;
+    u.x = (R)a.x;
+    u.y = (R)a.y;
+    w.x = (R)b.x;
+    w.y = (R)b.y;
+    psi[(size_t)j * nmodes + mi] = u;
+    psiz[(size_t)j * nmodes + mi] = w;
+  }
+}
+
 // Harmonic correction of the walls alone for a mode with k > 0: the closed
 // form of the column kernel with m_phi = 0, m_E^b = sigma_b, m_E^t = -sigma_t,
 // so R_b = -sigma_b / k and R_t = sigma_t / k.
@@ -787,6 +868,16 @@ bool column_valid(const Geom& g, int i) {
 
 template <typename R>
 hipError_t launch_column(dpse_plan* p) {
+  if (p->g.flags & DPSE_TRIPLY) {
+    using C = typename CT<R>::T;
+    const Geom& g = p->g;
+    const int MB = kTpKE / g.Nz;
+    const int nb = (g.Ny * g.nkx + MB - 1) / MB;
+    const size_t lds = (size_t)(2 * kTpKE + g.Nz / 2) * sizeof(double2);
+    hipLaunchKernelGGL(k_tp_column<R>, dim3(nb), dim3(kThreads), lds, p->stream, g, (const C*)p->w.fx_i,
+                       (C*)p->w.psi, (C*)p->w.psiz, (const double2*)p->t.twz);
+    return hipGetLastError();
+  }
   int c = p->column_cfg;
   if (!column_valid(p->g, c)) c = column_valid(p->g, 0) ? 0 : (column_valid(p->g, 1) ? 1 : 2);
   switch (c) {

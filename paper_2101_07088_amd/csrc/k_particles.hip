@@ -73,7 +73,13 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     if (!fin) {
       x = 0.0; y = 0.0; z = 0.5 * g.H; qq = 0.0;
     }
-    z = fmin(fmax(z, 0.0), g.H);
+    const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic with period H
+    if (tp) {
+      z -= g.H * floor(z / g.H);
+      if (!(z < g.H)) z = 0.0;
+    } else {
+      z = fmin(fmax(z, 0.0), g.H);
+    }
     x -= g.Lx * floor(x / g.Lx);
     if (!(x < g.Lx)) x = 0.0;
     y -= g.Ly * floor(y / g.Ly);
@@ -97,6 +103,21 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
       int s = atomicAdd(n_img, 1);
       ext[n + s] = Part{x, y, 2.0 * g.H - z, g.gamma_t * qq};
       meta[n + s] = GRP_IMAGE | (int)(i << 2);
+    }
+    if (tp) {
+      // periodic z windows: a copy of a charge within H_E of an end of the
+      // period, shifted by one period, spreads to the nodes across that end
+      // and gathers its field for the same output index (group of a charge)
+      if (z < g.H_E) {
+        int s = atomicAdd(n_img, 1);
+        ext[n + s] = Part{x, y, z + g.H, qq};
+        meta[n + s] = GRP_INNER | (int)(i << 2);
+      }
+      if (z >= g.H - g.H_E) {
+        int s = atomicAdd(n_img, 1);
+        ext[n + s] = Part{x, y, z - g.H, qq};
+        meta[n + s] = GRP_INNER | (int)(i << 2);
+      }
     }
     if (st) atomicOr(status, st);
   }
@@ -244,6 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
     if (xall) { xlo = 0; xhi = g.ncx - 1; }
     if (yall) { ylo = 0; yhi = g.ncy - 1; }
     int visit = 0;  // running index of the visited cells; this lane takes visit % kNearLanes == sub
+    const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic: wrapped cells, minimal image in z
     // three source families: direct (mirror sign +1), bottom images, top images
     for (int fam = 0; fam < 3; ++fam) {
       double zt, qf;  // z of the point whose neighbours are searched; strength factor
@@ -251,9 +273,17 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
       else if (fam == 1) { if (g.gamma_b == 0.0 || me.z >= g.r_cut) continue; zt = -me.z; qf = g.gamma_b; }
       else { if (g.gamma_t == 0.0 || g.H - me.z >= g.r_cut) continue; zt = 2.0 * g.H - me.z; qf = g.gamma_t; }
       int zlo = (int)floor((zt - g.r_cut) / g.cwz), zhi = (int)floor((zt + g.r_cut) / g.cwz);
-      zlo = max(zlo, 0);
-      zhi = min(zhi, g.ncz - 1);
-      for (int cz = zlo; cz <= zhi; ++cz) {
+      int cz0 = 0;
+      if (tp) {
+        cz0 = min(max((int)floor(zt / g.cwz), 0), g.ncz - 1);
+        zlo = g.ncz < 3 ? 0 : -1;
+        zhi = g.ncz < 3 ? g.ncz - 1 : 1;
+      } else {
+        zlo = max(zlo, 0);
+        zhi = min(zhi, g.ncz - 1);
+      }
+      for (int oz = zlo; oz <= zhi; ++oz) {
+        const int cz = !tp ? oz : (g.ncz < 3 ? oz : (cz0 + oz + g.ncz) % g.ncz);
         for (int oy = ylo; oy <= yhi; ++oy) {
           const int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
           for (int ox = xlo; ox <= xhi; ++ox, ++visit) {
@@ -267,7 +297,9 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
               dx -= g.Lx * rint(dx / g.Lx);
               dy -= g.Ly * rint(dy / g.Ly);
               const double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
-              near_pair<R>(g, dx, dy, me.z - zs, qf * o.q, ph, ex, ey, ez);
+              double dz = me.z - zs;
+              if (tp) dz -= g.H * rint(dz / g.H);
+              near_pair<R>(g, dx, dy, dz, qf * o.q, ph, ex, ey, ez);
             }
           }
         }

@@ -58,12 +58,16 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   if (!std::isfinite(p->g_w) || p->g_w < 0.0) return DPSE_EINVAL;
   if (!is_pow2(p->Nx) || !is_pow2(p->Ny) || p->Nx < 32 || p->Ny < 32 || p->Nx > 1024 || p->Ny > 1024)
     return DPSE_EINVAL;
-  if (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024) return DPSE_EINVAL;
+  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY))
+    return DPSE_EINVAL;
+  const bool tp = (p->flags & DPSE_TRIPLY) != 0;
+  if (tp ? (p->Nz < 32 || !is_pow2(p->Nz) || p->Nz > 1024) : (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024))
+    return DPSE_EINVAL;
   if (p->precision != DPSE_FP64 && p->precision != DPSE_MIXED) return DPSE_EINVAL;
-  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP)) return DPSE_EINVAL;
   const bool uniform = (p->flags & DPSE_UNIFORM_FAST) != 0;
   const bool one = (p->flags & DPSE_ONE_JUMP) != 0;
   if (uniform && one) return DPSE_EINVAL;
+  if (tp && (uniform || one || p->eps_bottom != p->eps || p->eps_top != p->eps)) return DPSE_EINVAL;
   if (uniform && !(p->eps_bottom == p->eps && p->eps_top == p->eps)) return DPSE_EINVAL;
   const bool jump_b = p->eps_bottom != p->eps, jump_t = p->eps_top != p->eps;
   if (one && jump_b == jump_t) return DPSE_EINVAL;
@@ -84,9 +88,10 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     rc += 4.0 * p->g_w;  // r_cut = r_nf + n_sigma g_w (Sec. 5.1)
   }
   if (!(rc > 0.0) || rc >= 0.5 * std::fmin(p->Lx, p->Ly)) return DPSE_EINVAL;
+  if (tp && (rc >= 0.5 * p->H || p->H < 4.0 * H_E)) return DPSE_EINVAL;
   // position-independent necessary conditions of Sec. 4.2 / 5.3 (h_min <= H/2);
   // they concern the images, which the uniform-permittivity solver has none of
-  if (!fast && (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H)) return DPSE_EINVAL;
+  if (!fast && !tp && (rc >= 1.5 * p->H || 2.0 * H_E >= 1.5 * p->H)) return DPSE_EINVAL;
   // Chebyshev domain: [-3 H_E, H + 3 H_E] with two jumps (Sec. 5.2.2); the
   // free-space solve (Sec. 3.1.1) needs only the span of the sources, and
   // with one jump of its images too
@@ -97,6 +102,9 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   } else if (one) {
     za = jump_b ? -p->H - H_E : -H_E;
     zb = jump_b ? p->H + H_E : 2.0 * p->H + H_E;
+  } else if (tp) {  // the uniform periodic nodes, z_c = (Nz - 1 - c) H / Nz
+    za = 0.0;
+    zb = p->H - p->H / p->Nz;
   }
 
   std::memset(info, 0, sizeof(*info));
@@ -130,15 +138,21 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     g->zmin_ok = 4.0 * p->g_w;
     g->zmax_ok = p->H - 4.0 * p->g_w;
     g->Nx = p->Nx; g->Ny = p->Ny; g->Nz = p->Nz; g->nkx = p->Nx / 2 + 1;
-    // the one-jump solver runs the free-space path of the uniform solver
-    g->ng = ng; g->flags = p->flags | (one ? DPSE_UNIFORM_FAST : 0);
+    // the one-jump solver runs the free-space path of the uniform solver; the
+    // triply periodic one has no groups, images, correction or gauge either
+    g->ng = ng;
+    g->flags = p->flags | (one ? DPSE_UNIFORM_FAST : 0) | (tp ? (DPSE_UNIFORM_FAST | DPSE_GAUGE_NONE) : 0);
+    if (tp) {  // any height, wrapped into [0, H)
+      g->zmin_ok = -HUGE_VAL;
+      g->zmax_ok = HUGE_VAL;
+    }
     g->B = std::min(dpse::kBin, std::min(p->Nx, p->Ny));
     g->nbx = p->Nx / g->B; g->nby = p->Ny / g->B;
     // z buckets of the particles (charges and images: centres within H_E of
     // the domain's interior)
-    g->zb_lo = za + H_E;
+    g->zb_lo = tp ? -H_E : za + H_E;  // periodic copies reach H_E beyond either end
     g->zb_w = 0.5 * H_E;
-    g->nzb = (int)std::ceil((zb - za - 2.0 * H_E) / g->zb_w) + 1;
+    g->nzb = (int)std::ceil((tp ? p->H + 2.0 * H_E : zb - za - 2.0 * H_E) / g->zb_w) + 1;
     g->ncx = std::max(1, std::min(1024, (int)std::floor(p->Lx / rc)));
     g->ncy = std::max(1, std::min(1024, (int)std::floor(p->Ly / rc)));
     g->ncz = std::max(1, std::min(1024, (int)std::floor(p->H / rc)));
@@ -154,7 +168,7 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
       double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
       if (z < 3.0 * H_E) bot_begin = j;
     }
-    if (fast) {  // one group: no wall band
+    if (fast || tp) {  // one group: no wall band
       top_end = 0;
       bot_begin = N;
     }
@@ -358,6 +372,14 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
     long double c = (j == 0 || j == nint) ? 1.0L : 2.0L;
     wq[j] = (double)(c / nint * acc * g.zR * g.h * g.h);
   }
+  const bool tp = (g.flags & DPSE_TRIPLY) != 0;
+  if (tp) {  // uniform periodic nodes, descending like the Chebyshev ones; weight h^2 h_z
+    const double hz = g.H / N;
+    for (int j = 0; j < N; ++j) {
+      z[j] = (N - 1 - j) * hz;
+      wq[j] = g.h * g.h * hz;
+    }
+  }
   std::vector<double> T0, dT0, TH, dTH;
   cheb_table(N, ((long double)0.0 - g.zc) / g.zR, T0, dT0);
   cheb_table(N, ((long double)g.H - g.zc) / g.zR, TH, dTH);
@@ -413,7 +435,8 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
     }
     return tw;
   };
-  auto tox = twid(g.Nx), toy = twid(g.Ny), toz = twid(2 * (N - 1));
+  // z twiddles: the DCT's even extension (length 2(Nz - 1)), or the periodic z transform (length Nz)
+  auto tox = twid(g.Nx), toy = twid(g.Ny), toz = twid(tp ? N : 2 * (N - 1));
   std::vector<float2> txf(tox.size()), tyf(toy.size());
   for (size_t i = 0; i < tox.size(); ++i) txf[i] = make_float2((float)tox[i].x, (float)tox[i].y);
   for (size_t i = 0; i < toy.size(); ++i) tyf[i] = make_float2((float)toy[i].x, (float)toy[i].y);

@@ -17,6 +17,7 @@ DPSE_GAUGE_NONE = 1
 DPSE_KMAX_GT = 2
 DPSE_UNIFORM_FAST = 4
 DPSE_ONE_JUMP = 8
+DPSE_TRIPLY = 16
 
 _STATUS = {
     0: "DPSE_OK", 1: "DPSE_EINVAL", 2: "DPSE_ENOMEM", 3: "DPSE_EHIP", 4: "DPSE_ENONNEUTRAL",
@@ -137,6 +138,8 @@ def _params(p, precision: int = DPSE_FP64, delta: float = 0.0) -> _Params:
         flags |= DPSE_UNIFORM_FAST
     if getattr(p, "one_jump", False):
         flags |= DPSE_ONE_JUMP
+    if getattr(p, "triply", False):
+        flags |= DPSE_TRIPLY
     return _Params(Lx=p.Lx, Ly=p.Ly, H=p.H, eps=p.eps, eps_bottom=p.eps_b, eps_top=p.eps_t, xi=p.xi,
                    g_w=getattr(p, "g_w", 0.0), Nx=p.Nx, Ny=p.Ny, Nz=p.Nz, support=getattr(p, "n_g", 0),
                    r_cut=p.r_cut, delta=delta, precision=precision, flags=flags)

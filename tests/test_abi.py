@@ -99,3 +99,17 @@ def test_one_jump_flag_validation():
                 pb.copy(uniform_fast=True)):
         with pytest.raises(dp.DpseError):
             dp.derive(bad)
+
+
+def test_triply_flag_validation():
+    """The triply periodic variant: equal permittivities, Nz a power of two,
+    a period of at least 4 H_E, r_cut below half of it, no other solver flag."""
+    from workloads import SlabParams
+    p = SlabParams(Lx=16.0, Ly=16.0, H=16.0, eps=1.0, eps_b=1.0, eps_t=1.0, xi=1.0, Nx=64, Ny=64, Nz=64,
+                   r_cut=3.0, triply=True)
+    info = dp.derive(p)
+    assert info["z_lo"] == 0.0 and abs(info["z_hi"] - (16.0 - 0.25)) < 1e-12
+    for bad in (p.copy(Nz=65), p.copy(eps_b=0.5), p.copy(H=8.0), p.copy(uniform_fast=True),
+                p.copy(one_jump=True), p.copy(H=5.5, r_cut=3.0)):
+        with pytest.raises(dp.DpseError):
+            dp.derive(bad)
