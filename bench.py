@@ -302,6 +302,28 @@ def bench_bd(dp, torch, steps):
     return out
 
 
+def bench_triply(dp, torch, steps):
+    """The triply periodic performance workload of Sec. 7.4 (2 x 10^4
+    charges, 185 x 185 x 100, 64^2 x 32, point charges, g_t = 1.2 h): solve
+    time in mixed precision and FP64 with the per-stage split. The paper
+    quotes 0.84 ms for this comparison (single precision, 70^2 grid, RTX
+    2080 Ti); another machine's figure, context only."""
+    import workloads as W
+    p, pos, q = W.config_triply(0)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    out = {"n": len(q), "grid": [p.Nx, p.Ny, p.Nz], "paper_ms_rtx2080ti": 0.84}
+    forces = {}
+    for name, prec in (("mixed", dp.DPSE_MIXED), ("fp64", dp.DPSE_FP64)):
+        r = time_path(dp, torch, p, tpos, tq, prec, steps, 3)
+        out[name] = {"ms": 1e3 * r["wall_s"] / steps, "evals_per_s": len(q) / (r["wall_s"] / steps),
+                     "p50_ms": float(np.percentile(r["lat_ms"], 50)),
+                     "stages_ms": {k: round(v, 4) for k, v in r["stages"].items()}}
+        forces[name] = r["F"]
+    out["mixed_vs_fp64_rel_rms_force"] = rel_rms(forces["mixed"], forces["fp64"])
+    return out
+
+
 def bench_walls(dp, torch, steps):
     """The jump workload with fixed charge densities on both walls (Sec. 2
     eq. rho): Gaussians of s = 4 centred in the box with total charge +64
@@ -436,6 +458,8 @@ def main(argv=None):
     ap.add_argument("--batch-branches", type=int, default=8)
     ap.add_argument("--uniform", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the uniform-permittivity and one-jump solvers against the general one")
+    ap.add_argument("--triply", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the triply periodic variant on the paper's TP workload")
     ap.add_argument("--bd", action=argparse.BooleanOptionalAction, default=True,
                     help="also time Brownian-dynamics steps with and without far-field reuse")
     ap.add_argument("--walls", action=argparse.BooleanOptionalAction, default=True,
@@ -518,6 +542,9 @@ def main(argv=None):
     if a.uniform:
         line["one_jump"] = bench_one_jump(dp, torch, a.steps)
         print(f"[bench] one jump: {line['one_jump']}", file=sys.stderr, flush=True)
+    if a.triply:
+        line["triply_periodic"] = bench_triply(dp, torch, a.steps)
+        print(f"[bench] triply periodic: {line['triply_periodic']}", file=sys.stderr, flush=True)
     if a.bd:
         line["brownian_dynamics"] = bench_bd(dp, torch, a.steps)
         print(f"[bench] brownian dynamics: {line['brownian_dynamics']}", file=sys.stderr, flush=True)

@@ -6,6 +6,8 @@
 // (eqs. Ufinal, fqE, self term of Sec. 6.3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "dpse_internal.h"
 
 namespace dpse {
@@ -239,21 +241,23 @@ __device__ inline void near_pair(const Geom& g, double dx, double dy, double dz,
   ez += qr * e * (R)dz;
 }
 
-// kNearLanes lanes per target charge (cell-sorted order), each taking every
-// kNearLanes-th of the neighbouring cells; the lanes' sums are combined by a
-// butterfly inside the lane group. Sources: other charges in the 27
-// neighbouring cells (minimal image), and the bottom/top images of all
-// charges, found through the mirror points (x, y, -z) and (x, y, 2H - z).
-constexpr int kNearLanes = 8;
-
-template <typename R>
+// L lanes per target charge (cell-sorted order); the lanes' sums are combined
+// by a butterfly inside the lane group. With BY_CELL each lane takes every
+// L-th of the neighbouring cells (few candidates per cell); otherwise every
+// lane visits every cell and takes every L-th charge in it (many candidates:
+// short serial chains per lane and many waves in flight). Sources: other
+// charges in the 27 neighbouring cells (minimal image), and the bottom/top
+// images of all charges, found through the mirror points (x, y, -z) and
+// (x, y, 2H - z).
+template <typename R, int L, bool BY_CELL>
 __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part* __restrict__ srt,
                                                    const int* __restrict__ idx, const int* __restrict__ off,
                                                    double4* near4) {
+  static_assert(kThreads % L == 0 && L <= 64, "lane groups inside a wave");
   const int64_t gt = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  const int64_t t = gt / kNearLanes;
-  const int sub = (int)(gt % kNearLanes);
-  const bool active = t < n;  // lane groups never straddle the end (kThreads is a multiple of kNearLanes)
+  const int64_t t = gt / L;
+  const int sub = (int)(gt % L);
+  const bool active = t < n;  // lane groups never straddle the end (kThreads is a multiple of L)
   R ph = 0, ex = 0, ey = 0, ez = 0;
   if (active) {
     const Part me = srt[t];
@@ -264,7 +268,7 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
     const bool xall = g.ncx < 3, yall = g.ncy < 3;
     if (xall) { xlo = 0; xhi = g.ncx - 1; }
     if (yall) { ylo = 0; yhi = g.ncy - 1; }
-    int visit = 0;  // running index of the visited cells; this lane takes visit % kNearLanes == sub
+    int visit = 0;  // running index of the visited cells (BY_CELL: this lane takes visit % L == sub)
     const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic: wrapped cells, minimal image in z
     // three source families: direct (mirror sign +1), bottom images, top images
     for (int fam = 0; fam < 3; ++fam) {
@@ -287,10 +291,10 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
         for (int oy = ylo; oy <= yhi; ++oy) {
           const int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
           for (int ox = xlo; ox <= xhi; ++ox, ++visit) {
-            if (visit % kNearLanes != sub) continue;
+            if (BY_CELL && visit % L != sub) continue;
             const int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
             const int c = (cz * g.ncy + yy) * g.ncx + xx;
-            for (int s = off[c]; s < off[c + 1]; ++s) {
+            for (int s = off[c] + (BY_CELL ? 0 : sub); s < off[c + 1]; s += (BY_CELL ? 1 : L)) {
               if (fam == 0 && s == t) continue;
               const Part o = srt[s];
               double dx = me.x - o.x, dy = me.y - o.y;
@@ -307,7 +311,7 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
     }
   }
 #pragma unroll
-  for (int o = 1; o < kNearLanes; o <<= 1) {
+  for (int o = 1; o < L; o <<= 1) {
     ph += __shfl_xor(ph, o, 64);
     ex += __shfl_xor(ex, o, 64);
     ey += __shfl_xor(ey, o, 64);
@@ -488,11 +492,25 @@ hipError_t launch_bin(dpse_plan* p, int64_t n) {
   return hipGetLastError();
 }
 
+template <typename R, int L, bool BY_CELL>
+void near_as(dpse_plan* p, int64_t n) {
+  int nb = (int)((n * L + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL((k_near<R, L, BY_CELL>), dim3(nb), dim3(kThreads), 0, p->stream, p->g, n,
+                     (const Part*)p->w.nsrt, (const int*)p->w.nsrt_idx, (const int*)p->w.cell_off, p->w.near4);
+}
+
+// Lanes per target from the expected candidates per target (charges in the
+// neighbouring cells at uniform density): 8 lanes over cells below 256
+// candidates (the slab workloads: 25-100), 32 or 64 lanes over the charges
+// of every cell beyond (the triply periodic workload: ~2100).
 template <typename R>
 hipError_t launch_near(dpse_plan* p, int64_t n) {
-  int nb = (int)((n * kNearLanes + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_near<R>, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, (const Part*)p->w.nsrt,
-                     (const int*)p->w.nsrt_idx, (const int*)p->w.cell_off, p->w.near4);
+  const Geom& g = p->g;
+  const double cells = (double)std::min(g.ncx, 3) * std::min(g.ncy, 3) * std::min(g.ncz, 3);
+  const double cand = (double)n * cells / ((double)g.ncx * g.ncy * g.ncz);
+  if (cand < 256.0) near_as<R, 8, true>(p, n);
+  else if (cand < 1024.0) near_as<R, 32, false>(p, n);
+  else near_as<R, 64, false>(p, n);
   return hipGetLastError();
 }
 

@@ -867,8 +867,9 @@ int dpse_plan_set_walls(dpse_plan* p, const double* sigma_b, const double* sigma
       c.take((char**)&wl.phis, G * rs);
       c.take(&wl.scal, 8);
       // one partial per block of the gather interpolation (x,y tiles of 16,
-      // at least 4 nodes per block)
-      c.take(&wl.part, (size_t)(g.Nx / 16) * (g.Ny / 16) * ((g.Nz + 3) / 4));
+      // at least 4 nodes per block, split over more blocks below 512 of them)
+      const size_t nbl = (size_t)(g.Nx / 16) * (g.Ny / 16) * ((g.Nz + 3) / 4);
+      c.take(&wl.part, std::max<size_t>(nbl, 2048));
       return c.off;
     };
     const size_t bytes = carve(nullptr);
