@@ -174,7 +174,9 @@ namespace dpse {
 
 // Stage launchers (each enqueues on plan->stream). R = double or float.
 hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double* q);
-hipError_t launch_bin(dpse_plan* p, int64_t n);
+hipError_t launch_bin(dpse_plan* p, int64_t n);        // both of:
+hipError_t launch_bin_grid(dpse_plan* p, int64_t n);   // bins of spreading and interpolation
+hipError_t launch_bin_cells(dpse_plan* p, int64_t n);  // cell list of the near field
 template <typename R> hipError_t launch_spread(dpse_plan* p);
 template <typename R> hipError_t launch_fft_forward(dpse_plan* p);
 template <typename R> hipError_t launch_column(dpse_plan* p);

@@ -471,25 +471,40 @@ hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double*
   return hipGetLastError();
 }
 
-hipError_t launch_bin(dpse_plan* p, int64_t n) {
+// Bins of the grid stages: counting sort of charges and images by (x,y tile
+// bin, z bucket).
+hipError_t launch_bin_grid(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   hipError_t e = fill_int(w.bin_cnt, 0, p->nkeys + 1, s);
-  if (e == hipSuccess) e = fill_int(w.cell_cnt, 0, p->ncells + 1, s);
   if (e != hipSuccess) return e;
   int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
-  int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      (const int*)w.n_img, w.bin_cnt);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
   hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta);
+  return hipGetLastError();
+}
+
+// Cell list of the near field: counting sort of the charges by cell.
+hipError_t launch_bin_cells(dpse_plan* p, int64_t n) {
+  hipStream_t s = p->stream;
+  Workspace& w = p->w;
+  hipError_t e = fill_int(w.cell_cnt, 0, p->ncells + 1, s);
+  if (e != hipSuccess) return e;
+  int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext, w.cell_cnt);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.cell_cnt, w.cell_off, w.cell_cur,
                      p->ncells);
   hipLaunchKernelGGL(k_scatter_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      w.cell_cur, w.nsrt, w.nsrt_idx);
   return hipGetLastError();
+}
+
+hipError_t launch_bin(dpse_plan* p, int64_t n) {
+  hipError_t e = launch_bin_grid(p, n);
+  return e == hipSuccess ? launch_bin_cells(p, n) : e;
 }
 
 template <typename R, int L, bool BY_CELL>

@@ -524,9 +524,9 @@ static const char* kStageNames[DPSE_NUM_STAGES] = {
 
 }  // extern "C"
 
-// One solve: prep and binning, then the near field on the plan's side stream
-// (it needs only the cell list) while the far-field stages run on the plan's
-// stream, joined before the gauge constant and the outputs.
+// One solve: validation and images, then the cell list and the near field on
+// the plan's side stream while the grid bins and the far-field stages run on
+// the plan's stream, joined before the gauge constant and the outputs.
 template <typename R>
 static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,
                                double* phi, double* force, hipEvent_t* ev) {
@@ -544,7 +544,6 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   p->wall_part = nullptr;  // set by whichever kernel forms the wall term
   p->wall_nparts = 0;
   start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
-  start(1, main); if (e == hipSuccess) e = dpse::launch_bin(p, n); end(1, main);
   // fork the near field (stage 7) and its part of the gauge; inside a graph
   // capture they stay on the capturing stream (see dpse_solve_graph)
   const bool fork = !p->capturing;
@@ -553,11 +552,13 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
   p->stream = ns;
   start(7, ns);
+  if (e == hipSuccess) e = dpse::launch_bin_cells(p, n);  // only the near field needs the cell list
   if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
   if (e == hipSuccess) e = dpse::launch_near_origin(p, n);
   end(7, ns);
   if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
   p->stream = main;
+  start(1, main); if (e == hipSuccess) e = dpse::launch_bin_grid(p, n); end(1, main);
   start(2, main); run(dpse::launch_spread<R>); end(2, main);
   start(3, main); run(dpse::launch_fft_forward<R>); end(3, main);
   start(4, main); run(dpse::launch_column<R>); end(4, main);
