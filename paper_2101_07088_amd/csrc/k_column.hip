@@ -37,7 +37,7 @@ constexpr int kThreads = 256;
 constexpr int kColumnKE[] = {2048, 1024, 4096, 2048, 4096};
 constexpr int kColumnNT[] = {256, 256, 256, 512, 512};  // threads per workgroup
 constexpr int kNumColumn = 5;
-constexpr int kMaxMB = 32;    // modes per block: 8 MB chain threads <= kThreads
+constexpr int kMaxMB = 32;    // modes per block (16 MB chain threads <= the block's threads)
 // dynamic LDS per block: 160 KB per workgroup less a margin for the static
 // arrays of the kernel (under 3 KB)
 constexpr size_t kMaxLds = 156 * 1024;
@@ -81,9 +81,11 @@ __device__ inline void mode_wave(const Geom& g, int mi, double& kk, int& keep) {
   if (g.flags & DPSE_UNIFORM_FAST) keep = 0;  // nothing to correct without jumps
 }
 
-// Plan-time factorisation of the per-mode chains (they depend on kappa only):
-// the elimination multipliers cp_r of the even (rows n = 2r) and odd (n =
-// 2r+1) chains, stored chain-major, cpiv[(par * ceil(N/2) + r) * nmodes + mode].
+// Plan-time factorisation of the per-mode chains (they depend on kappa only)
+// for the twisted elimination of the column kernel: for the even (rows n =
+// 2r) and odd (n = 2r+1) chain of L rows, the downward multipliers cp_r above
+// the middle row t = L/2, the upward ones cq_r below it and the inverse of the
+// middle row's pivot at t; chain-major, cpiv[(par * ceil(N/2) + r) * nmodes + mode].
 __global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __restrict__ ctab,
                                                      double* __restrict__ cpiv) {
   const int nmodes = g.Ny * g.nkx, N = g.Nz;
@@ -98,14 +100,28 @@ __global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __res
   const double* cb = ctab + N;
   const double* cc = ctab + 2 * N;
   const int half0 = (N + 1) / 2;
+  const int L = par == 0 ? (N + 1) / 2 : N / 2, mt = L / 2;
+  double* out = cpiv + (size_t)par * half0 * nmodes + mi;
+  // downwards to the middle row: cp_r = sup_r / (dia_r - sub_r cp_{r-1})
   double cp = 0.0;
-  int r = 0;
-  for (int n = par; n < N; n += 2, ++r) {
+  for (int r = 0; r < mt; ++r) {
+    const int n = par + 2 * r;
     const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
-    const double inv = rcp_refined(fma(-sub, cp, dia));
-    cp = sup * inv;
-    cpiv[(size_t)(par * half0 + r) * nmodes + mi] = cp;
+    cp = sup * rcp_refined(fma(-sub, cp, dia));
+    out[(size_t)r * nmodes] = cp;
   }
+  // upwards to the middle row: cq_r = sub_r / (dia_r - sup_r cq_{r+1})
+  double cq = 0.0;
+  for (int r = L - 1; r > mt; --r) {
+    const int n = par + 2 * r;
+    const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
+    cq = sub * rcp_refined(fma(-sup, cq, dia));
+    out[(size_t)r * nmodes] = cq;
+  }
+  // the middle row's pivot, inverted
+  const int n = par + 2 * mt;
+  const double sub = -kap2 * ca[n], dia = fma(kap2, cb[n], 1.0), sup = -kap2 * cc[n];
+  out[(size_t)mt * nmodes] = rcp_refined(dia - sub * cp - sup * cq);
 }
 
 // Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8)
@@ -242,117 +258,176 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
   // 2. tridiagonal chains: for each mode and parity, the mode equations in the
   //    unknowns y''_n of that parity, with right-hand sides Re/Im g of psi_i*,
   //    psi_o*, and the unit free constant (kappa^2 on the chain's first row).
-  //    Four threads per chain, one real right-hand side each (the first also
-  //    carries the free constant); each recomputes the elimination pivots.
-  //    Both sweeps move through the chain in groups of kSweep rows: the LDS
-  //    operands of a group are loaded together and its results stored
-  //    together, so the serial recurrence runs on registers and the LDS
-  //    latency is paid once per group instead of once per row.
+  //    Twisted (two-ended) elimination: for every chain and right-hand side
+  //    one thread eliminates downwards from the first row to the middle row
+  //    t = L/2 and another upwards from the last row, with the plan's
+  //    multipliers of each direction; both then form the middle unknown and
+  //    substitute back outwards, so the serial recurrences are half as long.
+  //    Four right-hand sides per chain (the first thread of each side also
+  //    carries the free constant, whose right-hand side vanishes below row 0).
   constexpr int kSweep = 8;
-  if (tid < 8 * MB) {
-    const int k = tid >> (logMB + 1);          // right-hand side: 0 Re i, 1 Im i, 2 Re o, 3 Im o
-    const int cm = tid & (2 * MB - 1);
+  if (tid < 16 * MB) {
+    const int side = tid >> (logMB + 3);         // 0: rows 0 .. t-1, 1: rows L-1 .. t+1
+    const int u = tid & (8 * MB - 1);
+    const int k = u >> (logMB + 1);              // right-hand side: 0 Re i, 1 Im i, 2 Re o, 3 Im o
+    const int cm = u & (2 * MB - 1);
     const int m = cm & (MB - 1), par = cm >> logMB;
-    // row r of the chain: X at Xp[r * s4], coefficients at cp0[2 r], multiplier at crow[r]
+    // row r of the chain: X at Xp[r * s4], coefficients at ap[2 r] etc., multiplier at crow[r]
     double* Xp = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1) + par * 2 * MB;
     const int s4 = 4 * MB;
     const double* ap = ca + par;
     const double* bp = cb + par;
+    const double* cp = cc + par;
     const double* gp = gsc + par;
     const double* crow = spA + m * cst + par * half0;
     double* hrow = spB + m * cst + par * half0;
     const double kap2 = s_kap[m] * s_kap[m];
-    const int L = par == 0 ? (N + 1) / 2 : N / 2;
-    double d = 0.0, dh = 0.0;
-    // forward: d_r = (g_r x_r - sub_r d_{r-1}) / (dia_r - sub_r cp_{r-1}); the
-    // pivots no longer recur (cp comes from the plan), only d and dh do
-    auto fwd = [&](int r, double xv, double av, double bv, double gv, double pv, double& dv, double& dhv) {
-      const double inv = rcp_refined(fma(kap2 * av, pv, fma(kap2, bv, 1.0)));
-      const double sub = -kap2 * av;
-      d = (gv * xv - sub * d) * inv;
-      dh = ((r == 0 ? kap2 : 0.0) - sub * dh) * inv;
-      dv = d;
-      dhv = dh;
-    };
-    const int Lfull = L & ~(kSweep - 1);
-    for (int r0 = 0; r0 < Lfull; r0 += kSweep) {
-      double* Xr = Xp + r0 * s4;
-      const double* ar = ap + 2 * r0;
-      const double* br = bp + 2 * r0;
-      const double* gr = gp + 2 * r0;
-      const double* cr = crow + r0 - 1;  // in LDS for r0 = 0 too (the value is not used)
-      double xv[kSweep], av[kSweep], bv[kSweep], gv[kSweep], pv[kSweep];
+    const int L = par == 0 ? (N + 1) / 2 : N / 2, mt = L / 2;
+    // rows go in groups of kSweep: the LDS operands of a group are loaded
+    // together and its results stored together, so the serial recurrence
+    // runs on registers and the LDS latency is paid once per group
+    if (side == 0) {
+      // d_r = (g_r x_r - sub_r d_{r-1}) / (dia_r - sub_r cp_{r-1})
+      double d = 0.0, dh = 0.0;
+      auto row = [&](int r, double av, double bv, double gv, double xv, double pv, double& dv, double& hv) {
+        const double inv = rcp_refined(fma(kap2 * av, pv, fma(kap2, bv, 1.0)));
+        const double sub = -kap2 * av;
+        d = (gv * xv - sub * d) * inv;
+        dh = ((r == 0 ? kap2 : 0.0) - sub * dh) * inv;
+        dv = d;
+        hv = dh;
+      };
+      int r0 = 0;
+      for (; r0 + kSweep <= mt; r0 += kSweep) {
+        double av[kSweep], bv[kSweep], gv[kSweep], xv[kSweep], pv[kSweep], dv[kSweep], hv[kSweep];
 #pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
-        xv[u] = Xr[u * s4];
-        av[u] = ar[2 * u];
-        bv[u] = br[2 * u];
-        gv[u] = gr[2 * u];
-        pv[u] = cr[u];
+        for (int q = 0; q < kSweep; ++q) {
+          const int r = r0 + q;
+          av[q] = ap[2 * r];
+          bv[q] = bp[2 * r];
+          gv[q] = gp[2 * r];
+          xv[q] = Xp[r * s4];
+          pv[q] = r > 0 ? crow[r - 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) row(r0 + q, av[q], bv[q], gv[q], xv[q], pv[q], dv[q], hv[q]);
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) Xp[(r0 + q) * s4] = dv[q];
+        if (k == 0) {
+#pragma unroll
+          for (int q = 0; q < kSweep; ++q) hrow[r0 + q] = hv[q];
+        }
       }
-      if (r0 == 0) pv[0] = 0.0;
-      double dv[kSweep], dhv[kSweep];
-#pragma unroll
-      for (int u = 0; u < kSweep; ++u) fwd(r0 + u, xv[u], av[u], bv[u], gv[u], pv[u], dv[u], dhv[u]);
-#pragma unroll
-      for (int u = 0; u < kSweep; ++u) Xr[u * s4] = dv[u];
-      if (k == 0) {
-#pragma unroll
-        for (int u = 0; u < kSweep; ++u) hrow[r0 + u] = dhv[u];
+      for (int r = r0; r < mt; ++r) {
+        double dv, hv;
+        row(r, ap[2 * r], bp[2 * r], gp[2 * r], Xp[r * s4], r > 0 ? crow[r - 1] : 0.0, dv, hv);
+        Xp[r * s4] = dv;
+        if (k == 0) hrow[r] = hv;
       }
-    }
-    for (int r = Lfull; r < L; ++r) {
-      double dv, dhv;
-      fwd(r, Xp[r * s4], ap[2 * r], bp[2 * r], gp[2 * r], r > 0 ? crow[r - 1] : 0.0, dv, dhv);
-      Xp[r * s4] = dv;
-      if (k == 0) hrow[r] = dhv;
+    } else {
+      // e_r = (g_r x_r - sup_r e_{r+1}) / (dia_r - sup_r cq_{r+1}); the free
+      // constant's right-hand side is zero here
+      double e = 0.0;
+      auto row = [&](double cv, double bv, double gv, double xv, double qv) {
+        const double inv = rcp_refined(fma(kap2 * cv, qv, fma(kap2, bv, 1.0)));
+        const double sup = -kap2 * cv;
+        e = (gv * xv - sup * e) * inv;
+        return e;
+      };
+      int r0 = L - 1;  // rows r0, r0 - 1, ..., r0 - kSweep + 1 > mt
+      for (; r0 - kSweep >= mt; r0 -= kSweep) {
+        double cv[kSweep], bv[kSweep], gv[kSweep], xv[kSweep], qv[kSweep], ev[kSweep];
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          const int r = r0 - q;
+          cv[q] = cp[2 * r];
+          bv[q] = bp[2 * r];
+          gv[q] = gp[2 * r];
+          xv[q] = Xp[r * s4];
+          qv[q] = r < L - 1 ? crow[r + 1] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) ev[q] = row(cv[q], bv[q], gv[q], xv[q], qv[q]);
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) Xp[(r0 - q) * s4] = ev[q];
+        if (k == 0) {
+#pragma unroll
+          for (int q = 0; q < kSweep; ++q) hrow[r0 - q] = 0.0;
+        }
+      }
+      for (int r = r0; r > mt; --r) {
+        Xp[r * s4] = row(cp[2 * r], bp[2 * r], gp[2 * r], Xp[r * s4], r < L - 1 ? crow[r + 1] : 0.0);
+        if (k == 0) hrow[r] = 0.0;
+      }
     }
   }
   __syncthreads();
-  if (tid < 8 * MB) {
-    const int k = tid >> (logMB + 1);
-    const int cm = tid & (2 * MB - 1);
-    const int m = cm & (MB - 1), par = cm >> logMB;
-    double* Xp = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1) + par * 2 * MB;
-    const int s4 = 4 * MB;
-    const double* crow = spA + m * cst + par * half0;
-    double* hrow = spB + m * cst + par * half0;
-    const int L = par == 0 ? (N + 1) / 2 : N / 2;
-    // back substitution x_r = d_r - cp_r x_{r+1} for rows L-2 .. 0: first the
-    // rows above a multiple of kSweep one by one, then whole groups (all in range)
-    double x = Xp[(L - 1) * s4];
-    double xh = hrow[L - 1];
-    int r = L - 2;
-    for (int i = 0; i < ((L - 1) & (kSweep - 1)); ++i, --r) {
-      const double c = crow[r];
-      x = fma(-c, x, Xp[r * s4]);
-      xh = fma(-c, xh, hrow[r]);
-      Xp[r * s4] = x;
-      if (k == 0) hrow[r] = xh;  // the only thread touching this chain's entries
+  {
+    // the middle row from both sides' eliminations, then back substitution:
+    // x_r = d_r - cp_r x_{r+1} above it, x_r = e_r - cq_r x_{r-1} below it
+    double xm = 0.0, xhm = 0.0;
+    int side = 0, k = 0, mt = 0, L = 0, s4 = 4 * MB;
+    double* Xp = nullptr;
+    double* hrow = nullptr;
+    const double* crow = nullptr;
+    if (tid < 16 * MB) {
+      side = tid >> (logMB + 3);
+      const int u = tid & (8 * MB - 1);
+      k = u >> (logMB + 1);
+      const int cm = u & (2 * MB - 1);
+      const int m = cm & (MB - 1), par = cm >> logMB;
+      Xp = reinterpret_cast<double*>(k < 2 ? B : A) + 2 * m + (k & 1) + par * 2 * MB;
+      crow = spA + m * cst + par * half0;
+      hrow = spB + m * cst + par * half0;
+      const double kap2 = s_kap[m] * s_kap[m];
+      L = par == 0 ? (N + 1) / 2 : N / 2;
+      mt = L / 2;
+      const double sub = -kap2 * ca[par + 2 * mt], sup = -kap2 * cc[par + 2 * mt];
+      const double itw = crow[mt];  // 1 / (dia_t - sub_t cp_{t-1} - sup_t cq_{t+1})
+      xm = (gsc[par + 2 * mt] * Xp[mt * s4] - sub * Xp[(mt - 1) * s4] - sup * Xp[(mt + 1) * s4]) * itw;
+      xhm = (-sub * hrow[mt - 1] - sup * hrow[mt + 1]) * itw;
     }
-    for (; r >= 0; r -= kSweep) {  // rows r, r-1, ..., r-kSweep+1 >= 0
-      double* Xr = Xp + (r - kSweep + 1) * s4;
-      const double* cr = crow + r - kSweep + 1;
-      double* hr = hrow + r - kSweep + 1;
-      double xv[kSweep], cv[kSweep], hv[kSweep];
-#pragma unroll
-      for (int u = 0; u < kSweep; ++u) {
-        xv[u] = Xr[u * s4];
-        cv[u] = cr[u];
-        hv[u] = hr[u];
+    __syncthreads();  // every read of the middle row precedes its overwrite
+    if (tid < 16 * MB) {
+      double x = xm, xh = xhm;
+      // rows r = a + dir q in groups of kSweep, with the same loads-first layout
+      const int dir = side == 0 ? -1 : 1;
+      int a = side == 0 ? mt - 1 : mt + 1;
+      const int cnt = side == 0 ? mt : L - 1 - mt;
+      if (side == 0) {
+        Xp[mt * s4] = xm;
+        if (k == 0) hrow[mt] = xhm;
       }
+      int done = 0;
+      for (; done + kSweep <= cnt; done += kSweep, a += dir * kSweep) {
+        double cv[kSweep], xv[kSweep], hv[kSweep];
 #pragma unroll
-      for (int u = kSweep - 1; u >= 0; --u) {
-        x = fma(-cv[u], x, xv[u]);
-        xh = fma(-cv[u], xh, hv[u]);
-        xv[u] = x;
-        hv[u] = xh;
+        for (int q = 0; q < kSweep; ++q) {
+          const int r = a + dir * q;
+          cv[q] = crow[r];
+          xv[q] = Xp[r * s4];
+          hv[q] = hrow[r];
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) {
+          x = fma(-cv[q], x, xv[q]);
+          xh = fma(-cv[q], xh, hv[q]);
+          xv[q] = x;
+          hv[q] = xh;
+        }
+#pragma unroll
+        for (int q = 0; q < kSweep; ++q) Xp[(a + dir * q) * s4] = xv[q];
+        if (k == 0) {
+#pragma unroll
+          for (int q = 0; q < kSweep; ++q) hrow[a + dir * q] = hv[q];
+        }
       }
-#pragma unroll
-      for (int u = 0; u < kSweep; ++u) Xr[u * s4] = xv[u];
-      if (k == 0) {
-#pragma unroll
-        for (int u = 0; u < kSweep; ++u) hr[u] = hv[u];
+      for (; done < cnt; ++done, a += dir) {
+        const double c = crow[a];
+        x = fma(-c, x, Xp[a * s4]);
+        xh = fma(-c, xh, hrow[a]);
+        Xp[a * s4] = x;
+        if (k == 0) hrow[a] = xh;
       }
     }
   }
@@ -862,7 +937,7 @@ int column_threads(int i) { return kColumnNT[i]; }
 bool column_valid(const Geom& g, int i) {
   if (i < 0 || i >= kNumColumn) return false;
   const int KE = kColumnKE[i], M = 2 * (g.Nz - 1);
-  return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && 8 * (KE / M) <= kColumnNT[i] &&
+  return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && 16 * (KE / M) <= kColumnNT[i] &&
          column_lds(g, KE) <= kMaxLds;
 }
 
