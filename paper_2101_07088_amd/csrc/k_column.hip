@@ -599,18 +599,22 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
   __syncthreads();
 
   // 6. derivative series into B: d_j = (2/R) sum_{m > j, m = j+1 mod 2} m y_m
-  //    (d_{N-1} = 0, d_0 halved), a suffix sum per mode and parity: one wave
-  //    per chain, lanes own consecutive entries, scanned from the top.
+  //    (d_{N-1} = 0, d_0 halved), a suffix sum per mode and parity: all
+  //    2 MB chains at once, G lanes per chain (the chains of a wave side by
+  //    side), lanes own consecutive entries, scanned from the top.
   {
-    const int lane = tid & 63, wv = tid >> 6;
+    constexpr int kW = NT / 64;                 // waves
+    const int cpw = (2 * MB + kW - 1) / kW;     // chains per wave (a power of two)
+    const int G = 64 / cpw;                     // lanes per chain
+    const int ch = tid / G, gl = tid & (G - 1);
     const double ir = 1.0 / Rz;
-    for (int ch = wv; ch < 2 * MB; ch += NT / 64) {
+    if (ch < 2 * MB) {  // whole lane groups
       const int m = ch & (MB - 1), q = ch >> logMB;  // q: parity of the output index j
       // outputs j = q, q+2, ... <= N-1; entry t (from the top) is j = jt - 2t
       const int jt = (N - 1) - (((N - 1) - q) & 1);
       const int Lc = jt / 2 + 1;
-      const int E = (Lc + 63) >> 6;
-      const int t0 = lane * E, t1 = min(Lc, t0 + E);
+      const int E = (Lc + G - 1) / G;
+      const int t0 = gl * E, t1 = min(Lc, t0 + E);
       double sx = 0.0, sy = 0.0;
       for (int t = t0; t < t1; ++t) {
         const int j = jt - 2 * t;
@@ -621,12 +625,12 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
           sy = fma(f, y.y, sy);
         }
       }
-      for (int o = 1; o < 64; o <<= 1) {
-        const double cx = __shfl_up(sx, o, 64), cy = __shfl_up(sy, o, 64);
-        if (lane >= o) { sx += cx; sy += cy; }
+      for (int o = 1; o < G; o <<= 1) {
+        const double cx = __shfl_up(sx, o, G), cy = __shfl_up(sy, o, G);
+        if (gl >= o) { sx += cx; sy += cy; }
       }
-      double ax = __shfl_up(sx, 1, 64), ay = __shfl_up(sy, 1, 64);
-      if (lane == 0) { ax = 0.0; ay = 0.0; }
+      double ax = __shfl_up(sx, 1, G), ay = __shfl_up(sy, 1, G);
+      if (gl == 0) { ax = 0.0; ay = 0.0; }
       for (int t = t0; t < t1; ++t) {
         const int j = jt - 2 * t;
         if (j + 1 < N) {
