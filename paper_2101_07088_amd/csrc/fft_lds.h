@@ -158,4 +158,82 @@ __device__ void fft_lds_r22(C* buf, int logL, int lognseq, int ss, int es, const
   }
 }
 
+// Two transforms of the same shape (two buffers, same twiddles) in lockstep:
+// every pass does the butterflies of both buffers, so the pair costs the
+// barriers of one transform and each thread has twice the independent work
+// between them.
+template <typename C, bool SEQ_FAST, int BPT4, int NTHR>
+__device__ void fft_lds_r22_pair(C* buf0, C* buf1, int logL, int lognseq, int ss, int es, const C* tw, bool inverse,
+                                 int tid) {
+  const int nseq = 1 << lognseq;
+  const int L = 1 << logL;
+  const int nb4 = L >> 2;
+  const int lognb4 = logL - 2;
+  int lh = 0;
+  if (logL & 1) {
+#pragma unroll
+    for (int q = 0; q < 2 * BPT4; ++q) {
+      const int t = tid + q * NTHR;
+      int s, b;
+      if (SEQ_FAST) { s = t & (nseq - 1); b = t >> lognseq; }
+      else { b = t & ((L >> 1) - 1); s = t >> (logL - 1); }
+      const int o = s * ss + (2 * b) * es;
+      const C u0 = buf0[o], v0 = buf0[o + es], u1 = buf1[o], v1 = buf1[o + es];
+      buf0[o] = cadd(u0, v0);
+      buf0[o + es] = csub(u0, v0);
+      buf1[o] = cadd(u1, v1);
+      buf1[o + es] = csub(u1, v1);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  for (; lh < logL; lh += 2) {
+    const int half = 1 << lh;
+    const int ts1 = (L >> 1) >> lh;
+    const int ts2 = ts1 >> 1;
+    C a[2][BPT4][4], w1[BPT4], w2[BPT4];
+    int base[BPT4];
+#pragma unroll
+    for (int q = 0; q < BPT4; ++q) {
+      const int t = tid + q * NTHR;
+      int s, b;
+      if (SEQ_FAST) { s = t & (nseq - 1); b = t >> lognseq; }
+      else { b = t & (nb4 - 1); s = t >> lognb4; }
+      const int grp = b >> lh, pos = b & (half - 1);
+      base[q] = s * ss + ((grp << (lh + 2)) + pos) * es;
+      w1[q] = tw[pos * ts1];
+      w2[q] = tw[pos * ts2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a[0][q][e] = buf0[base[q] + e * half * es];
+        a[1][q][e] = buf1[base[q] + e * half * es];
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      C* buf = bi == 0 ? buf0 : buf1;
+#pragma unroll
+      for (int q = 0; q < BPT4; ++q) {
+        C x1 = w1[q], x2 = w2[q];
+        if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
+        const C t1 = cmul(a[bi][q][1], x1), t3 = cmul(a[bi][q][3], x1);
+        const C b0 = cadd(a[bi][q][0], t1), b1 = csub(a[bi][q][0], t1);
+        const C b2 = cadd(a[bi][q][2], t3), b3 = csub(a[bi][q][2], t3);
+        const C u2 = cmul(b2, x2);
+        C u3 = cmul(b3, x2);  // times -i (forward) or +i (inverse)
+        {
+          const auto re = u3.x;
+          if (inverse) { u3.x = -u3.y; u3.y = re; }
+          else { u3.x = u3.y; u3.y = -re; }
+        }
+        buf[base[q]] = cadd(b0, u2);
+        buf[base[q] + 2 * half * es] = csub(b0, u2);
+        buf[base[q] + half * es] = cadd(b1, u3);
+        buf[base[q] + 3 * half * es] = csub(b1, u3);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dpse

@@ -136,6 +136,20 @@ __device__ inline int xcd_block(int b, int nb) {
   return x * per + min(x, extra) + b / kXcd;
 }
 
+// The two FFTs of a column workgroup: in lockstep where each thread holds at
+// most two radix-4 butterflies per buffer (one barrier per pass for both),
+// one after the other where the pair's registers would spill.
+template <int KE, int NT>
+__device__ __forceinline__ void fft2(double2* A, double2* B, int logM, int logMB, const double2* tw, int tid) {
+  constexpr int kBpt4 = KE / 4 / NT;  // KE == M * MB elements per buffer
+  if constexpr (kBpt4 <= 2) {
+    fft_lds_r22_pair<double2, true, kBpt4, NT>(A, B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+  } else {
+    fft_lds_r22<double2, true, kBpt4, NT>(A, logM, logMB, 1, 1 << logMB, tw, false, tid);
+    fft_lds_r22<double2, true, kBpt4, NT>(B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+  }
+}
+
 template <typename R, int KE, int NT>
 __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                      const typename CT<R>::T* __restrict__ fx_o,
@@ -234,8 +248,7 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
     }
   }
   __syncthreads();
-  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(A, logM, logMB, 1, MB, tw, false, tid);
-  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(B, logM, logMB, 1, MB, tw, false, tid);
+  fft2<KE, NT>(A, B, logM, logMB, tw, tid);
 
   // spare storage beyond index N of each buffer (N-2 complex = 2N-4 doubles per mode)
   double* spA = reinterpret_cast<double*>(A + N * MB);  // chain pivots
@@ -672,8 +685,7 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
     }
     __syncthreads();
   }
-  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(A, logM, logMB, 1, MB, tw, false, tid);
-  fft_lds_r22<double2, true, kElems / 4 / NT, NT>(B, logM, logMB, 1, MB, tw, false, tid);
+  fft2<KE, NT>(A, B, logM, logMB, tw, tid);
 
   // 8. add the correction at the window nodes and the k = 0 linear mode; write out
   for (int t = tid; t < N * MB; t += NT) {
