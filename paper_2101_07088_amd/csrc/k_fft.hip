@@ -48,11 +48,24 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const R* __restr
   const int64_t r_base = row0 + (int64_t)blockIdx.x * 2 * nseq;
   const int nr = (int)min((int64_t)2 * nseq, row0 + nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
-  for (int i = threadIdx.x; i < 2 * nseq * Nx; i += kThreads) {
-    int rl = i / Nx, x = i % Nx;
-    R v = rl < nr ? in[(r_base + rl) * Nx + x] : (R)0;
-    C* d = &buf[(rl >> 1) * Nx + bitrev(x, logN)];
-    if (rl & 1) d->y = v; else d->x = v;
+  // slot i of the buffer (nseq * Nx == kElems) takes x of rows 2s and 2s + 1;
+  // all global loads of the thread are issued before the LDS stores
+  constexpr int kPer = kElems / kThreads;
+  R v0[kPer], v1[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = i & (Nx - 1);
+    const int64_t r = r_base + 2 * s;
+    v0[q] = 2 * s < nr ? in[r * Nx + x] : (R)0;
+    v1[q] = 2 * s + 1 < nr ? in[(r + 1) * Nx + x] : (R)0;
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = i & (Nx - 1);
+    C d;
+    d.x = v0[q];
+    d.y = v1[q];
+    buf[s * Nx + bitrev(x, logN)] = d;
   }
   __syncthreads();
   fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(nseq), Nx, 1, tw, false, threadIdx.x);
@@ -130,18 +143,24 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
   const int kb = (blockIdx.x % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   const size_t off = (size_t)plane * Ny * nkx;
-  C a[kPer];
+  // Psi and Psi_z both loaded up front: the Psi_z loads are in flight
+  // during the first two transforms
+  C a[kPer], c[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+    a[q].x = 0; a[q].y = 0; c[q].x = 0; c[q].y = 0;
+    if (kb + kl < nkx) {
+      a[q] = psi[off + (size_t)ky * nkx + kb + kl];
+      c[q] = psiz[off + (size_t)ky * nkx + kb + kl];
+    }
+  }
   const double kyf = 2.0 * kPi / g.Ly;
 #pragma nounroll
   for (int f = 0; f < 3; ++f) {
-    if (f != 1) {
-      const C* src = f == 0 ? psi : psiz;
+    if (f == 2) {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-        a[q].x = 0; a[q].y = 0;
-        if (kb + kl < nkx) a[q] = src[off + (size_t)ky * nkx + kb + kl];
-      }
+      for (int q = 0; q < kPer; ++q) a[q] = c[q];
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -183,15 +202,31 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   const double kxf = 2.0 * kPi / g.Lx;
-  for (int i = threadIdx.x; i < nrow_blk * Nx; i += kThreads) {
-    int rl = i / Nx, k = i % Nx;
+  // nrow_blk * Nx == kElems / 2 slots; all global loads of the thread are
+  // issued before the LDS stores
+  constexpr int kPer = kElems / 2 / kThreads;
+  C la[kPer], lb[kPer], lc[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = i & (Nx - 1);
+    la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
+    if (rl < nr) {
+      const int kk = k <= Nx / 2 ? k : Nx - k;
+      const size_t o = (size_t)(r_base + rl) * nkx + kk;
+      la[q] = p0[o];
+      lb[q] = py[o];
+      lc[q] = pz[o];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = i & (Nx - 1);
     C z1, z2;
     z1.x = 0; z1.y = 0; z2.x = 0; z2.y = 0;
     if (rl < nr) {
       int kk = k <= Nx / 2 ? k : Nx - k;
       bool cj = k > Nx / 2;
-      size_t o = (size_t)(r_base + rl) * nkx + kk;
-      C a = p0[o], b = py[o], c = pz[o];
+      C a = la[q], b = lb[q], c = lc[q];
       if (kk == 0 || kk == Nx / 2) { a.y = 0; b.y = 0; c.y = 0; }
       R kxv = (kk == Nx / 2) ? (R)0 : (R)(kxf * kk);
       C ex;  // -i kx a
