@@ -218,6 +218,19 @@ int interp_splits(int blocks);
 // Sets kernel attributes once (before any stream capture).
 hipError_t prepare_kernels();
 
+// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8)
+// and every XCD has an L2 of its own. Where neighbouring workgroups share
+// 128-byte lines (mode blocks of the column solve, kx column blocks of the y
+// transforms, whose rows of nkx complex values are not line-aligned), the
+// block index is remapped to give every XCD one contiguous run of blocks,
+// taken in dispatch order: the lines two blocks share then meet in one L2
+// instead of being fetched from HBM by two. A bijection on [0, nb).
+__device__ inline int xcd_block(int b, int nb) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
+  return x * per + min(x, extra) + b / kXcd;
+}
+
 // Small helpers.
 hipError_t fill_int(int* ptr, int value, int64_t count, hipStream_t s);
 hipError_t fill_double(double* ptr, double value, int64_t count, hipStream_t s);

@@ -124,18 +124,6 @@ __global__ void __launch_bounds__(kThreads) k_pivots(Geom g, const double* __res
   out[(size_t)mt * nmodes] = rcp_refined(dia - sub * cp - sup * cq);
 }
 
-// Workgroups are handed to the 8 XCDs in turn (workgroup b to XCD b mod 8)
-// and every XCD has an L2 of its own. Neighbouring mode blocks share the
-// 128-byte lines of each z row of the spectra and of the pivots, so the
-// block index is remapped to give every XCD one contiguous run of mode
-// blocks, taken in dispatch order: the lines two blocks share then meet in
-// one L2 instead of being fetched from HBM by two. A bijection on [0, nb).
-__device__ inline int xcd_block(int b, int nb) {
-  constexpr int kXcd = 8;
-  const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
-  return x * per + min(x, extra) + b / kXcd;
-}
-
 // The two FFTs of a column workgroup: in lockstep where each thread holds at
 // most two radix-4 butterflies per buffer (one barrier per pass for both),
 // one after the other where the pair's registers would spill.

@@ -97,8 +97,9 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* d
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
   const int KB = KE / Ny, logKB = ilog2(KB);
   const int nblk = (nkx + KB - 1) / KB;
-  const int plane = p0 + blockIdx.x / nblk;
-  const int kb = (blockIdx.x % nblk) * KB;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int plane = p0 + blk / nblk;
+  const int kb = (blk % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   C* base = data + (size_t)plane * Ny * nkx;
   C v[kPer];
@@ -139,8 +140,9 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
   const int KB = KE / Ny, logKB = ilog2(KB);
   const int nblk = (nkx + KB - 1) / KB;
-  const int plane = blockIdx.x / nblk;
-  const int kb = (blockIdx.x % nblk) * KB;
+  const int blk = xcd_block(blockIdx.x, gridDim.x);
+  const int plane = blk / nblk;
+  const int kb = (blk % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   const size_t off = (size_t)plane * Ny * nkx;
   // Psi and Psi_z both loaded up front: the Psi_z loads are in flight
@@ -198,7 +200,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   __shared__ C tw[512];
   const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
   const int nrow_blk = kElems / (2 * Nx);  // rows per block (2 sequences per row)
-  const int64_t r_base = (int64_t)blockIdx.x * nrow_blk;
+  const int64_t r_base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * nrow_blk;
   const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   const double kxf = 2.0 * kPi / g.Lx;
