@@ -17,10 +17,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kElems = 2048;  // complex elements per LDS FFT buffer (x passes)
-// y passes: 32 KB of LDS per buffer, so that a block spans KB = kYElems / Ny
-// consecutive kx columns and its global rows are 128 bytes when Ny <= 256
+// y passes: 2048 complex elements per LDS buffer, a block spanning
+// KB = kYElems / Ny consecutive kx columns (row pieces of KB values; the
+// XCD-aware block order keeps the neighbours that share their lines in one L2)
 template <typename R>
-constexpr int kYElems = sizeof(R) == 8 ? 2048 : 4096;
+constexpr int kYElems = 2048;
 
 template <typename R>
 struct CT;
@@ -35,17 +36,43 @@ __host__ __device__ inline int ilog2(int v) {
   return l;
 }
 
-// R2C along x of rows [row0, row0 + nrows_total) of `in` (rows of length Nx).
+// Up to three ranges of one forward pass in one launch (the grid of the
+// inner charges and the one or two z bands of the outer grid): range s takes
+// rows (x pass) or planes (y pass) [lo[s], lo[s] + cnt[s]) of in[s] (x pass)
+// into out[s], with the blocks [first[s], first[s + 1]).
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const R* __restrict__ in,
-                                                        typename CT<R>::T* __restrict__ out, int64_t row0,
-                                                        int64_t nrows, const typename CT<R>::T* __restrict__ twg) {
+struct FftJobs {
+  const R* in[3];
+  typename CT<R>::T* out[3];
+  int lo[3], cnt[3];
+  int first[4];
+  int n;
+};
+
+// the range of block b (uniform; kernel-argument arrays read at constant indices)
+template <typename R>
+__device__ inline int job_of(const FftJobs<R>& J, int b) {
+  return (J.n > 1 && b >= J.first[1]) + (J.n > 2 && b >= J.first[2]);
+}
+template <typename T, int K>
+__device__ inline T pick3(const T (&a)[K], int s) {
+  return s == 0 ? a[0] : (s == 1 ? a[1] : a[2]);
+}
+
+// R2C along x of the row ranges of J (rows of length Nx).
+template <typename R>
+__global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R> J,
+                                                        const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
   __shared__ C buf[kElems];
   __shared__ C tw[512];
   const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
   const int nseq = kElems / Nx;              // row pairs per block
-  const int64_t r_base = row0 + (int64_t)blockIdx.x * 2 * nseq;
+  const int js = job_of(J, blockIdx.x);
+  const R* __restrict__ in = pick3(J.in, js);
+  C* __restrict__ out = pick3(J.out, js);
+  const int64_t row0 = pick3(J.lo, js), nrows = pick3(J.cnt, js);
+  const int64_t r_base = row0 + (int64_t)(blockIdx.x - pick3(J.first, js)) * 2 * nseq;
   const int nr = (int)min((int64_t)2 * nseq, row0 + nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   // slot i of the buffer (nseq * Nx == kElems) takes x of rows 2s and 2s + 1;
@@ -85,9 +112,9 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const R* __restr
   }
 }
 
-// Forward C2C along y, in place, for planes [p0, p0 + np).
+// Forward C2C along y, in place, for the plane ranges of J.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* data, int p0,
+__global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, const FftJobs<R> J,
                                                     const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
   constexpr int KE = kYElems<R>;
@@ -98,8 +125,11 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, typename CT<R>::T* d
   const int KB = KE / Ny, logKB = ilog2(KB);
   const int nblk = (nkx + KB - 1) / KB;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
-  const int plane = p0 + blk / nblk;
-  const int kb = (blk % nblk) * KB;
+  const int js = job_of(J, blk);
+  typename CT<R>::T* data = pick3(J.out, js);
+  const int lb = blk - pick3(J.first, js);
+  const int plane = pick3(J.lo, js) + lb / nblk;
+  const int kb = (lb % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   C* base = data + (size_t)plane * Ny * nkx;
   C v[kPer];
@@ -273,23 +303,47 @@ template <>
 const float2* twy<float>(dpse_plan* p) { return p->t.twy_f; }
 
 template <typename R>
-void launch_x_rows(dpse_plan* p, const R* in, typename CT<R>::T* out, int plane_a, int plane_b) {
-  const Geom& g = p->g;
+void add_x_rows(const Geom& g, FftJobs<R>& J, const R* in, typename CT<R>::T* out, int plane_a, int plane_b) {
   if (plane_b <= plane_a) return;
-  int64_t row0 = (int64_t)plane_a * g.Ny, nrows = (int64_t)(plane_b - plane_a) * g.Ny;
-  int rows_per = 2 * (kElems / g.Nx);
-  int nb = (int)((nrows + rows_per - 1) / rows_per);
-  hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3(nb), dim3(kThreads), 0, p->stream, g, in, out, row0, nrows, twx<R>(p));
+  const int rows = (plane_b - plane_a) * g.Ny, rows_per = 2 * (kElems / g.Nx);
+  J.in[J.n] = in;
+  J.out[J.n] = out;
+  J.lo[J.n] = plane_a * g.Ny;
+  J.cnt[J.n] = rows;
+  J.first[J.n + 1] = J.first[J.n] + (rows + rows_per - 1) / rows_per;
+  ++J.n;
 }
 
 template <typename R>
-void launch_y_planes(dpse_plan* p, typename CT<R>::T* data, int plane_a, int plane_b) {
-  const Geom& g = p->g;
+void add_y_planes(const Geom& g, FftJobs<R>& J, typename CT<R>::T* data, int plane_a, int plane_b) {
   if (plane_b <= plane_a) return;
-  int KB = kYElems<R> / g.Ny;
-  int nblk = (g.nkx + KB - 1) / KB;
-  hipLaunchKernelGGL(k_fft_y<R>, dim3(nblk * (plane_b - plane_a)), dim3(kThreads), 0, p->stream, g, data,
-                     plane_a, twy<R>(p));
+  const int KB = kYElems<R> / g.Ny, nblk = (g.nkx + KB - 1) / KB;
+  J.in[J.n] = nullptr;
+  J.out[J.n] = data;
+  J.lo[J.n] = plane_a;
+  J.cnt[J.n] = plane_b - plane_a;
+  J.first[J.n + 1] = J.first[J.n] + nblk * (plane_b - plane_a);
+  ++J.n;
+}
+
+template <typename R>
+FftJobs<R> no_jobs() {
+  FftJobs<R> J{};
+  J.first[0] = 0;
+  J.n = 0;
+  return J;
+}
+
+template <typename R>
+void launch_x(dpse_plan* p, const FftJobs<R>& J) {
+  if (J.n > 0)
+    hipLaunchKernelGGL(k_fft_x_r2c<R>, dim3(J.first[J.n]), dim3(kThreads), 0, p->stream, p->g, J, twx<R>(p));
+}
+
+template <typename R>
+void launch_y(dpse_plan* p, const FftJobs<R>& J) {
+  if (J.n > 0)
+    hipLaunchKernelGGL(k_fft_y<R>, dim3(J.first[J.n]), dim3(kThreads), 0, p->stream, p->g, J, twy<R>(p));
 }
 
 }  // namespace
@@ -298,17 +352,20 @@ template <typename R>
 hipError_t launch_fft_forward(dpse_plan* p) {
   using C = typename CT<R>::T;
   const Geom& g = p->g;
-  launch_x_rows<R>(p, (const R*)p->w.f_i, (C*)p->w.fx_i, 0, g.Nz);
-  launch_y_planes<R>(p, (C*)p->w.fx_i, 0, g.Nz);
+  FftJobs<R> X = no_jobs<R>(), Y = no_jobs<R>();
+  add_x_rows<R>(g, X, (const R*)p->w.f_i, (C*)p->w.fx_i, 0, g.Nz);
+  add_y_planes<R>(g, Y, (C*)p->w.fx_i, 0, g.Nz);
   if (g.top_end >= g.bot_begin) {
-    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.Nz);
-    launch_y_planes<R>(p, (C*)p->w.fx_o, 0, g.Nz);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.Nz);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, 0, g.Nz);
   } else {
-    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.top_end);
-    launch_x_rows<R>(p, (const R*)p->w.f_o, (C*)p->w.fx_o, g.bot_begin, g.Nz);
-    launch_y_planes<R>(p, (C*)p->w.fx_o, 0, g.top_end);
-    launch_y_planes<R>(p, (C*)p->w.fx_o, g.bot_begin, g.Nz);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.top_end);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, g.bot_begin, g.Nz);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, 0, g.top_end);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, g.bot_begin, g.Nz);
   }
+  launch_x<R>(p, X);
+  launch_y<R>(p, Y);
   return hipGetLastError();
 }
 
@@ -331,8 +388,11 @@ hipError_t launch_fft_inverse(dpse_plan* p) {
 // x,y transforms (FP64, the normalisation of the forward transform) of the
 // two staged wall densities, planes 0 (bottom) and 1 (top).
 hipError_t launch_wall_transforms(dpse_plan* p) {
-  launch_x_rows<double>(p, (const double*)p->walls.stage, (double2*)p->walls.hat, 0, 2);
-  launch_y_planes<double>(p, (double2*)p->walls.hat, 0, 2);
+  FftJobs<double> X = no_jobs<double>(), Y = no_jobs<double>();
+  add_x_rows<double>(p->g, X, (const double*)p->walls.stage, (double2*)p->walls.hat, 0, 2);
+  add_y_planes<double>(p->g, Y, (double2*)p->walls.hat, 0, 2);
+  launch_x<double>(p, X);
+  launch_y<double>(p, Y);
   return hipGetLastError();
 }
 
