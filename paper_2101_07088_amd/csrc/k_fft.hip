@@ -75,24 +75,26 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
   const int64_t r_base = row0 + (int64_t)(blockIdx.x - pick3(J.first, js)) * 2 * nseq;
   const int nr = (int)min((int64_t)2 * nseq, row0 + nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
-  // slot i of the buffer (nseq * Nx == kElems) takes x of rows 2s and 2s + 1;
-  // all global loads of the thread are issued before the LDS stores
+  // slot p of sequence s (nseq * Nx == kElems) takes x = bitrev(p) of rows
+  // 2s and 2s + 1: the bit reversal is a gather within the row's 128-byte
+  // lines and the LDS stores run in order (no bank conflicts); all global
+  // loads of the thread are issued before the LDS stores
   constexpr int kPer = kElems / kThreads;
   R v0[kPer], v1[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = i & (Nx - 1);
+    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = bitrev(i & (Nx - 1), logN);
     const int64_t r = r_base + 2 * s;
     v0[q] = 2 * s < nr ? in[r * Nx + x] : (R)0;
     v1[q] = 2 * s + 1 < nr ? in[(r + 1) * Nx + x] : (R)0;
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = i & (Nx - 1);
+    const int i = threadIdx.x + q * kThreads;
     C d;
     d.x = v0[q];
     d.y = v1[q];
-    buf[s * Nx + bitrev(x, logN)] = d;
+    buf[i] = d;
   }
   __syncthreads();
   fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(nseq), Nx, 1, tw, false, threadIdx.x);
@@ -234,13 +236,14 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   const double kxf = 2.0 * kPi / g.Lx;
-  // nrow_blk * Nx == kElems / 2 slots; all global loads of the thread are
-  // issued before the LDS stores
+  // nrow_blk * Nx == kElems / 2 slots; slot p of row rl takes k = bitrev(p)
+  // (a gather within the row's lines; LDS stores in order); all global loads
+  // of the thread are issued before the LDS stores
   constexpr int kPer = kElems / 2 / kThreads;
   C la[kPer], lb[kPer], lc[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = i & (Nx - 1);
+    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = bitrev(i & (Nx - 1), logN);
     la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
     if (rl < nr) {
       const int kk = k <= Nx / 2 ? k : Nx - k;
@@ -252,7 +255,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   }
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = i & (Nx - 1);
+    const int i = threadIdx.x + q * kThreads, rl = i >> logN, pos = i & (Nx - 1), k = bitrev(pos, logN);
     C z1, z2;
     z1.x = 0; z1.y = 0; z2.x = 0; z2.y = 0;
     if (rl < nr) {
@@ -272,7 +275,6 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
       z1.x = a.x - ex.y; z1.y = a.y + ex.x;
       z2.x = b.x - ez.y; z2.y = b.y + ez.x;
     }
-    int pos = bitrev(k, logN);
     buf[(2 * rl) * Nx + pos] = z1;
     buf[(2 * rl + 1) * Nx + pos] = z2;
   }
