@@ -210,14 +210,17 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
 
   for (int i = tid; i < M / 2; i += NT) tw[i] = twz[i];
   // 1. even extension of the node values in bit-reversed order, then FFT;
-  //    all global loads of the thread are issued before the LDS stores
+  //    slot p takes node j = bitrev(p) (each z row is a separate contiguous
+  //    piece of MB modes in global memory, so the reversal costs the loads
+  //    nothing, and the LDS stores run in order); all global loads of the
+  //    thread are issued before the stores
   {
     constexpr int kPer = KE / NT;  // M * MB == KE
     C va[kPer], vb[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int t = tid + q * NT;
-      const int j = t >> logMB, m = t & (MB - 1), mi = m0 + m;
+      const int j = bitrev(t >> logMB, logM), m = t & (MB - 1), mi = m0 + m;
       const int c = j < N ? j : M - j;
       va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
       if (mi < nmodes) {
@@ -229,10 +232,8 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int t = tid + q * NT;
-      const int j = t >> logMB, m = t & (MB - 1);
-      const int pos = bitrev(j, logM) * MB + m;
-      A[pos] = make_double2((double)vb[q].x, (double)vb[q].y);
-      B[pos] = make_double2((double)va[q].x, (double)va[q].y);
+      A[t] = make_double2((double)vb[q].x, (double)vb[q].y);
+      B[t] = make_double2((double)va[q].x, (double)va[q].y);
     }
   }
   __syncthreads();
