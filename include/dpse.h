@@ -197,9 +197,9 @@ int dpse_plan_set_walls(dpse_plan* plan, const double* sigma_b, const double* si
 
 /* Enqueues one solve (Sec. 5.2.2 steps 1-7 plus the near field). The near
  * field needs only its cell list: that list and the near field run on a
- * stream private to the plan, forked from the plan's stream after the
- * validation and joined back before the gauge constant, concurrently with the
- * grid binning and the far-field stages. */
+ * stream private to the plan, forked from the plan's stream once the forward
+ * transforms are queued and joined back before the gauge constant,
+ * concurrently with the column solve and the later far-field stages. */
 /* Arguments of dpse_solve:
  *   n      number of charges, 1 <= n <= max_n;
  *   pos    device, n x 3 row-major float64 (x, y, z); x, y are taken modulo Lx, Ly;

@@ -524,9 +524,10 @@ static const char* kStageNames[DPSE_NUM_STAGES] = {
 
 }  // extern "C"
 
-// One solve: validation and images, then the cell list and the near field on
-// the plan's side stream while the grid bins and the far-field stages run on
-// the plan's stream, joined before the gauge constant and the outputs.
+// One solve: validation and images, the grid bins, spreading and forward
+// transforms, then the cell list and the near field on the plan's side stream
+// while the column solve and the remaining far-field stages run on the plan's
+// stream, joined before the gauge constant and the outputs.
 template <typename R>
 static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,
                                double* phi, double* force, hipEvent_t* ev) {
@@ -544,10 +545,17 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   p->wall_part = nullptr;  // set by whichever kernel forms the wall term
   p->wall_nparts = 0;
   start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
-  // fork the near field (stage 7) and its part of the gauge; inside a graph
-  // capture they stay on the capturing stream (see dpse_solve_graph)
+  // The near field (stage 7) and its part of the gauge go to the side stream
+  // once the forward transforms are queued: they then share the CUs with the
+  // column solve, whose workgroups are bound by latency and LDS and leave
+  // issue slots and registers free, rather than with the bandwidth-bound
+  // spreading. Inside a graph capture they stay on the capturing stream (see
+  // dpse_solve_graph).
   const bool fork = !p->capturing;
   hipStream_t ns = fork ? p->side : main;
+  start(1, main); if (e == hipSuccess) e = dpse::launch_bin_grid(p, n); end(1, main);
+  start(2, main); run(dpse::launch_spread<R>); end(2, main);
+  start(3, main); run(dpse::launch_fft_forward<R>); end(3, main);
   if (fork && e == hipSuccess) e = hipEventRecord(p->fork_ev, main);
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
   p->stream = ns;
@@ -558,9 +566,6 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   end(7, ns);
   if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
   p->stream = main;
-  start(1, main); if (e == hipSuccess) e = dpse::launch_bin_grid(p, n); end(1, main);
-  start(2, main); run(dpse::launch_spread<R>); end(2, main);
-  start(3, main); run(dpse::launch_fft_forward<R>); end(3, main);
   start(4, main); run(dpse::launch_column<R>); end(4, main);
   start(5, main); run(dpse::launch_fft_inverse<R>); end(5, main);
   start(6, main); if (e == hipSuccess) e = dpse::launch_interp<R>(p, n); end(6, main);
