@@ -134,18 +134,18 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, const FftJobs<R> J,
   const int kb = (lb % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   C* base = data + (size_t)plane * Ny * nkx;
+  // slot p of column kl takes row ky = bitrev(p): every row piece is read
+  // on its own, so the reversal costs the loads nothing and the LDS stores
+  // run in order
   C v[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+    const int i = threadIdx.x + q * kThreads, ky = bitrev(i >> logKB, logN), kl = i & (KB - 1);
     v[q].x = 0; v[q].y = 0;
     if (kb + kl < nkx) v[q] = base[(size_t)ky * nkx + kb + kl];
   }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-    buf[bitrev(ky, logN) * KB + kl] = v[q];
-  }
+  for (int q = 0; q < kPer; ++q) buf[threadIdx.x + q * kThreads] = v[q];
   __syncthreads();
   fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf, logN, logKB, 1, KB, tw, false, threadIdx.x);
 #pragma unroll
@@ -156,8 +156,10 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, const FftJobs<R> J,
 }
 
 // Inverse C2C along y: (Psi, Psi_z) -> (P0 = Psi, PY = -i ky Psi, PZ = Psi_z),
-// y-transformed. Psi is read once into registers for the first two fields,
-// then Psi_z for the third; the fields take turns in one LDS buffer.
+// y-transformed. Psi and Psi_z are read once into registers. In FP32 the
+// transforms of Psi and -i ky Psi run in lockstep in two LDS buffers, then
+// Psi_z's; in FP64 (where the pair measured slower) the three take turns in
+// one buffer.
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R>::T* __restrict__ psi,
                                                      const typename CT<R>::T* __restrict__ psiz,
@@ -167,7 +169,9 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
   using C = typename CT<R>::T;
   constexpr int KE = kYElems<R>;
   constexpr int kPer = KE / kThreads;
-  __shared__ C buf[KE];
+  constexpr bool kPair = sizeof(R) == 4;
+  __shared__ C buf0[KE];
+  __shared__ C buf1[kPair ? KE : 1];
   __shared__ C tw[512];
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
   const int KB = KE / Ny, logKB = ilog2(KB);
@@ -177,12 +181,12 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
   const int kb = (blk % nblk) * KB;
   for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
   const size_t off = (size_t)plane * Ny * nkx;
-  // Psi and Psi_z both loaded up front: the Psi_z loads are in flight
-  // during the first two transforms
+  // slot p of column kl takes row ky = bitrev(p) (separate row pieces: the
+  // reversal costs the loads nothing, the LDS stores run in order)
   C a[kPer], c[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+    const int i = threadIdx.x + q * kThreads, ky = bitrev(i >> logKB, logN), kl = i & (KB - 1);
     a[q].x = 0; a[q].y = 0; c[q].x = 0; c[q].y = 0;
     if (kb + kl < nkx) {
       a[q] = psi[off + (size_t)ky * nkx + kb + kl];
@@ -190,35 +194,54 @@ __global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R
     }
   }
   const double kyf = 2.0 * kPi / g.Ly;
+  // -i ky Psi at slot i
+  auto dy = [&](int i, C v) -> C {
+    const int ky = bitrev(i >> logKB, logN);
+    const int ny = ky < Ny / 2 ? ky : ky - Ny;
+    const R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
+    C d;
+    d.x = kyv * v.y;
+    d.y = -kyv * v.x;
+    return d;
+  };
+  auto store = [&](C* dst, const C* src) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
+      if (kb + kl < nkx) dst[off + (size_t)ky * nkx + kb + kl] = src[i];
+    }
+  };
+  if constexpr (kPair) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      buf0[i] = a[q];
+      buf1[i] = dy(i, a[q]);
+    }
+    __syncthreads();
+    fft_lds_r22_pair<C, true, KE / 4 / kThreads, kThreads>(buf0, buf1, logN, logKB, 1, KB, tw, true, threadIdx.x);
+    store(p0, buf0);
+    store(py, buf1);
+  } else {
 #pragma nounroll
-  for (int f = 0; f < 3; ++f) {
-    if (f == 2) {
+    for (int f = 0; f < 2; ++f) {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) a[q] = c[q];
-    }
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-      C v = a[q];
-      if (f == 1) {  // -i ky Psi
-        const int ny = ky < Ny / 2 ? ky : ky - Ny;
-        const R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
-        const C t = v;
-        v.x = kyv * t.y;
-        v.y = -kyv * t.x;
+      for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kThreads;
+        buf0[i] = f == 0 ? a[q] : dy(i, a[q]);
       }
-      buf[bitrev(ky, logN) * KB + kl] = v;
+      __syncthreads();
+      fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf0, logN, logKB, 1, KB, tw, true, threadIdx.x);
+      store(f == 0 ? p0 : py, buf0);
+      __syncthreads();
     }
-    __syncthreads();
-    fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf, logN, logKB, 1, KB, tw, true, threadIdx.x);
-    C* dst = f == 0 ? p0 : (f == 1 ? py : pz);
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-      if (kb + kl < nkx) dst[off + (size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
-    }
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) buf0[threadIdx.x + q * kThreads] = c[q];
+  __syncthreads();
+  fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf0, logN, logKB, 1, KB, tw, true, threadIdx.x);
+  store(pz, buf0);
 }
 
 // Inverse C2R along x: rows of (P0, PY, PZ) -> u4[row][x] = (phi, Ex, Ey, Ez).
