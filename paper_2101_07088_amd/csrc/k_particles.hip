@@ -65,9 +65,13 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
                                                    int* n_img, double* scal, int* status) {
   __shared__ double sh[kThreads / 64];
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  double qq = 0.0;
+  const int lane = threadIdx.x & 63;
+  double qq = 0.0, x = 0.0, y = 0.0, z = 0.0;
+  // images and periodic copies this charge makes
+  bool img_b = false, img_t = false, cp_lo = false, cp_hi = false;
+  const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic with period H
   if (i < n) {
-    double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+    x = pos[3 * i]; y = pos[3 * i + 1]; z = pos[3 * i + 2];
     qq = q[i];
     int st = 0;
     bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qq);
@@ -75,7 +79,6 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     if (!fin) {
       x = 0.0; y = 0.0; z = 0.5 * g.H; qq = 0.0;
     }
-    const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic with period H
     if (tp) {
       z -= g.H * floor(z / g.H);
       if (!(z < g.H)) z = 0.0;
@@ -96,32 +99,42 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
       low = true;
       high = true;  // the wall without a jump has gamma = 0: no image
     }
-    if (low && g.gamma_b != 0.0) {
-      int s = atomicAdd(n_img, 1);
-      ext[n + s] = Part{x, y, -z, g.gamma_b * qq};
-      meta[n + s] = GRP_IMAGE | (int)(i << 2);
-    }
-    if (high && g.gamma_t != 0.0) {
-      int s = atomicAdd(n_img, 1);
-      ext[n + s] = Part{x, y, 2.0 * g.H - z, g.gamma_t * qq};
-      meta[n + s] = GRP_IMAGE | (int)(i << 2);
-    }
-    if (tp) {
-      // periodic z windows: a copy of a charge within H_E of an end of the
-      // period, shifted by one period, spreads to the nodes across that end
-      // and gathers its field for the same output index (group of a charge)
-      if (z < g.H_E) {
-        int s = atomicAdd(n_img, 1);
-        ext[n + s] = Part{x, y, z + g.H, qq};
-        meta[n + s] = GRP_INNER | (int)(i << 2);
-      }
-      if (z >= g.H - g.H_E) {
-        int s = atomicAdd(n_img, 1);
-        ext[n + s] = Part{x, y, z - g.H, qq};
-        meta[n + s] = GRP_INNER | (int)(i << 2);
-      }
-    }
+    img_b = low && g.gamma_b != 0.0;
+    img_t = high && g.gamma_t != 0.0;
+    // periodic z windows: a copy of a charge within H_E of an end of the
+    // period, shifted by one period, spreads to the nodes across that end and
+    // gathers its field for the same output index (group of a charge)
+    cp_lo = tp && z < g.H_E;
+    cp_hi = tp && z >= g.H - g.H_E;
     if (st) atomicOr(status, st);
+  }
+  // slots of the extra entries: one atomic per wave and kind on the shared
+  // counter, the lanes in order after it
+  auto claim = [&](bool want) -> int {
+    const unsigned long long m = __ballot(want);
+    if (m == 0) return 0;
+    const int lead = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == lead) base = atomicAdd(n_img, __popcll(m));
+    base = __shfl(base, lead, 64);
+    return base + __popcll(m & ((1ull << lane) - 1));
+  };
+  const int sb = claim(img_b), stt = claim(img_t), sl = claim(cp_lo), sh_ = claim(cp_hi);
+  if (img_b) {
+    ext[n + sb] = Part{x, y, -z, g.gamma_b * qq};
+    meta[n + sb] = GRP_IMAGE | (int)(i << 2);
+  }
+  if (img_t) {
+    ext[n + stt] = Part{x, y, 2.0 * g.H - z, g.gamma_t * qq};
+    meta[n + stt] = GRP_IMAGE | (int)(i << 2);
+  }
+  if (cp_lo) {
+    ext[n + sl] = Part{x, y, z + g.H, qq};
+    meta[n + sl] = GRP_INNER | (int)(i << 2);
+  }
+  if (cp_hi) {
+    ext[n + sh_] = Part{x, y, z - g.H, qq};
+    meta[n + sh_] = GRP_INNER | (int)(i << 2);
   }
   double s1 = block_sum(qq, sh);
   double s2 = block_sum(fabs(qq), sh);
