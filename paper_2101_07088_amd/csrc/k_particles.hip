@@ -144,18 +144,31 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
   }
 }
 
-// Neutrality of the charges and the wall charges together (eq. elecneu);
-// ws = the wall scalars (int sigma, int |sigma|), or null without walls.
-__global__ void k_check_neutral(const double* scal, const double* ws, int* status) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+// What a solve accumulates into, cleared in one launch before the prep
+// kernel: the image counter, the charge sums (sum q, sum |q|; the gauge
+// constant scal[2] of the last full solve stays, for dpse_solve_near) and the
+// bin counters of the grid stages and of the near-field cell list.
+__global__ void __launch_bounds__(kThreads) k_reset(int* n_img, double* scal, int* bin_cnt, int nbin,
+                                                    int* cell_cnt, int ncell) {
+  const int t = blockIdx.x * kThreads + threadIdx.x, stride = gridDim.x * kThreads;
+  if (t == 0) *n_img = 0;
+  if (t < 2) scal[t] = 0.0;
+  for (int i = t; i < nbin; i += stride) bin_cnt[i] = 0;
+  for (int i = t; i < ncell; i += stride) cell_cnt[i] = 0;
+}
+
+// Bin counts of charges and images; the first thread also checks the
+// neutrality of the charges and the wall charges together (eq. elecneu) from
+// the sums of the prep kernel (ws = the wall scalars (int sigma, int |sigma|),
+// or null without walls).
+__global__ void __launch_bounds__(kThreads) k_count_ext(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                        const int* __restrict__ n_img, int* cnt,
+                                                        const double* scal, const double* ws, int* status) {
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (i == 0) {
     const double net = scal[0] + (ws ? ws[0] : 0.0), tot = scal[1] + (ws ? ws[1] : 0.0);
     if (!(fabs(net) <= 1e-12 * tot)) atomicOr(status, 4);
   }
-}
-
-__global__ void __launch_bounds__(kThreads) k_count_ext(Geom g, int64_t n, const Part* __restrict__ ext,
-                                                        const int* __restrict__ n_img, int* cnt) {
-  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i >= n + *n_img) return;
   Part p = ext[i];
   atomicAdd(&cnt[spread_key(g, p.x, p.y, p.z)], 1);
@@ -471,41 +484,35 @@ hipError_t fill_double(double* ptr, double value, int64_t count, hipStream_t s) 
 hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double* q) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
-  // only the accumulated sums (sum q, sum |q|) start from zero: the gauge
-  // constant scal[2] of the last full solve serves dpse_solve_near
-  hipError_t e = fill_int(w.n_img, 0, 1, s);
-  if (e == hipSuccess) e = fill_double(w.scal, 0.0, 2, s);
-  if (e != hipSuccess) return e;
+  const int nbin = (int)p->nkeys + 1, ncell = (int)p->ncells + 1;
+  hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max(nbin, ncell), 64)), dim3(kThreads), 0, s, w.n_img, w.scal,
+                     w.bin_cnt, nbin, w.cell_cnt, ncell);
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
                      w.n_img, w.scal, w.status);
-  hipLaunchKernelGGL(k_check_neutral, dim3(1), dim3(64), 0, s, (const double*)w.scal,
-                     p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
   return hipGetLastError();
 }
 
 // Bins of the grid stages: counting sort of charges and images by (x,y tile
-// bin, z bucket).
+// bin, z bucket); the counters were cleared by launch_prep.
 hipError_t launch_bin_grid(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
-  hipError_t e = fill_int(w.bin_cnt, 0, p->nkeys + 1, s);
-  if (e != hipSuccess) return e;
   int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
-                     (const int*)w.n_img, w.bin_cnt);
+                     (const int*)w.n_img, w.bin_cnt, (const double*)w.scal,
+                     p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
   hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta);
   return hipGetLastError();
 }
 
-// Cell list of the near field: counting sort of the charges by cell.
+// Cell list of the near field: counting sort of the charges by cell; the
+// counters were cleared by launch_prep.
 hipError_t launch_bin_cells(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
-  hipError_t e = fill_int(w.cell_cnt, 0, p->ncells + 1, s);
-  if (e != hipSuccess) return e;
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_count_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext, w.cell_cnt);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.cell_cnt, w.cell_off, w.cell_cur,
