@@ -185,9 +185,8 @@ template <typename R> hipError_t launch_interp(dpse_plan* p, int64_t n);
 template <typename R> hipError_t launch_near(dpse_plan* p, int64_t n);
 template <typename R> hipError_t launch_gauge_far(dpse_plan* p);
 hipError_t launch_near_origin(dpse_plan* p, int64_t n);
-hipError_t launch_gauge_final(dpse_plan* p, int64_t n);
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy,
-                           double* phi, double* force);
+                           double* phi, double* force, bool gauge);
 hipError_t launch_bd_step(dpse_plan* p, int64_t n, const double* pos, const double* force, const double* w_prev,
                           const double* w_next, double mu_dt, double noise, double* pos_out, int* escaped);
 

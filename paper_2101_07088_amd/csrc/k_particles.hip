@@ -375,34 +375,45 @@ __global__ void __launch_bounds__(kThreads) k_near_origin(Geom g, int64_t n, con
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
-// One wave: the near part at the origin from nb block partials, the far part
-// from the per-node partials far_part[0 .. Nz), then the gauge constant.
-__global__ void k_gauge_final(Geom g, int nb, const double* partials, const double* far_part, double* scal) {
-  const int lane = threadIdx.x;
-  double sn = 0.0, sf = 0.0;
-  for (int i = lane; i < nb; i += 64) sn += partials[i];
-  for (int i = lane; i < g.Nz; i += 64) sf += far_part[i];
-  for (int o = 32; o > 0; o >>= 1) {
-    sn += __shfl_down(sn, o, 64);
-    sf += __shfl_down(sf, o, 64);
-  }
-  if (lane == 0) {
-    const double near0 = sn / (4.0 * kPi * g.eps);
-    scal[4] = sf;
-    scal[5] = near0;
-    scal[2] = (g.flags & DPSE_GAUGE_NONE) ? 0.0 : -(sf + near0);
-  }
-}
-
 // phibar = far + near + B_i - q * 2 xi_e / (4 pi eps sqrt(pi)); F = q (E_far + E_near).
+// With gnear non-null the gauge constant B_i is formed here first: the first
+// wave of every block sums the near part at the origin from gnb block
+// partials and the far part from the per-node partials gfar[0 .. Nz), in a
+// fixed order (every block gets the same bits), and block 0 stores it with
+// its parts in scal[2], scal[4], scal[5]; otherwise B_i is scal[2] as it
+// stands (the near-field-only solve keeps that of the last full solve).
 __global__ void __launch_bounds__(kThreads) k_finalize(Geom g, int64_t n, const double* __restrict__ q,
                                                        const double4* __restrict__ far4,
-                                                       const double4* __restrict__ near4,
-                                                       const double* __restrict__ scal, double* phi,
-                                                       double* force, double* partials) {
+                                                       const double4* __restrict__ near4, double* scal,
+                                                       double* phi, double* force, double* partials,
+                                                       const double* gnear, int gnb, const double* gfar) {
   __shared__ double sh[kThreads / 64];
+  __shared__ double bsh;
   const double selfc = 2.0 * g.xi_e / (4.0 * kPi * g.eps * sqrt(kPi));
-  const double Bi = scal[2];
+  if (gnear) {
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      double sn = 0.0, sf = 0.0;
+      for (int i = lane; i < gnb; i += 64) sn += gnear[i];
+      for (int i = lane; i < g.Nz; i += 64) sf += gfar[i];
+      for (int o = 32; o > 0; o >>= 1) {
+        sn += __shfl_down(sn, o, 64);
+        sf += __shfl_down(sf, o, 64);
+      }
+      if (lane == 0) {
+        const double near0 = sn / (4.0 * kPi * g.eps);
+        const double b = (g.flags & DPSE_GAUGE_NONE) ? 0.0 : -(sf + near0);
+        bsh = b;
+        if (blockIdx.x == 0) {
+          scal[4] = sf;
+          scal[5] = near0;
+          scal[2] = b;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const double Bi = gnear ? bsh : scal[2];
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kThreads) {
@@ -559,19 +570,15 @@ hipError_t launch_near_origin(dpse_plan* p, int64_t n) {
 }
 
 // Gauge constant from the near partials and the far per-node partials.
-hipError_t launch_gauge_final(dpse_plan* p, int64_t n) {
-  int nb = blocks_for(n, p->npartials);
-  hipLaunchKernelGGL(k_gauge_final, dim3(1), dim3(64), 0, p->stream, p->g, nb, (const double*)p->w.partials,
-                     (const double*)(p->w.partials + 2 * p->npartials), p->w.scal);
-  return hipGetLastError();
-}
-
 hipError_t launch_finalize(dpse_plan* p, int64_t n, const double* q, double* energy, double* phi,
-                           double* force) {
+                           double* force, bool gauge) {
   int nb = blocks_for(n, p->npartials);
+  // the near-origin partials (nb of them, partials[0 ..)) and the far per-node
+  // partials (partials[2 npartials ..)) of the gauge constant
   hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(kThreads), 0, p->stream, p->g, n, q,
-                     (const double4*)p->w.far4, (const double4*)p->w.near4, (const double*)p->w.scal, phi,
-                     force, p->w.partials + p->npartials);
+                     (const double4*)p->w.far4, (const double4*)p->w.near4, p->w.scal, phi, force,
+                     p->w.partials + p->npartials, gauge ? (const double*)p->w.partials : nullptr, nb,
+                     (const double*)(p->w.partials + 2 * p->npartials));
   // the partials of the wall term, from the interpolation or the per-charge kernel
   const bool wall = p->walls_on && energy && p->wall_part;
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, p->stream, nb,

@@ -572,11 +572,10 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   start(8, main);
   run(dpse::launch_gauge_far<R>);
   if (fork && e == hipSuccess) e = hipStreamWaitEvent(main, p->join_ev, 0);
-  if (e == hipSuccess) e = dpse::launch_gauge_final(p, n);
   end(8, main);
   start(9, main);
   if (p->walls_on && energy && !p->wall_part && e == hipSuccess) e = dpse::launch_wall_energy<R>(p, n);
-  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force);
+  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force, true);  // forms the gauge constant first
   end(9, main);
   return e;
 }
@@ -589,7 +588,7 @@ static hipError_t solve_near_stages(dpse_plan* p, int64_t n, const double* pos, 
   hipError_t e = dpse::launch_prep(p, n, pos, q);
   if (e == hipSuccess) e = dpse::launch_bin(p, n);
   if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
-  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force);
+  if (e == hipSuccess) e = dpse::launch_finalize(p, n, q, energy, phi, force, false);
   return e;
 }
 
