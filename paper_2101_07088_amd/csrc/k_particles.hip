@@ -239,7 +239,9 @@ __device__ inline void near_pair(const Geom& g, double dx, double dy, double dz,
                                  R& ph, R& ex, R& ey, R& ez) {
   double r2 = dx * dx + dy * dy + dz * dz;
   if (!(r2 < g.r_cut * g.r_cut)) return;
-  R r = (R)sqrt(r2);
+  R r;
+  if constexpr (sizeof(R) == 4) r = sqrtf((float)r2);  // the FP32 path takes no FP64 square root
+  else r = sqrt(r2);
   R G, e;
   if (g.g_w > 0.0) {
     R a1 = (R)(1.0 / (2.0 * g.g_w)), b1 = (R)g.xi_e;
