@@ -62,7 +62,8 @@ __device__ inline int cell_of(const Geom& g, double x, double y, double z) {
 // Validation, periodic wrap, groups C_o / C_>, images of C_o charges.
 __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const double* __restrict__ pos,
                                                    const double* __restrict__ q, Part* ext, int* meta,
-                                                   int* n_img, double* scal, int* status) {
+                                                   int* n_img, double* scal, int* status, int* bin_cnt,
+                                                   int* cell_cnt) {
   __shared__ double sh[kThreads / 64];
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   const int lane = threadIdx.x & 63;
@@ -95,6 +96,9 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     bool low = !fast && z < 2.0 * g.H_E, high = !fast && z > g.H - 2.0 * g.H_E;
     ext[i] = Part{x, y, z, qq};
     meta[i] = ((low || high) ? GRP_WALL : GRP_INNER) | (int)(i << 2);
+    // counts of the two counting sorts (spreading bins, near-field cells)
+    atomicAdd(&bin_cnt[spread_key(g, x, y, z)], 1);
+    atomicAdd(&cell_cnt[cell_of(g, x, y, z)], 1);
     if (g.flags & DPSE_ONE_JUMP) {  // one jump: every charge imaged across that wall
       low = true;
       high = true;  // the wall without a jump has gamma = 0: no image
@@ -123,18 +127,22 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
   if (img_b) {
     ext[n + sb] = Part{x, y, -z, g.gamma_b * qq};
     meta[n + sb] = GRP_IMAGE | (int)(i << 2);
+    atomicAdd(&bin_cnt[spread_key(g, x, y, -z)], 1);
   }
   if (img_t) {
     ext[n + stt] = Part{x, y, 2.0 * g.H - z, g.gamma_t * qq};
     meta[n + stt] = GRP_IMAGE | (int)(i << 2);
+    atomicAdd(&bin_cnt[spread_key(g, x, y, 2.0 * g.H - z)], 1);
   }
   if (cp_lo) {
     ext[n + sl] = Part{x, y, z + g.H, qq};
     meta[n + sl] = GRP_INNER | (int)(i << 2);
+    atomicAdd(&bin_cnt[spread_key(g, x, y, z + g.H)], 1);
   }
   if (cp_hi) {
     ext[n + sh_] = Part{x, y, z - g.H, qq};
     meta[n + sh_] = GRP_INNER | (int)(i << 2);
+    atomicAdd(&bin_cnt[spread_key(g, x, y, z - g.H)], 1);
   }
   double s1 = block_sum(qq, sh);
   double s2 = block_sum(fabs(qq), sh);
@@ -157,13 +165,15 @@ __global__ void __launch_bounds__(kThreads) k_reset(int* n_img, double* scal, in
   for (int i = t; i < ncell; i += stride) cell_cnt[i] = 0;
 }
 
-// Bin counts of charges and images; the first thread also checks the
-// neutrality of the charges and the wall charges together (eq. elecneu) from
-// the sums of the prep kernel (ws = the wall scalars (int sigma, int |sigma|),
-// or null without walls).
-__global__ void __launch_bounds__(kThreads) k_count_ext(Geom g, int64_t n, const Part* __restrict__ ext,
-                                                        const int* __restrict__ n_img, int* cnt,
-                                                        const double* scal, const double* ws, int* status) {
+// Scatter of charges and images into the spreading bins (counted by the prep
+// kernel); the first thread also checks the neutrality of the charges and the
+// wall charges together (eq. elecneu) from the sums of the prep kernel (ws =
+// the wall scalars (int sigma, int |sigma|), or null without walls).
+__global__ void __launch_bounds__(kThreads) k_scatter_ext(Geom g, int64_t n, const Part* __restrict__ ext,
+                                                          const int* __restrict__ meta,
+                                                          const int* __restrict__ n_img, int* cur,
+                                                          Part* srt, int* srt_meta, const double* scal,
+                                                          const double* ws, int* status) {
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (i == 0) {
     const double net = scal[0] + (ws ? ws[0] : 0.0), tot = scal[1] + (ws ? ws[1] : 0.0);
@@ -171,27 +181,9 @@ __global__ void __launch_bounds__(kThreads) k_count_ext(Geom g, int64_t n, const
   }
   if (i >= n + *n_img) return;
   Part p = ext[i];
-  atomicAdd(&cnt[spread_key(g, p.x, p.y, p.z)], 1);
-}
-
-__global__ void __launch_bounds__(kThreads) k_scatter_ext(Geom g, int64_t n, const Part* __restrict__ ext,
-                                                          const int* __restrict__ meta,
-                                                          const int* __restrict__ n_img, int* cur,
-                                                          Part* srt, int* srt_meta) {
-  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i >= n + *n_img) return;
-  Part p = ext[i];
   int s = atomicAdd(&cur[spread_key(g, p.x, p.y, p.z)], 1);
   srt[s] = p;
   srt_meta[s] = meta[i];
-}
-
-__global__ void __launch_bounds__(kThreads) k_count_cells(Geom g, int64_t n, const Part* __restrict__ ext,
-                                                          int* cnt) {
-  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i >= n) return;
-  Part p = ext[i];
-  atomicAdd(&cnt[cell_of(g, p.x, p.y, p.z)], 1);
 }
 
 __global__ void __launch_bounds__(kThreads) k_scatter_cells(Geom g, int64_t n, const Part* __restrict__ ext,
@@ -502,32 +494,29 @@ hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double*
                      w.bin_cnt, nbin, w.cell_cnt, ncell);
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
-                     w.n_img, w.scal, w.status);
+                     w.n_img, w.scal, w.status, w.bin_cnt, w.cell_cnt);
   return hipGetLastError();
 }
 
 // Bins of the grid stages: counting sort of charges and images by (x,y tile
-// bin, z bucket); the counters were cleared by launch_prep.
+// bin, z bucket); launch_prep cleared and filled the counts.
 hipError_t launch_bin_grid(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_count_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
-                     (const int*)w.n_img, w.bin_cnt, (const double*)w.scal,
-                     p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
   hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
-                     (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta);
+                     (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta,
+                     (const double*)w.scal, p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
   return hipGetLastError();
 }
 
-// Cell list of the near field: counting sort of the charges by cell; the
-// counters were cleared by launch_prep.
+// Cell list of the near field: counting sort of the charges by cell;
+// launch_prep cleared and filled the counts.
 hipError_t launch_bin_cells(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   int nb = (int)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_count_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext, w.cell_cnt);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.cell_cnt, w.cell_off, w.cell_cur,
                      p->ncells);
   hipLaunchKernelGGL(k_scatter_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
