@@ -471,8 +471,8 @@ def main(argv=None):
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (see DESIGN.md, "
-              "'How the path would shard'); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the sharding "
+              "is a design, not code); run with --gpus 1", file=sys.stderr)
         return 2
     import torch
     import paper_2101_07088_amd as dp

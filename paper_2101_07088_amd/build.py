@@ -27,7 +27,8 @@ CFLAGS = [
     "-std=c++17",
     "-fPIC",
     "-munsafe-fp-atomics",
-    # packed FP32 instructions stay off ("Build")
+    # no packed FP32 instructions (v_pk_add/mul/fma_f32) are generated: a
+    # deliberate restriction, FP32 code runs as scalar VALU instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE,
     "-I", CSRC,
