@@ -18,6 +18,7 @@ DPSE_KMAX_GT = 2
 DPSE_UNIFORM_FAST = 4
 DPSE_ONE_JUMP = 8
 DPSE_TRIPLY = 16
+DPSE_DETERMINISTIC = 32
 
 _STATUS = {
     0: "DPSE_OK", 1: "DPSE_EINVAL", 2: "DPSE_ENOMEM", 3: "DPSE_EHIP", 4: "DPSE_ENONNEUTRAL",
@@ -38,6 +39,7 @@ class Stage(enum.IntEnum):
     WALL_HAT = 9
     WALL_PHI = 10
     WALL_SCALARS = 11
+    FH_O = 12
 
 
 class DpseError(RuntimeError):
@@ -140,6 +142,8 @@ def _params(p, precision: int = DPSE_FP64, delta: float = 0.0) -> _Params:
         flags |= DPSE_ONE_JUMP
     if getattr(p, "triply", False):
         flags |= DPSE_TRIPLY
+    if getattr(p, "deterministic", False):
+        flags |= DPSE_DETERMINISTIC
     return _Params(Lx=p.Lx, Ly=p.Ly, H=p.H, eps=p.eps, eps_bottom=p.eps_b, eps_top=p.eps_t, xi=p.xi,
                    g_w=getattr(p, "g_w", 0.0), Nx=p.Nx, Ny=p.Ny, Nz=p.Nz, support=getattr(p, "n_g", 0),
                    r_cut=p.r_cut, delta=delta, precision=precision, flags=flags)
@@ -165,6 +169,51 @@ def workspace_size(params, max_n: int, precision: int = DPSE_FP64) -> int:
     return b.value
 
 
+def check_charges(torch, pos, q, device=None):
+    """Validates the inputs of a solve before any pointer reaches the library:
+    pos float64 [n, 3] and q float64 [n], contiguous HIP tensors on one device
+    (the plan's, when given). Raises ValueError (TypeError for a wrong type);
+    returns n."""
+    for name, t in (("pos", pos), ("q", q)):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name} must be float64, got {t.dtype}")
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be a HIP device tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+    if q.dim() != 1 or q.shape[0] < 1:
+        raise ValueError(f"q must have shape (n,) with n >= 1, got {tuple(q.shape)}")
+    n = int(q.shape[0])
+    if tuple(pos.shape) != (n, 3):
+        raise ValueError(f"pos must have shape ({n}, 3), got {tuple(pos.shape)}")
+    if pos.device != q.device:
+        raise ValueError("pos and q are on different devices")
+    if device is not None and pos.device.index != device:
+        raise ValueError(f"inputs are on cuda:{pos.device.index}, the plan on cuda:{device}")
+    return n
+
+
+def check_outputs(torch, n, device, energy, phi, force):
+    """Validates caller-given outputs (None entries are skipped): energy
+    float64 with at least one element, phi float64 [n], force float64 [n, 3],
+    contiguous, on `device`."""
+    for name, t, shape in (("energy", energy, None), ("phi", phi, (n,)), ("force", force, (n, 3))):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 HIP tensor")
+        if t.device.index != device:
+            raise ValueError(f"{name} is on cuda:{t.device.index}, the plan on cuda:{device}")
+        if shape is None and t.numel() < 1:
+            raise ValueError("energy needs one element")
+        if shape is not None and tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}, got {tuple(t.shape)}")
+
+
 class Plan:
     """A plan for one slab system on the current HIP device and stream.
 
@@ -182,6 +231,7 @@ class Plan:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self.workspace = None
+        self.device = torch.cuda.current_device()
         prm = _params(params, precision)
         h = ctypes.c_void_p()
         if own_workspace:
@@ -199,14 +249,10 @@ class Plan:
     def handle(self) -> ctypes.c_void_p:
         return self._h
 
-    def solve(self, pos, q, energy=None, phi=None, force=None):
-        """Enqueues a solve. pos: float64 [n,3], q: float64 [n] HIP tensors.
-        Returns (energy[1], phi[n], force[n,3]) device tensors (allocated if
-        not given)."""
+    def _io(self, pos, q, energy, phi, force):
         torch = self._torch
-        n = int(q.shape[0])
-        assert pos.dtype == torch.float64 and q.dtype == torch.float64 and pos.is_cuda and q.is_cuda
-        assert pos.is_contiguous() and q.is_contiguous() and tuple(pos.shape) == (n, 3)
+        n = check_charges(torch, pos, q, self.device)
+        check_outputs(torch, n, self.device, energy, phi, force)
         dev = pos.device
         if energy is None:
             energy = torch.empty(1, dtype=torch.float64, device=dev)
@@ -214,6 +260,13 @@ class Plan:
             phi = torch.empty(n, dtype=torch.float64, device=dev)
         if force is None:
             force = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        return n, energy, phi, force
+
+    def solve(self, pos, q, energy=None, phi=None, force=None):
+        """Enqueues a solve. pos: float64 [n,3], q: float64 [n] HIP tensors.
+        Returns (energy[1], phi[n], force[n,3]) device tensors (allocated if
+        not given)."""
+        n, energy, phi, force = self._io(pos, q, energy, phi, force)
         _check(_lib().dpse_solve(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
                                  force.data_ptr()), "dpse_solve")
         return energy, phi, force
@@ -221,16 +274,7 @@ class Plan:
     def solve_near(self, pos, q, energy=None, phi=None, force=None):
         """dpse_solve_near: the near field at pos with the far field and gauge
         constant of the plan's last full solve of these charges held fixed."""
-        torch = self._torch
-        n = int(q.shape[0])
-        assert pos.dtype == torch.float64 and pos.is_contiguous() and tuple(pos.shape) == (n, 3)
-        dev = pos.device
-        if energy is None:
-            energy = torch.empty(1, dtype=torch.float64, device=dev)
-        if phi is None:
-            phi = torch.empty(n, dtype=torch.float64, device=dev)
-        if force is None:
-            force = torch.empty((n, 3), dtype=torch.float64, device=dev)
+        n, energy, phi, force = self._io(pos, q, energy, phi, force)
         _check(_lib().dpse_solve_near(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(), phi.data_ptr(),
                                       force.data_ptr()), "dpse_solve_near")
         return energy, phi, force
@@ -239,9 +283,15 @@ class Plan:
         """dpse_bd_step: pos_out = pos + mu_dt force + noise (w_prev + w_next);
         escaped (int32 device tensor [1]) counts charges leaving the slab."""
         torch = self._torch
-        for t in (pos, force, w_prev, w_next, pos_out):
-            assert t.dtype == torch.float64 and t.is_cuda and t.is_contiguous() and t.shape == pos.shape
-        assert escaped.dtype == torch.int32 and escaped.is_cuda
+        for name, t in (("pos", pos), ("force", force), ("w_prev", w_prev), ("w_next", w_next),
+                        ("pos_out", pos_out)):
+            if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda and t.is_contiguous()
+                    and t.dim() == 2 and t.shape[1] == 3 and t.shape == pos.shape
+                    and t.device.index == self.device):
+                raise ValueError(f"{name} must be a contiguous float64 [n, 3] tensor on cuda:{self.device}")
+        if not (isinstance(escaped, torch.Tensor) and escaped.dtype == torch.int32 and escaped.is_cuda
+                and escaped.numel() >= 1 and escaped.device.index == self.device):
+            raise ValueError(f"escaped must be an int32 tensor on cuda:{self.device}")
         _check(_lib().dpse_bd_step(self._h, int(pos.shape[0]), pos.data_ptr(), force.data_ptr(), w_prev.data_ptr(),
                                    w_next.data_ptr(), float(mu_dt), float(noise), pos_out.data_ptr(),
                                    escaped.data_ptr()), "dpse_bd_step")
@@ -259,7 +309,11 @@ class Plan:
     def solve_graph(self, pos, q, energy, phi, force):
         """dpse_solve_graph: the solve as one graph launch (re-captured when
         the sizes, buffers or stream change). Outputs must be given."""
-        n = int(q.shape[0])
+        torch = self._torch
+        n = check_charges(torch, pos, q, self.device)
+        if energy is None or phi is None or force is None:
+            raise ValueError("solve_graph needs all three outputs (the graph records their addresses)")
+        check_outputs(torch, n, self.device, energy, phi, force)
         _check(_lib().dpse_solve_graph(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(),
                                        phi.data_ptr(), force.data_ptr()), "dpse_solve_graph")
         return energy, phi, force
@@ -268,6 +322,7 @@ class Plan:
         """dpse_plan_autotune: times the launch-shape candidates of spreading,
         interpolation and the column kernel on these charges and keeps the
         fastest. Returns (choice[3], {(stage, index): ms})."""
+        check_charges(self._torch, pos, q, self.device)
         ch = (ctypes.c_int32 * 3)()
         ms = (ctypes.c_double * (3 * 16))()
         _check(_lib().dpse_plan_autotune(self._h, int(q.shape[0]), pos.data_ptr(), q.data_ptr(), int(reps), ch, ms),
@@ -309,7 +364,7 @@ class Plan:
         p = self.params
         nkx = p.Nx // 2 + 1
         G = p.Nz * p.Ny * p.Nx
-        sizes = {Stage.F_I: G, Stage.F_O: G, Stage.FH_I: 2 * p.Nz * p.Ny * nkx, Stage.PSI: 2 * p.Nz * p.Ny * nkx,
+        sizes = {Stage.F_I: G, Stage.F_O: G, Stage.FH_I: 2 * p.Nz * p.Ny * nkx, Stage.FH_O: 2 * p.Nz * p.Ny * nkx, Stage.PSI: 2 * p.Nz * p.Ny * nkx,
                  Stage.PSIZ: 2 * p.Nz * p.Ny * nkx, Stage.GRIDS: 4 * G, Stage.FAR: 4 * self.max_n,
                  Stage.NEAR: 4 * self.max_n, Stage.SCALARS: 8, Stage.WALL_HAT: 4 * p.Ny * nkx,
                  Stage.WALL_PHI: G, Stage.WALL_SCALARS: 4}
@@ -325,7 +380,7 @@ class Plan:
         if stage == Stage.WALL_HAT:
             c = a.reshape(2, p.Ny, nkx, 2)
             return c[..., 0] + 1j * c[..., 1]
-        if stage in (Stage.FH_I, Stage.PSI, Stage.PSIZ):
+        if stage in (Stage.FH_I, Stage.FH_O, Stage.PSI, Stage.PSIZ):
             c = a.reshape(p.Nz, p.Ny, nkx, 2)
             return c[..., 0] + 1j * c[..., 1]
         if stage == Stage.GRIDS:
@@ -364,6 +419,10 @@ def solve_batch(plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Optio
     allocated when not given. Returns lists (energy, phi, force)."""
     import torch
     k = len(plans)
+    if not (len(pos) == len(q) == k) or k < 1:
+        raise ValueError("one position and one charge tensor per plan")
+    for i in range(k):
+        check_charges(torch, pos[i], q[i], plans[i].device)
     if energy is None:
         energy = [torch.empty(1, dtype=torch.float64, device=p_.device) for p_ in pos]
     if phi is None:
@@ -373,6 +432,8 @@ def solve_batch(plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Optio
     VP = ctypes.c_void_p * k
     hs = VP(*[p_.handle.value for p_ in plans])
     ns = (ctypes.c_int64 * k)(*[int(q_.shape[0]) for q_ in q])
+    for i in range(k):
+        check_outputs(torch, int(q[i].shape[0]), plans[i].device, energy[i], phi[i], force[i])
     ptr = lambda ts: VP(*[t.data_ptr() for t in ts])
     _check(_lib().dpse_solve_batch(k, hs, ns, ptr(pos), ptr(q), ptr(energy), ptr(phi), ptr(force)),
            "dpse_solve_batch")
@@ -386,7 +447,13 @@ class BatchGraph:
 
     def __init__(self, plans: Sequence[Plan], pos: Sequence, q: Sequence, energy: Sequence, phi: Sequence,
                  force: Sequence, branch: Optional[Sequence[int]] = None, n_branches: int = 1):
+        import torch
         k = len(plans)
+        if not (len(pos) == len(q) == len(energy) == len(phi) == len(force) == k) or k < 1:
+            raise ValueError("one tensor of each kind per plan")
+        for i in range(k):
+            n = check_charges(torch, pos[i], q[i], plans[i].device)
+            check_outputs(torch, n, plans[i].device, energy[i], phi[i], force[i])
         VP = ctypes.c_void_p * k
         hs = VP(*[p_.handle.value for p_ in plans])
         ns = (ctypes.c_int64 * k)(*[int(q_.shape[0]) for q_ in q])
