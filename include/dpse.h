@@ -89,13 +89,23 @@ enum {
                            [-H - H_E, H + H_E] (bottom) or [-H_E, 2H + H_E] (top); no wall
                            group or correction. Shorter than the general domain when
                            H < 4 H_E; no wall charges */
-  DPSE_TRIPLY = 16      /* triply periodic variant (Sec. 7 and its performance comparison): the box
+  DPSE_TRIPLY = 16,     /* triply periodic variant (Sec. 7 and its performance comparison): the box
                            is periodic in z too, with period H (the permittivities must be equal,
                            and the walls play no part); a uniform z grid of Nz nodes (a power of two
                            in [32, 1024]), the far field solved by Fourier transforms in all three
                            directions (psi^ = f^ / (eps |k|^2), psi^(0) = 0), the near field over
                            minimal images in x, y and z; no gauge constant (the k = 0 mode is zero);
                            needs H >= 4 H_E and r_cut < H / 2; not with the other solver flags */
+  DPSE_DETERMINISTIC = 32 /* bitwise-reproducible solves: the same inputs give the same output bits
+                           on every run, alone or beside other work on the device. No floating-point
+                           atomics: the spreading and near-field cell lists are put in a fixed order
+                           inside every bin and cell after the counting sorts, spreading runs in its
+                           gather form with one block per tile, and interpolation with one wavefront
+                           per charge (a fixed-order sum and a plain store); every other reduction
+                           already has a fixed order. Overrides the tuned shapes of spreading and
+                           interpolation (dpse_plan_autotune and dpse_plan_set_tiles leave them to
+                           this rule). Slower than the default path; results agree with it to
+                           rounding */
 };
 
 /* Parameters of one slab system. Lengths share one unit. */
@@ -109,7 +119,8 @@ typedef struct {
   double r_cut;                     /* near cutoff, 0 < r_cut < min(Lx, Ly)/2; 0 = derive from delta (eq. rnf) */
   double delta;                     /* tolerance used when r_cut == 0 (default 1e-4 if 0)    */
   int32_t precision;                /* DPSE_FP64 or DPSE_MIXED                               */
-  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY */
+  int32_t flags;                    /* DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY
+                                       | DPSE_DETERMINISTIC */
 } dpse_params;
 
 /* Derived quantities of a plan (Sec. 3.2 eq. gt, Sec. 5.1 eq. He, Sec. 5.2.2). */
@@ -329,11 +340,13 @@ const char* dpse_status_string(int status);
  *   DPSE_STAGE_WALL_HAT   x,y transforms of sigma_b then sigma_t, complex [2][Ny][Nx/2+1], FP64
  *   DPSE_STAGE_WALL_PHI   potential of the wall charges alone on the grid, [Nz][Ny][Nx]
  *   DPSE_STAGE_WALL_SCALARS (int sigma, int |sigma|, int sigma phi_s, k = 0 slope of phi_s), FP64
+ *   DPSE_STAGE_FH_O   x,y transform of F_O, complex [Nz][Ny][Nx/2+1] (zero outside the bands)
  * (the wall entries after dpse_plan_set_walls) */
 enum {
   DPSE_STAGE_F_I = 0, DPSE_STAGE_F_O = 1, DPSE_STAGE_FH_I = 2, DPSE_STAGE_PSI = 3,
   DPSE_STAGE_PSIZ = 4, DPSE_STAGE_GRIDS = 5, DPSE_STAGE_FAR = 6, DPSE_STAGE_NEAR = 7,
-  DPSE_STAGE_SCALARS = 8, DPSE_STAGE_WALL_HAT = 9, DPSE_STAGE_WALL_PHI = 10, DPSE_STAGE_WALL_SCALARS = 11
+  DPSE_STAGE_SCALARS = 8, DPSE_STAGE_WALL_HAT = 9, DPSE_STAGE_WALL_PHI = 10, DPSE_STAGE_WALL_SCALARS = 11,
+  DPSE_STAGE_FH_O = 12
 };
 int dpse_debug_copy(dpse_plan* plan, int which, void* dst, int64_t bytes,
                     int32_t* elem_bytes, int64_t* count);

@@ -29,9 +29,21 @@ struct Geom {
   // near-field cell list
   int ncx, ncy, ncz;
   double cwx, cwy, cwz;
-  // wall bands of the psi_o* solve: nodes [0, top_end) and [bot_begin, Nz)
-  int top_end, bot_begin;
+  // wall bands of the psi_o* solve, where the spread of the wall group can be
+  // non-zero: nodes [top_lo, top_end) (H - 3 H_E < z <= H + H_E) and
+  // [bot_begin, bot_end) (-H_E <= z < 3 H_E); the nodes descend with the index
+  int top_lo, top_end, bot_begin, bot_end;
 };
+
+// Whether node c lies in a wall band (the wall-group grid is zero elsewhere).
+__host__ __device__ inline bool in_band(const Geom& g, int c) {
+  return (c >= g.top_lo && c < g.top_end) || (c >= g.bot_begin && c < g.bot_end);
+}
+
+// Whether nodes [c0, c1) meet a wall band.
+__host__ __device__ inline bool meets_band(const Geom& g, int c0, int c1) {
+  return (c0 < g.top_end && c1 > g.top_lo) || (c0 < g.bot_end && c1 > g.bot_begin);
+}
 
 // One particle record: position and strength.
 struct Part {
@@ -90,6 +102,7 @@ struct Workspace {
   // scalars: 0 sum q, 1 sum |q|, 2 B_i, 3 A_i, 4 far0, 5 near0, 6 energy scratch
   double* scal = nullptr;
   double* partials = nullptr;  // block partial sums
+  double* qpart = nullptr;     // per-block sums of q and |q| of the prep kernel, [2][ceil(max_n / 256)]
   int* status = nullptr;
 };
 

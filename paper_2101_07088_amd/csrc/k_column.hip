@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
       if (mi < nmodes) {
         const size_t o = (size_t)c * nmodes + mi;
         va[q] = fx_i[o];
-        if (c < g.top_end || c >= g.bot_begin) vb[q] = fx_o[o];
+        if (in_band(g, c)) vb[q] = fx_o[o];
       }
     }
 #pragma unroll

@@ -380,14 +380,16 @@ hipError_t launch_fft_forward(dpse_plan* p) {
   FftJobs<R> X = no_jobs<R>(), Y = no_jobs<R>();
   add_x_rows<R>(g, X, (const R*)p->w.f_i, (C*)p->w.fx_i, 0, g.Nz);
   add_y_planes<R>(g, Y, (C*)p->w.fx_i, 0, g.Nz);
+  // the wall-group grid only on its bands (one range where they meet)
   if (g.top_end >= g.bot_begin) {
-    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.Nz);
-    add_y_planes<R>(g, Y, (C*)p->w.fx_o, 0, g.Nz);
+    const int a = std::min(g.top_lo, g.bot_begin), b = std::max(g.top_end, g.bot_end);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, a, b);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, a, b);
   } else {
-    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, 0, g.top_end);
-    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, g.bot_begin, g.Nz);
-    add_y_planes<R>(g, Y, (C*)p->w.fx_o, 0, g.top_end);
-    add_y_planes<R>(g, Y, (C*)p->w.fx_o, g.bot_begin, g.Nz);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, g.top_lo, g.top_end);
+    add_x_rows<R>(g, X, (const R*)p->w.f_o, (C*)p->w.fx_o, g.bot_begin, g.bot_end);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, g.top_lo, g.top_end);
+    add_y_planes<R>(g, Y, (C*)p->w.fx_o, g.bot_begin, g.bot_end);
   }
   launch_x<R>(p, X);
   launch_y<R>(p, Y);

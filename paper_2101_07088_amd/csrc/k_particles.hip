@@ -62,7 +62,7 @@ __device__ inline int cell_of(const Geom& g, double x, double y, double z) {
 // Validation, periodic wrap, groups C_o / C_>, images of C_o charges.
 __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const double* __restrict__ pos,
                                                    const double* __restrict__ q, Part* ext, int* meta,
-                                                   int* n_img, double* scal, int* status, int* bin_cnt,
+                                                   int* n_img, double* qpart, int* status, int* bin_cnt,
                                                    int* cell_cnt) {
   __shared__ double sh[kThreads / 64];
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
@@ -144,40 +144,53 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     meta[n + sh_] = GRP_INNER | (int)(i << 2);
     atomicAdd(&bin_cnt[spread_key(g, x, y, z - g.H)], 1);
   }
+  // the block's sums of q and |q| (summed over the blocks in a fixed order by k_scatter_ext)
   double s1 = block_sum(qq, sh);
   double s2 = block_sum(fabs(qq), sh);
   if (threadIdx.x == 0) {
-    atomicAdd(&scal[0], s1);
-    atomicAdd(&scal[1], s2);
+    qpart[2 * blockIdx.x] = s1;
+    qpart[2 * blockIdx.x + 1] = s2;
   }
 }
 
 // What a solve accumulates into, cleared in one launch before the prep
-// kernel: the image counter, the charge sums (sum q, sum |q|; the gauge
-// constant scal[2] of the last full solve stays, for dpse_solve_near) and the
-// bin counters of the grid stages and of the near-field cell list.
-__global__ void __launch_bounds__(kThreads) k_reset(int* n_img, double* scal, int* bin_cnt, int nbin,
-                                                    int* cell_cnt, int ncell) {
+// kernel: the image counter and the bin counters of the grid stages and of
+// the near-field cell list (the gauge constant scal[2] of the last full
+// solve stays, for dpse_solve_near).
+__global__ void __launch_bounds__(kThreads) k_reset(int* n_img, int* bin_cnt, int nbin, int* cell_cnt, int ncell) {
   const int t = blockIdx.x * kThreads + threadIdx.x, stride = gridDim.x * kThreads;
   if (t == 0) *n_img = 0;
-  if (t < 2) scal[t] = 0.0;
   for (int i = t; i < nbin; i += stride) bin_cnt[i] = 0;
   for (int i = t; i < ncell; i += stride) cell_cnt[i] = 0;
 }
 
 // Scatter of charges and images into the spreading bins (counted by the prep
-// kernel); the first thread also checks the neutrality of the charges and the
-// wall charges together (eq. elecneu) from the sums of the prep kernel (ws =
-// the wall scalars (int sigma, int |sigma|), or null without walls).
+// kernel). The first block also sums the prep kernel's nqb block sums of q
+// and |q| in a fixed order (strided per thread, then a fixed tree), stores
+// them in scal[0], scal[1] and checks the neutrality of the charges and the
+// wall charges together (eq. elecneu; ws = the wall scalars (int sigma,
+// int |sigma|), or null without walls).
 __global__ void __launch_bounds__(kThreads) k_scatter_ext(Geom g, int64_t n, const Part* __restrict__ ext,
                                                           const int* __restrict__ meta,
                                                           const int* __restrict__ n_img, int* cur,
-                                                          Part* srt, int* srt_meta, const double* scal,
-                                                          const double* ws, int* status) {
+                                                          Part* srt, int* srt_meta, const double* qpart, int nqb,
+                                                          double* scal, const double* ws, int* status) {
+  __shared__ double sh[kThreads / 64];
   int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  if (i == 0) {
-    const double net = scal[0] + (ws ? ws[0] : 0.0), tot = scal[1] + (ws ? ws[1] : 0.0);
-    if (!(fabs(net) <= 1e-12 * tot)) atomicOr(status, 4);
+  if (blockIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nqb; k += kThreads) {
+      a += qpart[2 * k];
+      b += qpart[2 * k + 1];
+    }
+    a = block_sum(a, sh);
+    b = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+      scal[0] = a;
+      scal[1] = b;
+      const double net = a + (ws ? ws[0] : 0.0), tot = b + (ws ? ws[1] : 0.0);
+      if (!(fabs(net) <= 1e-12 * tot)) atomicOr(status, 4);
+    }
   }
   if (i >= n + *n_img) return;
   Part p = ext[i];
@@ -194,6 +207,33 @@ __global__ void __launch_bounds__(kThreads) k_scatter_cells(Geom g, int64_t n, c
   int s = atomicAdd(&cur[cell_of(g, p.x, p.y, p.z)], 1);
   srt[s] = p;
   idx[s] = (int)i;
+}
+
+// Deterministic order inside the segments of a counting sort (the scatters
+// claim slots with atomics, so the order within a segment follows the
+// scheduling): one thread per segment [off[b], off[b+1]) puts its entries in
+// increasing key order by insertion (segments hold a few entries at the
+// densities of the workloads; the cost grows with the square of a segment's
+// length). The keys are unique: spreading bins sort by (meta, z) (a charge,
+// each of its images and each periodic copy differ in group or height),
+// cells by the charge index.
+__global__ void __launch_bounds__(kThreads) k_sort_bins(int nseg, const int* __restrict__ off, Part* srt,
+                                                        int* key) {
+  const int b = blockIdx.x * kThreads + threadIdx.x;
+  if (b >= nseg) return;
+  const int a = off[b], e = off[b + 1];
+  for (int i = a + 1; i < e; ++i) {
+    const Part p = srt[i];
+    const int m = key[i];
+    int j = i - 1;
+    while (j >= a && (key[j] > m || (key[j] == m && srt[j].z > p.z))) {
+      srt[j + 1] = srt[j];
+      key[j + 1] = key[j];
+      --j;
+    }
+    srt[j + 1] = p;
+    key[j + 1] = m;
+  }
 }
 
 // Exclusive scan of cnt[0..m) into off[0..m] and cur[0..m) by one block:
@@ -490,11 +530,11 @@ hipError_t launch_prep(dpse_plan* p, int64_t n, const double* pos, const double*
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   const int nbin = (int)p->nkeys + 1, ncell = (int)p->ncells + 1;
-  hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max(nbin, ncell), 64)), dim3(kThreads), 0, s, w.n_img, w.scal,
+  hipLaunchKernelGGL(k_reset, dim3(blocks_for(std::max(nbin, ncell), 64)), dim3(kThreads), 0, s, w.n_img,
                      w.bin_cnt, nbin, w.cell_cnt, ncell);
   int nb = (int)((n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_prep, dim3(nb), dim3(kThreads), 0, s, p->g, n, pos, q, w.ext, w.ext_meta,
-                     w.n_img, w.scal, w.status, w.bin_cnt, w.cell_cnt);
+                     w.n_img, w.qpart, w.status, w.bin_cnt, w.cell_cnt);
   return hipGetLastError();
 }
 
@@ -505,9 +545,14 @@ hipError_t launch_bin_grid(dpse_plan* p, int64_t n) {
   Workspace& w = p->w;
   int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
+  const int nqb = (int)((n + kThreads - 1) / kThreads);  // blocks of the prep kernel
   hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta,
-                     (const double*)w.scal, p->walls_on ? (const double*)p->walls.scal : nullptr, w.status);
+                     (const double*)w.qpart, nqb, w.scal, p->walls_on ? (const double*)p->walls.scal : nullptr,
+                     w.status);
+  if (p->g.flags & DPSE_DETERMINISTIC)
+    hipLaunchKernelGGL(k_sort_bins, dim3((p->nkeys + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->nkeys,
+                       (const int*)w.bin_off, w.srt, w.srt_meta);
   return hipGetLastError();
 }
 
@@ -521,6 +566,9 @@ hipError_t launch_bin_cells(dpse_plan* p, int64_t n) {
                      p->ncells);
   hipLaunchKernelGGL(k_scatter_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      w.cell_cur, w.nsrt, w.nsrt_idx);
+  if (p->g.flags & DPSE_DETERMINISTIC)
+    hipLaunchKernelGGL(k_sort_bins, dim3((p->ncells + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p->ncells,
+                       (const int*)w.cell_off, w.nsrt, w.nsrt_idx);
   return hipGetLastError();
 }
 

@@ -58,7 +58,8 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   if (!std::isfinite(p->g_w) || p->g_w < 0.0) return DPSE_EINVAL;
   if (!is_pow2(p->Nx) || !is_pow2(p->Ny) || p->Nx < 32 || p->Ny < 32 || p->Nx > 1024 || p->Ny > 1024)
     return DPSE_EINVAL;
-  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY))
+  if (p->flags & ~(DPSE_GAUGE_NONE | DPSE_KMAX_GT | DPSE_UNIFORM_FAST | DPSE_ONE_JUMP | DPSE_TRIPLY |
+                   DPSE_DETERMINISTIC))
     return DPSE_EINVAL;
   const bool tp = (p->flags & DPSE_TRIPLY) != 0;
   if (tp ? (p->Nz < 32 || !is_pow2(p->Nz) || p->Nz > 1024) : (p->Nz < 33 || !is_pow2(p->Nz - 1) || p->Nz - 1 > 1024))
@@ -157,23 +158,32 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     g->ncy = std::max(1, std::min(1024, (int)std::floor(p->Ly / rc)));
     g->ncz = std::max(1, std::min(1024, (int)std::floor(p->H / rc)));
     g->cwx = p->Lx / g->ncx; g->cwy = p->Ly / g->ncy; g->cwz = p->H / g->ncz;
-    // wall bands of psi_o*: nodes with z_j > H - 3 H_E (top) or z_j < 3 H_E (bottom)
+    // wall bands of psi_o*: the wall group's charges lie in 0 < z < 2 H_E or
+    // H - 2 H_E < z < H and reach the nodes within H_E of them, so their
+    // spread is non-zero only at H - 3 H_E < z_j < H + H_E (top) and
+    // -H_E < z_j < 3 H_E (bottom); the bounds H + H_E and -H_E are kept
+    // inclusive. Nodes descend with the index j.
     int N = p->Nz;
-    int top_end = 0, bot_begin = N;
+    int top_lo = N, top_end = 0, bot_begin = N, bot_end = 0;
     for (int j = 0; j < N; ++j) {
       double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
-      if (z > p->H - 3.0 * H_E) top_end = j + 1;
+      if (z > p->H - 3.0 * H_E && z <= p->H + H_E) {
+        top_lo = std::min(top_lo, j);
+        top_end = j + 1;
+      }
+      if (z < 3.0 * H_E && z >= -H_E) {
+        bot_begin = std::min(bot_begin, j);
+        bot_end = j + 1;
+      }
     }
-    for (int j = N - 1; j >= 0; --j) {
-      double z = g->zc + g->zR * std::cos(dpse::kPi * j / (N - 1));
-      if (z < 3.0 * H_E) bot_begin = j;
+    if (fast || tp || top_end == 0 || bot_end == 0) {  // one group: no wall band
+      top_lo = top_end = 0;
+      bot_begin = bot_end = N;
     }
-    if (fast || tp) {  // one group: no wall band
-      top_end = 0;
-      bot_begin = N;
-    }
+    g->top_lo = top_lo;
     g->top_end = top_end;
     g->bot_begin = bot_begin;
+    g->bot_end = bot_end;
   }
   return DPSE_OK;
 }
@@ -226,6 +236,7 @@ size_t carve_workspace(dpse_plan* p, char* base) {
   // partials: near part at the origin, finalize, far part at the origin per
   // node (two blocks of npartials: Nz <= 2 npartials), wall energy
   c.take(&w.scal, 16); c.take(&w.partials, 5 * (size_t)p->npartials);
+  c.take(&w.qpart, 2 * ((max_n + 255) / 256));
   return (c.off + 255) & ~size_t(255);
 }
 
@@ -927,6 +938,8 @@ int dpse_plan_autotune(dpse_plan* p, int64_t n, const double* pos, const double*
   if (ms)
     for (int i = 0; i < DPSE_MAX_CANDIDATES * DPSE_NUM_TUNED; ++i) ms[i] = -1.0;
   for (int s = 0; s < DPSE_NUM_TUNED && st == DPSE_OK; ++s) {
+    // the deterministic mode fixes the spreading and interpolation kernels
+    if (s < 2 && (p->g.flags & DPSE_DETERMINISTIC)) continue;
     int best = -1;
     double tbest = 0.0;
     for (int i = 0; i < tuned_count(s) && st == DPSE_OK; ++i) {
@@ -1035,6 +1048,7 @@ int dpse_debug_copy(dpse_plan* p, int which, void* dst, int64_t bytes, int32_t* 
     case DPSE_STAGE_F_I: src = p->w.f_i; cnt = G; break;
     case DPSE_STAGE_F_O: src = p->w.f_o; cnt = G; break;
     case DPSE_STAGE_FH_I: src = p->w.fx_i; cnt = C; break;
+    case DPSE_STAGE_FH_O: src = p->w.fx_o; cnt = C; break;
     case DPSE_STAGE_PSI: src = p->w.psi; cnt = C; break;
     case DPSE_STAGE_PSIZ: src = p->w.psiz; cnt = C; break;
     case DPSE_STAGE_GRIDS: src = p->w.u4; cnt = 4 * G; break;
@@ -1049,10 +1063,11 @@ int dpse_debug_copy(dpse_plan* p, int which, void* dst, int64_t bytes, int32_t* 
   if (!src) return DPSE_EINVAL;  // wall data before dpse_plan_set_walls
   if (cnt * eb > bytes) return DPSE_EINVAL;
   if (hipMemcpy(dst, src, cnt * eb, hipMemcpyDeviceToHost) != hipSuccess) return DPSE_EHIP;
-  if (which == DPSE_STAGE_F_O) {
+  if (which == DPSE_STAGE_F_O || which == DPSE_STAGE_FH_O) {
     // only the wall-band planes are computed; report zeros elsewhere
-    int64_t plane = (int64_t)g.Ny * g.Nx * eb;
-    for (int j = g.top_end; j < g.bot_begin; ++j) std::memset((char*)dst + j * plane, 0, plane);
+    int64_t plane = (which == DPSE_STAGE_F_O ? (int64_t)g.Ny * g.Nx : (int64_t)g.Ny * g.nkx * 2) * eb;
+    for (int j = 0; j < g.Nz; ++j)
+      if (!dpse::in_band(g, j)) std::memset((char*)dst + j * plane, 0, plane);
   }
   if (elem_bytes) *elem_bytes = eb;
   if (count) *count = cnt;

@@ -97,6 +97,35 @@ def test_gaussian_charges_and_gauge_off():
     check(p.copy(kmax_gt=True), pos, q, 1e-9, label="kmax g_t cap")
 
 
+def test_gaussian_charges_closer_than_the_taylor_switch():
+    """Gaussian charges (g_w = 0.05) with pairs closer than 1e-3 g_w, where
+    the near-field kernel takes its small-r series (eq. GnearK at r -> 0),
+    one just above the switch, and a charge next to its own wall image:
+    the near stage at 1e-12 and the outputs at the FP64 bar."""
+    _need_gpu()
+    import paper_2101_07088_amd as dp
+    p, pos, q = small_jump(41, 40)
+    p = p.copy(g_w=0.05)
+    pos[:, 2] = np.clip(pos[:, 2], 0.25, p.H - 0.25)
+    # pairs of opposite charges at 2e-5, 4.5e-5 (both below 1e-3 g_w = 5e-5) and 6e-5 (above)
+    for k, (a, b, r) in enumerate(((0, 1, 2e-5), (2, 3, 4.5e-5), (4, 5, 6e-5))):
+        j = int(np.nonzero(q == -q[a])[0][k + 10])
+        q[[b, j]] = q[[j, b]]
+        pos[b] = pos[a] + r * np.array([0.6, -0.48, 0.64])
+    pos[6, 2] = 0.21   # 0.42 from its bottom image
+    assert abs(q.sum()) < 1e-12
+    U0, phi0, F0, inter = O.solve(p, pos, q)
+    plan, st, U, phi, F = run(p, pos, q)
+    assert st == 0
+    near = plan.debug(dp.Stage.NEAR)[: len(q)]
+    en = float(np.max(np.abs(near - inter["near"])) / np.max(np.abs(inter["near"])))
+    eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
+    print(f"[case] close Gaussian pairs: near {en:.2e} relRMS F {eF:.2e} phi {ep:.2e}", flush=True)
+    assert en < 1e-12
+    assert eF < 1e-9 and ep < 1e-9
+    assert abs(U - U0) < 1e-9 * 0.5 * np.sum(np.abs(q * phi0))
+
+
 def test_plan_reuse_with_changing_n():
     _need_gpu()
     import paper_2101_07088_amd as dp

@@ -65,6 +65,21 @@ CASES = {
 }
 
 
+def _growth(p, inter):
+    """Per node and mode, the factor e^{|k| d} by which the harmonic
+    correction grows at a node a distance d outside the slab (inside its
+    window -H_E <= z <= H + H_E, corrected modes only; 1 elsewhere): rounding
+    differences of the mismatches are magnified by it there (Sec. 5.2.2
+    step 4), so errors are compared after dividing by it."""
+    d = O.derive(p)
+    z = d["z"]
+    out = np.maximum(0.0, np.maximum(z - p.H, -z))
+    win = (z >= -d["H_E"]) & (z <= p.H + d["H_E"])
+    act = d["keep"] & (d["kabs"] > 0.0)
+    g = np.exp(np.where(win, out, 0.0)[:, None, None] * d["kabs"][None])
+    return np.where(act[None], g, 1.0)
+
+
 def _stage_report(plan, inter, p, n):
     import paper_2101_07088_amd as dp
     S = dp.Stage
@@ -72,14 +87,23 @@ def _stage_report(plan, inter, p, n):
     out["f_i"] = rel_max(plan.debug(S.F_I), inter["f_i"])
     out["f_o"] = rel_max(plan.debug(S.F_O), inter["f_o"]) if np.any(inter["f_o"]) else 0.0
     out["FH_i"] = rel_max(plan.debug(S.FH_I), inter["F_i"])
-    out["Psi"] = rel_max(plan.debug(S.PSI), inter["Psi"])
-    out["Psi_z"] = rel_max(plan.debug(S.PSIZ), inter["Psi_z"])
-    out["grids"] = rel_max(plan.debug(S.GRIDS), inter["grids"])
+    out["FH_o"] = rel_max(plan.debug(S.FH_O), inter["F_o"]) if np.any(inter["F_o"]) else 0.0
+    gr = _growth(p, inter)
+    for key, st in (("Psi", S.PSI), ("Psi_z", S.PSIZ)):
+        got, ref = plan.debug(st), inter[key]
+        out[key] = rel_max(got, ref)
+        out[key + "_scaled"] = float(np.max(np.abs(got - ref) / gr) / np.max(np.abs(ref)))
+    grids = plan.debug(S.GRIDS)
+    out["grids"] = rel_max(grids, inter["grids"])
+    inside = (inter["derived"]["z"] >= 0.0) & (inter["derived"]["z"] <= p.H)
+    out["grids_slab"] = float(np.max(np.abs(grids - inter["grids"])[:, inside]) / np.max(np.abs(inter["grids"])))
     out["far"] = rel_max(plan.debug(S.FAR)[:n], inter["far"])
     out["near"] = rel_max(plan.debug(S.NEAR)[:n], inter["near"])
     sc = plan.debug(S.SCALARS)
-    out["A_i"] = abs(sc[3] - inter["A_i"].real) / max(abs(inter["A_i"].real), 1e-300)
-    out["far0"] = abs(sc[4] - inter["far0"]) / max(abs(inter["far0"]), 1e-300)
+    # A_i joins the k = 0 column of Psi_z, far0 is an average of the potential grid
+    out["A_i"] = abs(sc[3] - inter["A_i"].real) / max(abs(inter["A_i"].real),
+                                                       float(np.max(np.abs(inter["Psi_z"][:, 0, 0]))), 1e-300)
+    out["far0"] = abs(sc[4] - inter["far0"]) / max(abs(inter["far0"]), float(np.max(np.abs(inter["grids"][0]))))
     out["near0"] = abs(sc[5] - inter["near0"]) / max(abs(inter["near0"]), 1e-300)
     return out
 
@@ -93,14 +117,18 @@ def test_fp64_stages_and_outputs_match_oracle(name):
     plan, U, phi, F = gpu_solve(p, pos, q)
     rep = _stage_report(plan, inter, p, len(q))
     print("[parity] stages:", {k: f"{v:.2e}" for k, v in rep.items()}, flush=True)
-    for k in ("f_i", "f_o", "FH_i", "far", "near"):
+    for k in ("f_i", "f_o", "FH_i", "FH_o", "far", "near", "near0"):
         assert rep[k] < 1e-12, (k, rep[k])
-    # node values of the harmonic correction grow like e^{k H_E} towards the
-    # edges of its window (Sec. 5.2.2 step 4), which magnifies rounding
-    # differences of the mismatches there; the interpolated results are not
-    # affected (checked below at the 1e-9 bar)
+    # node values of the harmonic correction grow like e^{k d} at a distance d
+    # outside the slab (Sec. 5.2.2 step 4), which magnifies rounding
+    # differences of the mismatches there: per node and mode the errors are
+    # compared after dividing by that factor, and the grids on the slab's own
+    # nodes; unscaled, every node stays within 1e-8 of the largest value
+    for k in ("Psi_scaled", "Psi_z_scaled", "grids_slab"):
+        assert rep[k] < 1e-12, (k, rep[k])
     for k in ("Psi", "Psi_z", "grids"):
         assert rep[k] < 1e-8, (k, rep[k])
+    assert rep["A_i"] < 1e-10 and rep["far0"] < 1e-11, (rep["A_i"], rep["far0"])
     errF = rel_rms(F, F0)
     errp = rel_rms(phi, phi0)
     print(f"[parity] relRMS F {errF:.2e} phi {errp:.2e} U {U:.12e} vs {U0:.12e}", flush=True)

@@ -177,15 +177,17 @@ def test_batch_matches_single_solves(precision, use_graph):
     br.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_server_alone_equals_mix(precision):
+@pytest.mark.parametrize("precision,deterministic", [(0, False), (1, False), (0, True), (1, True)])
+def test_server_alone_equals_mix(precision, deterministic):
     """Each request gives the same result served alone (a fresh plan, nothing
     else on the device) and in a mix of concurrent requests from several
-    systems under a memory budget that forces queueing."""
+    systems under a memory budget that forces queueing; with
+    DPSE_DETERMINISTIC the two are bitwise equal. One served result per
+    system is also checked against the oracle."""
     _need_gpu()
     import paper_2101_07088_amd as dp
     from paper_2101_07088_amd.serve import Server
-    systems = uneven_batch()
+    systems = [(p.copy(deterministic=deterministic), pos, q) for p, pos, q in uneven_batch()]
     fps = [dp.workspace_size(p, len(q), precision) for p, _, q in systems]
     budget = int(sum(sorted(fps)[-3:]) * 1.05)          # at most about three in flight
     srv = Server(budget_bytes=budget, n_slots=4, precision=precision)
@@ -201,16 +203,28 @@ def test_server_alone_equals_mix(precision):
     srv.drain()
     assert srv.stats["completed"] == len(reqs) and srv.stats["failed"] == 0
     assert srv.stats["peak_bytes"] <= budget
-    print(f"[case] server prec={precision}: {srv.stats}", flush=True)
-    tol = 1e-13 if precision == 0 else 2e-6
+    print(f"[case] server prec={precision} det={deterministic}: {srv.stats}", flush=True)
+    tol = 0.0 if deterministic else (1e-13 if precision == 0 else 2e-6)
+    checked = set()
     for k, cur, r in reqs:
         p, _, q = systems[k]
         pl = dp.Plan(p, max_n=len(q), precision=precision)
         U, phi, F = pl.solve(dev(cur), dev(q))
         assert pl.sync_status() == 0
         E1, PH1, F1 = r.result
-        assert rel_rms(F1.cpu().numpy(), F.cpu().numpy()) < tol
-        assert rel_rms(PH1.cpu().numpy(), phi.cpu().numpy()) < tol
-        assert abs(float(E1.cpu()[0]) - float(U.cpu()[0])) < 10 * tol * abs(float(U.cpu()[0]))
+        F1, PH1, U1 = F1.cpu().numpy(), PH1.cpu().numpy(), float(E1.cpu()[0])
+        if deterministic:
+            assert np.array_equal(F1, F.cpu().numpy()) and np.array_equal(PH1, phi.cpu().numpy())
+            assert U1 == float(U.cpu()[0])
+        else:
+            assert rel_rms(F1, F.cpu().numpy()) < tol
+            assert rel_rms(PH1, phi.cpu().numpy()) < tol
+            assert abs(U1 - float(U.cpu()[0])) < 10 * tol * abs(float(U.cpu()[0]))
         pl.close()
+        if k not in checked:   # the served result against the FP64 oracle
+            checked.add(k)
+            U0, phi0, F0, _ = O.solve(p, cur, q)
+            bar = 1e-9 if precision == 0 else 1e-5
+            assert rel_rms(F1, F0) < bar and rel_rms(PH1, phi0) < bar
+            assert abs(U1 - U0) < bar * 0.5 * np.sum(np.abs(q * phi0))
     srv.close()

@@ -33,7 +33,8 @@ class SlabParams:
     ``one_jump`` the solver for a jump at one wall only (every charge imaged
     across it, then the free-space solve on the span of charges and images);
     ``triply`` the triply periodic variant (z periodic with period H, uniform
-    z grid of Nz nodes).
+    z grid of Nz nodes). ``deterministic`` asks the HIP path for
+    bitwise-reproducible solves (no effect on what is computed).
     """
 
     Lx: float
@@ -54,6 +55,7 @@ class SlabParams:
     uniform_fast: bool = False
     one_jump: bool = False
     triply: bool = False
+    deterministic: bool = False
 
     def copy(self, **kw) -> "SlabParams":
         return dataclasses.replace(self, **kw)
