@@ -1,14 +1,20 @@
 """Benchmark: charge-force evaluations per second of the DP-SE far+near solve.
 
-One step = one complete solve (all stages, far field + near field + energy)
-of the jump workload: N = 16384 monovalent ions in Lx = Ly = 64, H = 32,
-eps = 1 inside, eps_b = eps_t = 0.05, xi = 1, grid 256 x 256 x 129, near
-cutoff 3. Positions and charges are resident in HBM before the timed region.
+One step = one complete solve (all stages: validation and binning, spreading,
+forward transforms, the per-mode column solve with the harmonic correction,
+inverse transforms, interpolation, near field, gauge and energy) of the large
+slab workload: N = 1,048,576 monovalent ions in Lx = Ly = 256, H = 64, eps = 1
+inside, eps_b = 0.05 below, eps_t = 20 above, xi = 1.5, grid 1024 x 1024 x 257,
+near cutoff 2. Positions and charges are resident in HBM before the timed
+region.
 
 The headline path is the mixed-precision one (FP32 grid stages, FP64
 per-mode solves and per-charge sums) when its relative RMS force error
-against the FP64 path is <= 1e-5; otherwise the FP64 path.
-Prints one JSON line.
+against the FP64 path on the same charges is <= 1e-5; otherwise the FP64
+path. Secondary lines: the 16,384-ion jump workload (256 x 256 x 129) in
+both precisions (accuracy over seeds 0-4), the 64-charge small workload
+(eager against graph launches), and the optional variant, batch and serving
+measurements. Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -27,16 +33,17 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def stage_bytes(p, info_band_frac, s):
+def stage_bytes(p, beta, s):
     """Algorithmic HBM bytes per launch of each grid stage: every stage-boundary
-    array read once and written once (G grid points, C half-spectrum complexes)."""
+    array read once and written once (G grid points, C half-spectrum reals,
+    beta the fraction of Chebyshev nodes where the wall-group grid can be
+    non-zero, s bytes per real)."""
     G = p.Nz * p.Ny * p.Nx
     Cr = 2 * p.Nz * p.Ny * (p.Nx // 2 + 1)
-    b = info_band_frac
     return {
-        "spread": (1 + b) * G * s,
-        "fft_forward": (1 + b) * (G + Cr) * s,
-        "column": (3 + b) * Cr * s,
+        "spread": (1 + beta) * G * s,
+        "fft_forward": (1 + beta) * (G + Cr) * s,
+        "column": (3 + beta) * Cr * s,
         "fft_inverse": (2 * Cr + 4 * G) * s,
         "interp": 4 * G * s,
     }
@@ -74,7 +81,7 @@ def profiled_traffic(kernel):
     import hashlib
     if kernel is None:
         return None
-    files = glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_jump_*.txt"))
+    files = glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_large_*.txt"))
     if not files:
         return None
     src = os.path.join(ROOT, "paper_2101_07088_amd", "csrc")
@@ -90,13 +97,25 @@ def profiled_traffic(kernel):
 
 
 def band_fraction(p, info):
+    """Fraction of the Chebyshev nodes in the wall bands, where the spread of
+    the wall group can be non-zero: H - 3 H_E < z <= H + H_E and
+    -H_E <= z < 3 H_E (charges of the group lie within 2 H_E of a wall and
+    reach nodes within H_E of them)."""
     z = [0.5 * (info["z_lo"] + info["z_hi"]) + 0.5 * (info["z_hi"] - info["z_lo"]) * math.cos(math.pi * j / (p.Nz - 1))
          for j in range(p.Nz)]
     he = info["H_E"]
-    return sum(1 for zz in z if zz < 3 * he or zz > p.H - 3 * he) / p.Nz
+    if getattr(p, "uniform_fast", False) or getattr(p, "one_jump", False) or getattr(p, "triply", False):
+        return 0.0
+    return sum(1 for zz in z if (p.H - 3 * he < zz <= p.H + he) or (-he <= zz < 3 * he)) / p.Nz
 
 
-def time_path(dp, torch, p, tpos, tq, precision, steps, warmup, walls=None):
+def time_path(dp, torch, p, tpos, tq, precision, steps, warmup, walls=None, live_stages=False, latency_solves=0):
+    """Plan, autotune (outside the timed region), warm up, then time `steps`
+    solves back to back. With live_stages the library's per-stage HIP events
+    are recorded on the plan's stream during the timed region itself (their
+    cost is negligible next to a solve of the large workload); otherwise in a
+    separate pass of the same solves. latency_solves > 0 adds a pass of that
+    many solves, each bracketed by its own events (p50/p99)."""
     plan = dp.Plan(p, max_n=len(tq), precision=precision)
     if walls is not None:
         plan.set_walls(*walls)
@@ -107,48 +126,141 @@ def time_path(dp, torch, p, tpos, tq, precision, steps, warmup, walls=None):
     for _ in range(warmup):
         plan.solve(tpos, tq, E, PH, F)
     plan.sync()
-    # per-solve latency with events on the plan's (= current) stream
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    if live_stages:
+        plan.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
+        plan.solve(tpos, tq, E, PH, F)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = plan.sync_status()
+    if live_stages:
+        stages, _ = plan.stage_times()
+        plan.set_timing(False)
+    else:
+        plan.set_timing(True)
+        for _ in range(steps):
+            plan.solve(tpos, tq, E, PH, F)
+        stages, _ = plan.stage_times()
+        plan.set_timing(False)
+    # per-solve latency with events on the plan's (= current) stream
+    nl = latency_solves or steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nl)]
+    torch.cuda.synchronize()
+    for k in range(nl):
         evs[k][0].record()
         plan.solve(tpos, tq, E, PH, F)
         evs[k][1].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    st = plan.sync_status()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
-    # per-stage times over a separate pass (events between stages)
-    plan.set_timing(True)
-    for _ in range(steps):
-        plan.solve(tpos, tq, E, PH, F)
-    stages, _ = plan.stage_times()
-    plan.set_timing(False)
     plan.sync()
     out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]), tiles=tiles,
-               phi=PH.cpu().numpy(), F=F.cpu().numpy(), far=plan.debug(dp.Stage.FAR)[: len(tq)], info=plan.info)
+               phi=PH.cpu().numpy(), F=F.cpu().numpy(), far=plan.debug(dp.Stage.FAR)[: len(tq)], info=plan.info,
+               workspace_bytes=plan.info["workspace_bytes"])
     plan.close()
+    del E, PH, F
+    torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(p, pos, q, near_stride=8):
-    """The FP64 CPU oracle on a bounded sample of the same workload: its whole
-    far field on the full system plus its all-pairs near field for every
-    near_stride-th block of 1024 target charges; the near time is scaled by
-    the inverse of the sampled fraction."""
+def cpu_baseline(p, pos, q, seed=0):
+    """The FP64 CPU oracle (as written, untuned) timed on bounded samples of
+    the same workload, each stage's cost scaled to the whole solve:
+      * groups and images of every charge (whole);
+      * spreading and interpolation: the per-charge cost from two sample
+        sizes (the difference cancels the fixed cost of the full grids),
+        times the charges each stage visits, plus the one-time grid clear;
+      * the x,y transforms on a slab of z planes, times the planes of the
+        two forward and four inverse transforms;
+      * the z transforms, the per-mode dense solves, the wall values, the
+        correction and the node evaluations on one block of 512 modes, times
+        the blocks;
+      * the near field on 64 targets (all pairs with every charge and image),
+        times N / 64.
+    Returns the estimated evaluations per second of a full solve."""
     from oracle import dpse_oracle as O
-    threads = os.cpu_count() or 1
-    tm = {}
-    O.solve(p, pos, q, timings=tm, near_rows=near_stride)
+    rng = np.random.default_rng(seed)
     n = len(q)
-    chunks = (n + 1023) // 1024
-    frac = len(range(0, chunks, near_stride)) / chunks
-    t = tm["far"] + tm["near"] / frac
-    return {"value": n / t, "unit": "charge-force evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle: far field of the full workload ({tm['far']:.1f} s) + all-pairs near "
-                      f"field for {frac:.3f} of the targets ({tm['near']:.1f} s, scaled to all); "
-                      f"estimated full solve {t:.1f} s"}
+    d = O.derive(p)
+    tm = {}
+    T0 = time.perf_counter()
+    t0 = time.perf_counter()
+    c_o, ipos, iq = O.groups_and_images(p, d, pos, q)
+    tm["groups"] = time.perf_counter() - t0
+
+    def per_item(fn, m1, m2):
+        a = time.perf_counter(); fn(m1); t1 = time.perf_counter() - a
+        a = time.perf_counter(); fn(m2); t2 = time.perf_counter() - a
+        return max(t2 - t1, 0.0) / (m2 - m1), max(t1 - (t2 - t1) * m1 / (m2 - m1), 0.0)
+
+    sel = rng.choice(n, 2000, replace=False)
+    c_spread, fix_spread = per_item(lambda m: O.spread(p, d, pos[sel[:m]], q[sel[:m]]), 400, 2000)
+    tm["spread"] = 2 * fix_spread + c_spread * (int(np.count_nonzero(c_o)) + n + len(iq))
+    grids = np.zeros((4, p.Nz, p.Ny, p.Nx))   # lazily zeroed pages; only the windows are touched
+    c_interp, _ = per_item(lambda m: O.interp(p, d, grids, pos[sel[:m]]), 200, 1000)
+    tm["interp"] = c_interp * n
+    del grids
+    planes = 8
+    f = rng.standard_normal((planes, p.Ny, p.Nx))
+    a = time.perf_counter(); F = O.fft_xy(f, p); t = time.perf_counter() - a
+    a = time.perf_counter(); O.ifft_xy(F, p); ti = time.perf_counter() - a
+    tm["fft_xy"] = (2 * t + 4 * ti) * p.Nz / planes
+    nm_all = p.Ny * (p.Nx // 2 + 1)
+    blk = 512
+    ms = rng.choice(nm_all, blk, replace=False)
+    Fi = (rng.standard_normal((p.Nz, 1, blk)) + 1j * rng.standard_normal((p.Nz, 1, blk)))
+    a = time.perf_counter()
+    fh_i = O.cheb_coeffs(Fi)
+    fh_o = O.cheb_coeffs(Fi)
+    tm["cheb"] = (time.perf_counter() - a) * nm_all / blk
+    sub = dict(d)
+    sub["kabs"] = d["kabs"].ravel()[ms].reshape(1, blk)
+    pb = p.copy(Ny=1, Nx=2 * (blk - 1))   # the shape solve_modes reshapes to: [Nz, 1, blk]
+    a = time.perf_counter()
+    y_o, y_i = O.solve_modes(pb, sub, [fh_o, fh_i])
+    tm["bvp"] = (time.perf_counter() - a) * nm_all / blk
+    a = time.perf_counter()
+    R = d["R"]
+    s0, sH = (0.0 - d["c"]) / R, (p.H - d["c"]) / R
+    vals = [O.series_at(y, s) for y in (y_o, y_i) for s in (s0, sH)]
+    ders = [O.series_dz_at(y, s, R) for y in (y_o, y_i) for s in (s0, sH)]
+    kk = sub["kabs"][0]
+    pos_k = kk > 0.0
+    O.correction_coeffs(p, kk[pos_k], (vals[2][0] - vals[0][0])[pos_k], (ders[2][0] - ders[0][0])[pos_k],
+                        (vals[3][0] - vals[1][0])[pos_k], (ders[3][0] - ders[1][0])[pos_k])
+    from numpy.polynomial import chebyshev as npcheb
+    O.cheb_eval_nodes(y_i, p.Nz)
+    O.cheb_eval_nodes(npcheb.chebder(y_i, axis=0), p.Nz)
+    tm["modes_rest"] = (time.perf_counter() - a) * nm_all / blk
+    tt = rng.choice(n, 64, replace=False)
+    a = time.perf_counter()
+    O.near_field(p, d, pos, q, targets=tt)
+    tm["near"] = (time.perf_counter() - a) * n / len(tt)
+    sampled = time.perf_counter() - T0
+    total = sum(tm.values())
+    try:
+        import threadpoolctl
+        blas = max([i.get("num_threads", 1) for i in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        blas = 1
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n / total, "unit": "charge-force evals/s", "cores": int(blas), "kind": "oracle",
+            "cpu_model": cpu, "host_cpus": os.cpu_count(),
+            "sample": (f"FP64 oracle on samples of the large workload ({sampled:.1f} s of CPU work): spreading of "
+                       f"400 and 2000 charges and interpolation of 200 and 1000 (per-charge cost from the "
+                       f"difference), x,y "
+                       f"transforms of {planes} planes, z transforms + dense per-mode solves + correction + node "
+                       f"evaluation of {blk} modes, near field of 64 targets; each scaled to the whole solve "
+                       f"(estimated {total:.0f} s per solve; BLAS threads {blas}, FFT and loops single-threaded)"),
+            "stage_estimate_s": {k: round(v, 2) for k, v in tm.items()}}
 
 
 def rel_rms(a, b):
@@ -443,14 +555,92 @@ def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_s
     return out
 
 
+def bench_small(dp, torch, steps):
+    """The 64-charge small workload (32 x 32 x 33, FP64): per-solve time of
+    eager launches (about 20 kernels) against one graph launch of the
+    captured solve, and the launch overhead that the graph removes."""
+    import workloads as W
+    p, pos, q = W.config_small(0)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    plan = dp.Plan(p, max_n=len(q))
+    E = torch.empty(1, dtype=torch.float64, device="cuda")
+    PH = torch.empty(len(q), dtype=torch.float64, device="cuda")
+    F = torch.empty((len(q), 3), dtype=torch.float64, device="cuda")
+    out = {"n": len(q), "grid": [p.Nx, p.Ny, p.Nz]}
+    k = max(200, 10 * steps)
+    for name, fn in (("eager", plan.solve), ("graph", plan.solve_graph)):
+        for _ in range(10):
+            fn(tpos, tq, E, PH, F)
+        plan.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn(tpos, tq, E, PH, F)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / k
+        out[name] = {"us_per_solve": 1e6 * t, "evals_per_s": len(q) / t}
+    plan.set_timing(True)
+    for _ in range(20):
+        plan.solve(tpos, tq, E, PH, F)
+    stages, _ = plan.stage_times()
+    plan.set_timing(False)
+    out["gpu_busy_us_eager"] = 1e3 * sum(stages.values())
+    out["launch_overhead_us_removed_by_graph"] = out["eager"]["us_per_solve"] - out["graph"]["us_per_solve"]
+    plan.close()
+    return out
+
+
+def bench_jump(dp, torch, steps, warmup, seeds=(1, 2, 3, 4)):
+    """The jump workload (N = 16384, 256 x 256 x 129): both precisions at seed
+    0 (time, p50/p99, stages), and the mixed path's force error against the
+    FP64 path at seeds 0-4."""
+    import workloads as W
+    out = {"workload": "jump: N=16384 +-1 ions, Lx=Ly=64, H=32, eps=1, eps_b=eps_t=0.05, xi=1.0, "
+                       "grid 256x256x129, r_cut=3.0"}
+    p, pos, q = W.config_jump(0)
+    tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    res = {}
+    for prec, name in ((dp.DPSE_FP64, "fp64"), (dp.DPSE_MIXED, "mixed")):
+        r = time_path(dp, torch, p, tpos, tq, prec, steps, warmup, latency_solves=200)
+        res[name] = r
+        out[name] = {"ms": 1e3 * r["wall_s"] / steps, "evals_per_s": len(q) / (r["wall_s"] / steps),
+                     "p50_ms": float(np.percentile(r["lat_ms"], 50)), "p99_ms": float(np.percentile(r["lat_ms"], 99)),
+                     "latency_solves": len(r["lat_ms"]), "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
+                     "tiles": list(r["tiles"])}
+        print(f"[bench] jump {name}: {out[name]['ms']:.3f} ms/solve", file=sys.stderr, flush=True)
+    errs = {0: rel_rms(res["mixed"]["F"], res["fp64"]["F"])}
+    for sd in seeds:
+        p, pos, q = W.config_jump(sd)
+        tp_ = torch.tensor(pos, dtype=torch.float64, device="cuda")
+        tq_ = torch.tensor(q, dtype=torch.float64, device="cuda")
+        Fs = {}
+        for prec in (dp.DPSE_FP64, dp.DPSE_MIXED):
+            pl = dp.Plan(p, max_n=len(q), precision=prec)
+            _, _, F = pl.solve(tp_, tq_)
+            assert pl.sync_status() == 0
+            Fs[prec] = F.cpu().numpy()
+            pl.close()
+        errs[sd] = rel_rms(Fs[dp.DPSE_MIXED], Fs[dp.DPSE_FP64])
+    out["mixed_vs_fp64_rel_rms_force_by_seed"] = {str(k): v for k, v in errs.items()}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--latency-solves", type=int, default=200,
+                    help="solves of the separate per-solve latency pass (p50/p99)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", choices=["auto", "fp64", "mixed"], default="auto")
+    ap.add_argument("--jump", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 16384-ion jump workload (both precisions, accuracy over seeds 0-4)")
+    ap.add_argument("--small", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 64-charge workload, eager against graph launches")
     ap.add_argument("--batch", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 64-system uneven batch")
     ap.add_argument("--serve", action=argparse.BooleanOptionalAction, default=True,
@@ -484,62 +674,87 @@ def main(argv=None):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    p, pos, q = W.config_jump(a.seed)
+    p, pos, q = W.config_large(a.seed)
     tpos = torch.tensor(pos, dtype=torch.float64, device="cuda")
     tq = torch.tensor(q, dtype=torch.float64, device="cuda")
     n = len(q)
     res = {}
-    for prec in (["fp64", "mixed"] if a.precision == "auto" else [a.precision]):
+    for prec in (["mixed", "fp64"] if a.precision == "auto" else [a.precision]):
+        # the headline path gets the full step count, live stage events and the latency pass
+        head_pass = prec == "mixed" or a.precision == "fp64"
+        steps = a.steps if head_pass else max(3, a.steps // 4)
         res[prec] = time_path(dp, torch, p, tpos, tq, dp.DPSE_FP64 if prec == "fp64" else dp.DPSE_MIXED,
-                              a.steps, a.warmup)
-        print(f"[bench] {prec}: {1e3 * res[prec]['wall_s'] / a.steps:.3f} ms/solve, stages "
+                              steps, a.warmup, live_stages=True,
+                              latency_solves=a.latency_solves if head_pass else steps)
+        res[prec]["steps"] = steps
+        print(f"[bench] large {prec}: {1e3 * res[prec]['wall_s'] / steps:.3f} ms/solve, stages "
               + ", ".join(f"{k}={v:.3f}" for k, v in res[prec]["stages"].items()), file=sys.stderr, flush=True)
     acc = {}
     head = "fp64" if "fp64" in res else "mixed"
     if "fp64" in res and "mixed" in res:
         F64, Fm = res["fp64"]["F"], res["mixed"]["F"]
-        err = float(np.sqrt(np.sum((Fm - F64) ** 2) / np.sum(F64 ** 2)))
+        err = rel_rms(Fm, F64)
         ffar64 = q[:, None] * res["fp64"]["far"][:, 1:]
         ffarm = q[:, None] * res["mixed"]["far"][:, 1:]
-        errfar = float(np.sqrt(np.sum((ffarm - ffar64) ** 2) / np.sum(ffar64 ** 2)))
-        acc = {"mixed_vs_fp64_rel_rms_force": err, "mixed_vs_fp64_rel_rms_far_force": errfar,
-               "mixed_vs_fp64_rel_energy": abs(res["mixed"]["U"] - res["fp64"]["U"]) / abs(res["fp64"]["U"])}
+        acc = {"mixed_vs_fp64_rel_rms_force": err, "mixed_vs_fp64_rel_rms_far_force": rel_rms(ffarm, ffar64),
+               "mixed_vs_fp64_rel_rms_phi": rel_rms(res["mixed"]["phi"], res["fp64"]["phi"]),
+               # U = 1/2 sum q phi cancels strongly over a million charges: its
+               # error is measured against the scale 1/2 sum |q phi| of its terms
+               "mixed_vs_fp64_energy_err_rel_to_sum_abs": abs(res["mixed"]["U"] - res["fp64"]["U"])
+               / (0.5 * float(np.sum(np.abs(q * res["fp64"]["phi"]))))}
         head = "mixed" if err <= 1e-5 else "fp64"
+    elif "mixed" in res:
+        head = "mixed"
     r = res[head]
-    ms = 1e3 * r["wall_s"] / a.steps
-    value = n / (r["wall_s"] / a.steps)
+    steps = r["steps"]
+    ms = 1e3 * r["wall_s"] / steps
+    value = n / (r["wall_s"] / steps)
     s_bytes = 4 if head == "mixed" else 8
-    bfrac = band_fraction(p, r["info"])
-    sb = stage_bytes(p, bfrac, s_bytes)
-    dom = max(sb, key=lambda k: r["stages"][k])
+    beta = band_fraction(p, r["info"])
+    sb = stage_bytes(p, beta, s_bytes)
+    single = ("spread", "column", "interp")   # stages of one kernel each
+    dom = max(single, key=lambda k: r["stages"][k])
     t_dom = r["stages"][dom] * 1e-3
     achieved = sb[dom] / t_dom / 1e9
     dom_kernel = kernel_name(dom, r["tiles"], head == "mixed")
     traffic = profiled_traffic(dom_kernel)
     line = {
         "metric": "charge-force evals/s at <=1e-5 rel RMS force err vs FP64; p50/p99 solve ms",
-        "value": value, "unit": "charge-force evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": value, "unit": "charge-force evals/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "none (one GPU)", "vs_baseline": None,
         "dtype": "f32+f64" if head == "mixed" else "f64", "data": "synthetic",
-        "config": {"workload": "jump: N=16384 +-1 ions, Lx=Ly=64, H=32, eps=1, eps_b=eps_t=0.05, xi=1.0, "
-                               "grid 256x256x129, r_cut=3.0, seed %d" % a.seed,
+        "config": {"workload": "large slab: N=1048576 +-1 ions, Lx=Ly=256, H=64, eps=1, eps_b=0.05, eps_t=20, "
+                               "xi=1.5, grid 1024x1024x257, r_cut=2.0, seed %d" % a.seed,
                    "precision": head, "parallelism": "single GPU"},
         "p50_ms": float(np.percentile(r["lat_ms"], 50)), "p99_ms": float(np.percentile(r["lat_ms"], 99)),
+        "latency_solves": int(len(r["lat_ms"])),
         "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
         "tiles": {"spread": r["tiles"][0], "interp": r["tiles"][1], "column": r["tiles"][2]},
         "accuracy": acc,
         "roofline": {"bound": "hbm", "kernel": dom_kernel or dom, "stage": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "algorithmic_bytes": sb[dom], "traffic": traffic},
+                     "traffic": traffic, "algorithmic_bytes": sb[dom], "beta": beta,
+                     "launch_ms": r["stages"][dom],
+                     "all_stages": {k: {"algorithmic_bytes": v, "ms": r["stages"][k],
+                                        "frac": v / (r["stages"][k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                    for k, v in sb.items()}},
+        "workspace_bytes": r["workspace_bytes"],
     }
     for prec, rr in res.items():
-        line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / a.steps)
+        line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / rr["steps"])
+        line[f"{prec}_ms"] = 1e3 * rr["wall_s"] / rr["steps"]
         line[f"{prec}_p50_ms"] = float(np.percentile(rr["lat_ms"], 50))
         line[f"{prec}_p99_ms"] = float(np.percentile(rr["lat_ms"], 99))
+    del res
+    torch.cuda.empty_cache()
+    if a.jump:
+        line["jump"] = bench_jump(dp, torch, a.steps, a.warmup)
+    if a.small:
+        line["small"] = bench_small(dp, torch, a.steps)
+        print(f"[bench] small: {line['small']}", file=sys.stderr, flush=True)
     if a.uniform:
         line["uniform_eps"] = bench_uniform(dp, torch, a.steps)
         print(f"[bench] uniform eps: {line['uniform_eps']}", file=sys.stderr, flush=True)
-    if a.uniform:
         line["one_jump"] = bench_one_jump(dp, torch, a.steps)
         print(f"[bench] one jump: {line['one_jump']}", file=sys.stderr, flush=True)
     if a.triply:
