@@ -244,11 +244,13 @@ int dpse_solve_graph(dpse_plan* plan, int64_t n, const double* pos, const double
  *   wall terms of the last full solve.
  * Costs the validation, the binning, the near field and the outputs, about a
  * quarter of a full solve. The last full solve must have had the same n and
- * the same charges q in the same order (the caller's contract), and the
- * plan's workspace must not have served another plan since (the far-field
- * averages live there; binding or dpse_plan_set_walls invalidates them).
- * Same arguments, outputs and device errors as dpse_solve; DPSE_EINVAL
- * without a full solve of this n to reuse. */
+ * the same charges q in the same order (the caller's contract). The far-field
+ * averages live in the workspace: the library keeps, per workspace, which
+ * plan's full solve last wrote them (a full solve, a replay of
+ * dpse_solve_graph or a launch of a batch graph holding the plan), and binding
+ * or dpse_plan_set_walls invalidates them. Same arguments, outputs and device
+ * errors as dpse_solve; DPSE_EINVAL without a full solve of this n to reuse,
+ * or when another plan has solved in the workspace (a shared arena) since. */
 int dpse_solve_near(dpse_plan* plan, int64_t n, const double* pos, const double* q,
                     double* energy, double* phi, double* force);
 

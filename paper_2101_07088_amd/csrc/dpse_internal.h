@@ -155,6 +155,10 @@ struct dpse_plan {
   // charges of the last full solve whose far-field averages (far4) and gauge
   // constant (scal[2]) are still in the workspace, for dpse_solve_near; 0 = none
   int64_t far_n = 0;
+  // identity of the plan and number of its full solves: the arena's owner
+  // record (plan.cpp) names the plan and solve whose far field it holds
+  uint64_t uid = 0;
+  uint64_t full_solves = 0;
   hipStream_t stream = nullptr;
   int device = 0;
   int64_t max_n = 0;

@@ -4,11 +4,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "dpse_internal.h"
@@ -18,6 +22,28 @@ using dpse::Geom;
 namespace {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Owner records of the workspaces: for every workspace base (a plan's own
+// workspace or an arena shared by several plans), the plan and full solve
+// whose far field (far4, the gauge constant, the wall partials) it holds.
+// dpse_solve_near reuses that far field only if the record names the
+// calling plan's own last full solve.
+std::atomic<uint64_t> g_next_uid{1};
+std::mutex g_owner_mu;
+std::unordered_map<const void*, std::pair<uint64_t, uint64_t>> g_owner;
+
+void note_full_solve(dpse_plan* p, int64_t n) {
+  p->far_n = n;
+  ++p->full_solves;
+  std::lock_guard<std::mutex> lk(g_owner_mu);
+  g_owner[(const void*)p->w.status] = {p->uid, p->full_solves};
+}
+
+bool owns_far_field(const dpse_plan* p) {
+  std::lock_guard<std::mutex> lk(g_owner_mu);
+  auto it = g_owner.find((const void*)p->w.status);
+  return it != g_owner.end() && it->second.first == p->uid && it->second.second == p->full_solves;
+}
 
 // d/dr of [erf(r/a) - erf(r/b)]/r with a = sqrt2 g_w (a = 0: the term is 1/r)
 // and b = sqrt(2 g_w^2 + xi^-2) (b absent when xi = 0): eq. Gnear without the
@@ -77,8 +103,13 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
   double h = p->Lx / p->Nx, hy = p->Ly / p->Ny;
   if (std::fabs(h - hy) > 1e-12 * h) return DPSE_EINVAL;
   double g_t = std::sqrt(1.0 / (4.0 * p->xi * p->xi) + p->g_w * p->g_w);
+  if (!std::isfinite(g_t) || !(g_t > 0.0)) return DPSE_EINVAL;
   int ng = p->support;
-  if (ng == 0) ng = 2 * (int)std::ceil(4.3 * g_t / h);
+  if (ng == 0) {
+    const double half = std::ceil(4.3 * g_t / h);  // compared before it becomes an int
+    if (!(half <= 0.5 * dpse::kMaxSupport)) return DPSE_EINVAL;
+    ng = 2 * (int)half;
+  }
   if (ng < 2 || (ng & 1) || ng > dpse::kMaxSupport) return DPSE_EINVAL;
   double H_E = ng * h / 2.0;
   double rc = p->r_cut;
@@ -107,6 +138,11 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     za = 0.0;
     zb = p->H - p->H / p->Nz;
   }
+
+  // z buckets of the spreading bins (width H_E / 2 over the span of the
+  // charges and images): bounded so that the bin arrays stay small
+  const double nzb_d = std::ceil((tp ? p->H + 2.0 * H_E : zb - za - 2.0 * H_E) / (0.5 * H_E)) + 1.0;
+  if (!(nzb_d <= 16384.0)) return DPSE_EINVAL;
 
   std::memset(info, 0, sizeof(*info));
   info->h = h;
@@ -153,10 +189,12 @@ int derive_all(const dpse_params* p, dpse_info* info, Geom* g) {
     // the domain's interior)
     g->zb_lo = tp ? -H_E : za + H_E;  // periodic copies reach H_E beyond either end
     g->zb_w = 0.5 * H_E;
-    g->nzb = (int)std::ceil((tp ? p->H + 2.0 * H_E : zb - za - 2.0 * H_E) / g->zb_w) + 1;
-    g->ncx = std::max(1, std::min(1024, (int)std::floor(p->Lx / rc)));
-    g->ncy = std::max(1, std::min(1024, (int)std::floor(p->Ly / rc)));
-    g->ncz = std::max(1, std::min(1024, (int)std::floor(p->H / rc)));
+    g->nzb = (int)nzb_d;
+    // cells per direction, clamped to [1, 1024] before the conversion to int
+    auto cells = [](double len, double c) { return (int)std::fmax(1.0, std::fmin(1024.0, std::floor(len / c))); };
+    g->ncx = cells(p->Lx, rc);
+    g->ncy = cells(p->Ly, rc);
+    g->ncz = cells(p->H, rc);
     g->cwx = p->Lx / g->ncx; g->cwy = p->Ly / g->ncy; g->cwz = p->H / g->ncz;
     // wall bands of psi_o*: the wall group's charges lie in 0 < z < 2 H_E or
     // H - 2 H_E < z < H and reach the nodes within H_E of them, so their
@@ -331,6 +369,7 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
   p->prm = *params;
   p->stream = (hipStream_t)stream;
   p->max_n = max_n;
+  p->uid = g_next_uid.fetch_add(1);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return DPSE_EHIP;
@@ -627,7 +666,8 @@ static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* 
   }
   hipError_t e = p->prm.precision == DPSE_MIXED ? solve_stages<float>(p, n, pos, q, energy, phi, force, ev)
                                                 : solve_stages<double>(p, n, pos, q, energy, phi, force, ev);
-  p->far_n = e == hipSuccess ? n : 0;
+  if (e == hipSuccess) note_full_solve(p, n);
+  else p->far_n = 0;
   return e == hipSuccess ? DPSE_OK : DPSE_EHIP;
 }
 
@@ -635,7 +675,9 @@ int dpse_solve_near(dpse_plan* p, int64_t n, const double* pos, const double* q,
                     double* force) {
   if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
   if (n > p->max_n) return DPSE_ETOOMANY;
-  if (p->far_n != n) return DPSE_EINVAL;  // no full solve of these charges to reuse
+  // a full solve of these charges whose far field the workspace still holds
+  // (no other plan has solved in a shared arena since)
+  if (p->far_n != n || !owns_far_field(p)) return DPSE_EINVAL;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
     if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
@@ -709,12 +751,20 @@ int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q
     p->graph_stream = p->stream;
   }
   p->last_n = n;
-  return hipGraphLaunch(p->graph_exec, p->stream) == hipSuccess ? DPSE_OK : DPSE_EHIP;
+  if (hipGraphLaunch(p->graph_exec, p->stream) != hipSuccess) {
+    p->far_n = 0;
+    return DPSE_EHIP;
+  }
+  note_full_solve(p, n);
+  return DPSE_OK;
 }
 
 struct dpse_graph {
   hipGraphExec_t exec = nullptr;
   int device = 0;
+  // the systems in capture order: a launch makes each plan the owner of its
+  // workspace's far field again (the last system of a shared arena wins)
+  std::vector<std::pair<dpse_plan*, int64_t>> systems;
 };
 
 int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n,
@@ -774,7 +824,10 @@ int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n
     gr = new (std::nothrow) dpse_graph();
     if (!gr) status = DPSE_ENOMEM;
     else if (hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0) != hipSuccess) status = DPSE_EHIP;
-    if (gr) gr->device = plans[0]->device;
+    if (gr) {
+      gr->device = plans[0]->device;
+      for (int i = 0; i < n_sys; ++i) gr->systems.emplace_back(plans[i], n[i]);
+    }
   }
   if (graph) (void)hipGraphDestroy(graph);
   for (int b = 0; b <= n_branches; ++b) {
@@ -792,7 +845,9 @@ int dpse_batch_graph_create(int n_sys, dpse_plan* const* plans, const int64_t* n
 
 int dpse_graph_launch(dpse_graph* g, void* stream) {
   if (!g || !g->exec) return DPSE_EINVAL;
-  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? DPSE_OK : DPSE_EHIP;
+  if (hipGraphLaunch(g->exec, (hipStream_t)stream) != hipSuccess) return DPSE_EHIP;
+  for (auto& s : g->systems) note_full_solve(s.first, s.second);
+  return DPSE_OK;
 }
 
 int dpse_graph_destroy(dpse_graph* g) {
@@ -1025,6 +1080,10 @@ const char* dpse_stage_name(int stage) {
 int dpse_plan_destroy(dpse_plan* p) {
   if (!p) return DPSE_EINVAL;
   (void)hipStreamSynchronize(p->stream);
+  if (p->owns_workspace) {  // its workspace is freed below: forget its owner record
+    std::lock_guard<std::mutex> lk(g_owner_mu);
+    g_owner.erase((const void*)p->w.status);
+  }
   for (hipEvent_t e : p->events) (void)hipEventDestroy(e);
   p->events.clear();
   free_all(p);
