@@ -118,10 +118,20 @@ def test_gaussian_charges_closer_than_the_taylor_switch():
     plan, st, U, phi, F = run(p, pos, q)
     assert st == 0
     near = plan.debug(dp.Stage.NEAR)[: len(q)]
-    en = float(np.max(np.abs(near - inter["near"])) / np.max(np.abs(inter["near"])))
+    scale = np.max(np.abs(inter["near"]))
+    # Just above the switch (the pair at 6e-5, charges 4 and 5) both sides
+    # evaluate the kernel's closed form, whose field -G'(r)/r is a difference
+    # of terms of size (2/sqrt(pi)) a / r^2 ~ 3e9 that leaves ~7.5e2: about
+    # 4e6 ulp of cancellation, so the two FP64 evaluations agree there only
+    # to ~1e-9 of the pair's field. Every other charge keeps the 1e-12 bar.
+    err = np.max(np.abs(near - inter["near"]), axis=1) / scale
+    en = float(np.max(np.delete(err, [4, 5])))
+    en_sw = float(np.max(err[[4, 5]]))
     eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
-    print(f"[case] close Gaussian pairs: near {en:.2e} relRMS F {eF:.2e} phi {ep:.2e}", flush=True)
+    print(f"[case] close Gaussian pairs: near {en:.2e} (above the switch {en_sw:.2e}) relRMS F {eF:.2e} "
+          f"phi {ep:.2e}", flush=True)
     assert en < 1e-12
+    assert en_sw < 1e-10
     assert eF < 1e-9 and ep < 1e-9
     assert abs(U - U0) < 1e-9 * 0.5 * np.sum(np.abs(q * phi0))
 
