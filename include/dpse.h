@@ -61,7 +61,8 @@ enum {
   DPSE_ENONNEUTRAL = 4, /* |sum q + int sigma| > 1e-12 (sum |q| + int |sigma|)  (device-detected) */
   DPSE_EOUTSIDE = 5,    /* a charge with z outside (n_sigma g_w, H - n_sigma g_w), or a non-finite coordinate (device-detected) */
   DPSE_ECONSTRAINT = 6, /* r_cut >= H + h_min or 2 H_E >= H + h_min, h_min the smallest distance of a charge to a wall (Sec. 4.2, 5.3; device-detected) */
-  DPSE_ETOOMANY = 7     /* n larger than the plan's max_n                        */
+  DPSE_ETOOMANY = 7,    /* n larger than the plan's max_n                        */
+  DPSE_ESCRATCH = 8     /* the plan's workspace exceeds the static scratch buffer of dpse_solve_static */
 };
 
 /* Precision of the grid stages. */
@@ -233,6 +234,32 @@ int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q,
  * arguments, results and errors as dpse_solve. */
 int dpse_solve_graph(dpse_plan* plan, int64_t n, const double* pos, const double* q,
                      double* energy, double* phi, double* force);
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The solve of
+ * dpse_solve (same arguments, results and device errors) with its workspace
+ * in a static device array of the library, 64 MiB per device, held from the
+ * library's first use on that device until the process ends. The call
+ * allocates nothing (no hipMalloc, hipFree, event or stream creation) and
+ * enqueues its kernels on `stream` (a hipStream_t; NULL = the null stream).
+ *   plan   from dpse_plan_create_unbound (its tables were allocated when it
+ *          was created); it stays bound to the static array and `stream`
+ *          after the call (dpse_sync, dpse_solve_near and dpse_debug_copy then
+ *          read the array; dpse_plan_bind moves it elsewhere);
+ *   n, pos, q, energy, phi, force  as for dpse_solve; per-stage timing is
+ *          not recorded.
+ * Every call on a device shares that device's array, whose contents stay
+ * from the last call: the call clears the status word with a kernel and every
+ * other buffer is rewritten by the solve's own kernels. Calls that overlap on
+ * one device (other streams, other threads, other plans) race on the array;
+ * the caller orders them. DPSE_ESCRATCH when dpse_info.workspace_bytes
+ * exceeds 64 MiB (about 52 bytes per grid point in DPSE_MIXED, 104 in
+ * DPSE_FP64, plus about 300 per charge of max_n: the 32 x 32 x 33 grid with
+ * 64 charges takes 3.5 MiB in FP64, a 128 x 128 x 65 grid with 3.5 * 10^4
+ * charges 63.9 MiB in DPSE_MIXED), DPSE_EINVAL for a plan that
+ * owns its workspace or bad arguments, DPSE_ETOOMANY. */
+int dpse_solve_static(dpse_plan* plan, void* stream, int64_t n, const double* pos, const double* q,
+                      double* energy, double* phi, double* force);
 
 /* Reuse of the far field between time steps (the paper's closing remark on
  * reusing far-field work between Brownian-dynamics steps, Sec. 8): the near

@@ -39,6 +39,35 @@ void note_full_solve(dpse_plan* p, int64_t n) {
   g_owner[(const void*)p->w.status] = {p->uid, p->full_solves};
 }
 
+// Static device scratch of dpse_solve_static: the workspace of callers that
+// cannot allocate. Each device holds its own copy of the array from the
+// first load of the library's code on it until the process ends; host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in), only the device address looked up once per device.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+std::unordered_map<int, void*> g_scratch;
+
+// Looks up this device's address of the scratch array (the device must be
+// current); once per device.
+hipError_t scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch.count(device)) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (ptr == nullptr) return hipErrorInvalidSymbol;
+  g_scratch[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch.find(device);
+  return it == g_scratch.end() ? nullptr : it->second;
+}
+
 bool owns_far_field(const dpse_plan* p) {
   std::lock_guard<std::mutex> lk(g_owner_mu);
   auto it = g_owner.find((const void*)p->w.status);
@@ -345,6 +374,7 @@ const char* dpse_status_string(int s) {
     case DPSE_EOUTSIDE: return "charge outside the slab or non-finite coordinate";
     case DPSE_ECONSTRAINT: return "near-field or far-field image constraint violated (Sec. 5.3)";
     case DPSE_ETOOMANY: return "more charges than the plan's max_n";
+    case DPSE_ESCRATCH: return "the plan's workspace is larger than the static scratch buffer (64 MiB)";
     default: return "unknown status";
   }
 }
@@ -505,6 +535,7 @@ static int plan_create(const dpse_params* params, int64_t max_n, void* stream, d
   int zero4[4] = {0, 0, 0, 0};
   if (p->bound) H2D(w.status, zero4, sizeof(zero4));
   if (e == hipSuccess) e = dpse::prepare_kernels();
+  if (e == hipSuccess) e = scratch_init(p->device);  // set-up of dpse_solve_static on this device
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&p->join_ev, hipEventDisableTiming);
@@ -645,7 +676,7 @@ static hipError_t solve_near_stages(dpse_plan* p, int64_t n, const double* pos, 
 extern "C" {
 
 static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* q,
-                      double* energy, double* phi, double* force) {
+                      double* energy, double* phi, double* force, bool allow_timing = true) {
   if (!p || !pos || !q || n <= 0 || !p->bound) return DPSE_EINVAL;
   if (n > p->max_n) return DPSE_ETOOMANY;
   int dev = 0;
@@ -654,7 +685,7 @@ static int solve_impl(dpse_plan* p, int64_t n, const double* pos, const double* 
   }
   p->last_n = n;
   hipEvent_t* ev = nullptr;
-  if (p->timing) {
+  if (p->timing && allow_timing) {
     size_t need = (size_t)(p->timed_solves + 1) * (2 * DPSE_NUM_STAGES);
     while (p->events.size() < need) {
       hipEvent_t e;
@@ -702,6 +733,31 @@ int dpse_bd_step(dpse_plan* p, int64_t n, const double* pos, const double* force
 int dpse_solve(dpse_plan* plan, int64_t n, const double* pos, const double* q, double* energy,
                double* phi, double* force) {
   return solve_impl(plan, n, pos, q, energy, phi, force);
+}
+
+int dpse_solve_static(dpse_plan* p, void* stream, int64_t n, const double* pos, const double* q,
+                      double* energy, double* phi, double* force) {
+  if (!p || !pos || !q || n <= 0) return DPSE_EINVAL;
+  if (p->owns_workspace) return DPSE_EINVAL;  // created by dpse_plan_create
+  if (n > p->max_n) return DPSE_ETOOMANY;
+  if (p->info.workspace_bytes > (int64_t)kScratchBytes) return DPSE_ESCRATCH;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device) {
+    if (hipSetDevice(p->device) != hipSuccess) return DPSE_EHIP;
+  }
+  void* base = scratch_ptr(p->device);  // looked up when the plan was created
+  if (base == nullptr) return DPSE_EHIP;
+  carve_workspace(p, (char*)base);
+  p->stream = (hipStream_t)stream;
+  p->bound = true;
+  // the array keeps the last call's contents: the status word starts at zero
+  // (a fill kernel, no memset node under capture); every other buffer a
+  // solve reads is cleared or written by its own kernels first
+  if (dpse::fill_int(p->w.status, 0, 4, p->stream) != hipSuccess) {
+    p->far_n = 0;
+    return DPSE_EHIP;
+  }
+  return solve_impl(p, n, pos, q, energy, phi, force, false);
 }
 
 int dpse_solve_graph(dpse_plan* p, int64_t n, const double* pos, const double* q, double* energy,

@@ -22,8 +22,10 @@ DPSE_DETERMINISTIC = 32
 
 _STATUS = {
     0: "DPSE_OK", 1: "DPSE_EINVAL", 2: "DPSE_ENOMEM", 3: "DPSE_EHIP", 4: "DPSE_ENONNEUTRAL",
-    5: "DPSE_EOUTSIDE", 6: "DPSE_ECONSTRAINT", 7: "DPSE_ETOOMANY",
+    5: "DPSE_EOUTSIDE", 6: "DPSE_ECONSTRAINT", 7: "DPSE_ETOOMANY", 8: "DPSE_ESCRATCH",
 }
+DPSE_ESCRATCH = 8
+STATIC_SCRATCH_BYTES = 64 << 20   # the static workspace array of dpse_solve_static, per device
 
 
 class Stage(enum.IntEnum):
@@ -93,6 +95,7 @@ def _lib():
         L.dpse_plan_create_unbound.argtypes = [ctypes.POINTER(_Params), i64, ctypes.POINTER(vp)]
         L.dpse_plan_bind.argtypes = [vp, vp, i64, vp]
         L.dpse_solve_graph.argtypes = [vp, i64, pd, pd, pd, pd, pd]
+        L.dpse_solve_static.argtypes = [vp, vp, i64, pd, pd, pd, pd, pd]
         L.dpse_batch_graph_create.argtypes = [ctypes.c_int, ctypes.POINTER(vp), ctypes.POINTER(i64),
                                               ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                               ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
@@ -118,7 +121,7 @@ def _lib():
                      "dpse_stage_times", "dpse_workspace_size", "dpse_plan_create_unbound", "dpse_plan_bind",
                      "dpse_solve_graph", "dpse_batch_graph_create", "dpse_graph_launch", "dpse_graph_destroy",
                      "dpse_plan_autotune", "dpse_plan_set_tiles", "dpse_plan_set_walls", "dpse_solve_near",
-                     "dpse_bd_step"):
+                     "dpse_bd_step", "dpse_solve_static"):
             getattr(L, name).restype = ctypes.c_int
         _LIB = L
     return _LIB
@@ -316,6 +319,25 @@ class Plan:
         check_outputs(torch, n, self.device, energy, phi, force)
         _check(_lib().dpse_solve_graph(self._h, n, pos.data_ptr(), q.data_ptr(), energy.data_ptr(),
                                        phi.data_ptr(), force.data_ptr()), "dpse_solve_graph")
+        return energy, phi, force
+
+    def solve_static(self, pos, q, energy, phi, force, stream=None):
+        """dpse_solve_static: the solve with its workspace in the library's
+        static device array (no allocation in the call). The plan must have
+        been made with own_workspace=False; it stays bound to that array and
+        to `stream` (default: the current stream). Outputs must be given."""
+        torch = self._torch
+        n = check_charges(torch, pos, q, self.device)
+        if energy is None or phi is None or force is None:
+            raise ValueError("solve_static needs all three outputs (it allocates nothing)")
+        check_outputs(torch, n, self.device, energy, phi, force)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(_lib().dpse_solve_static(self._h, ctypes.c_void_p(stream.cuda_stream), n, pos.data_ptr(),
+                                        q.data_ptr(), energy.data_ptr(), phi.data_ptr(), force.data_ptr()),
+               "dpse_solve_static")
+        self.workspace = None
+        self.stream = stream
         return energy, phi, force
 
     def autotune(self, pos, q, reps: int = 3):

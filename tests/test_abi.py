@@ -113,3 +113,9 @@ def test_triply_flag_validation():
                 p.copy(one_jump=True), p.copy(H=5.5, r_cut=3.0)):
         with pytest.raises(dp.DpseError):
             dp.derive(bad)
+
+
+def test_solve_static_rejects_a_null_plan():
+    """dpse_solve_static validates its plan on the host (no GPU needed)."""
+    from paper_2101_07088_amd.native import _lib
+    assert _lib().dpse_solve_static(None, None, 1, None, None, None, None, None) == 1
