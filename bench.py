@@ -51,7 +51,7 @@ def stage_bytes(p, beta, s):
 
 SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4)]
 INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4)]
-COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512)]  # (KE, threads)
+COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512), (2048, 256)]  # (KE, threads)
 
 
 def kernel_name(stage, tiles, mixed):
@@ -68,6 +68,8 @@ def kernel_name(stage, tiles, mixed):
         # the gather shapes carry the wall-term switch (off on this workload)
         return f"k_interp_gather<{r},{t},{pz},false>" if i >= 5 else f"k_interp<{r},{t},{pz}>"
     if stage == "column":
+        if tiles[2] == 5:   # the segmented-scan kernel of the grids with Nz <= 257
+            return f"k_column_scan<{r}>"
         ke, nt = COLUMN_SHAPES[tiles[2]]
         return f"k_column<{r},{ke},{nt}>"
     return None

@@ -34,9 +34,11 @@ namespace {
 constexpr int kThreads = 256;
 // KE (a template parameter) = complex elements per LDS buffer = modes per
 // block x 2(Nz-1); one of kColumnKE, chosen per grid by the autotuner.
-constexpr int kColumnKE[] = {2048, 1024, 4096, 2048, 4096};
-constexpr int kColumnNT[] = {256, 256, 256, 512, 512};  // threads per workgroup
-constexpr int kNumColumn = 5;
+// Candidates 0-4: k_column (Nz > 257); candidate 5: k_column_scan (Nz <= 257).
+constexpr int kColumnKE[] = {2048, 1024, 4096, 2048, 4096, 2048};
+constexpr int kColumnNT[] = {256, 256, 256, 512, 512, 256};  // threads per workgroup
+constexpr int kNumColumn = 6;
+constexpr int kScanCand = 5;
 constexpr int kMaxMB = 32;    // modes per block (16 MB chain threads <= the block's threads)
 // dynamic LDS per block: 160 KB per workgroup less a margin for the static
 // arrays of the kernel (under 3 KB)
@@ -714,6 +716,504 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Column solve for Nz <= 257 with every phase spread over all lanes. Same
+// mathematics as k_column (Sec. 5.2.2 steps 2-6, App. A); what differs is the
+// work split:
+//  * the z transforms run in the storage precision (FP32 in the mixed path,
+//    where the Chebyshev transform is one of the FFTs; FP64 otherwise);
+//  * the chains are solved with the plan's LU factors (inverse pivots per
+//    mode, mode-major) by a segmented scan: lane (mode, parity, segment)
+//    owns about four consecutive rows of one chain for all five right-hand
+//    sides (Re/Im of psi_i*, Re/Im of psi_o*, the unit free constant), sweeps
+//    them with carry 0 while forming the product of the multipliers, and the
+//    carries of the segments come from an inclusive scan of those affine maps
+//    over the lanes of the chain (wave shuffles); back substitution likewise,
+//    from the top segment down;
+//  * the linear functionals are partial dot products over each lane's rows,
+//    summed over the segments by shuffles;
+//  * the final series, its exact derivative (a suffix sum over the other
+//    parity, again a segmented scan) and the even extension for the inverse
+//    transform are formed in the same lanes and written straight to LDS.
+// KE = 2048 complex elements per transform buffer, 256 threads: MB = KE / M
+// modes per block (M = 2(Nz - 1)), S = M / 16 segments per chain, 2 S MB =
+// 256 lanes; 4 <= MB <= 32 for 33 <= Nz <= 257.
+constexpr int kScanKE = 2048;
+constexpr int kScanNT = 256;
+constexpr int kScanRows = 5;   // rows per lane: ceil(L / S) <= ceil(4 (Nz + 1) / (Nz - 1)) = 5
+constexpr int kNumFunBC = 8;   // S1..S4, V0, VH, D0, DH (Ea, Eb only for k = 0)
+
+// Plan-time LU factorisation of the chains of k_column_scan: for each mode
+// and parity, the inverse pivots 1 / (dia_r - sub_r c_{r-1}) with c_r = sup_r
+// times the inverse pivot, at cinv[mode * Nz + parity * ceil(Nz/2) + r].
+__global__ void __launch_bounds__(kThreads) k_pivots_scan(Geom g, const double* __restrict__ ctab,
+                                                          double* __restrict__ cinv) {
+  const int nmodes = g.Ny * g.nkx, N = g.Nz;
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t >= 2 * nmodes) return;
+  const int mi = t >> 1, par = t & 1;
+  double kk;
+  int keep;
+  mode_wave(g, mi, kk, keep);
+  const double kap = kk * g.zR, kap2 = kap * kap;
+  const int half0 = (N + 1) / 2, L = par == 0 ? half0 : N / 2;
+  double* out = cinv + (size_t)mi * N + par * half0;
+  double cp = 0.0;
+  for (int r = 0; r < L; ++r) {
+    const int n = par + 2 * r;
+    const double sub = -kap2 * ctab[n], dia = fma(kap2, ctab[N + n], 1.0), sup = -kap2 * ctab[2 * N + n];
+    const double inv = rcp_refined(fma(-sub, cp, dia));
+    out[r] = inv;
+    cp = sup * inv;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename CT<R>::T* __restrict__ fx_i,
+                                                         const typename CT<R>::T* __restrict__ fx_o,
+                                                         typename CT<R>::T* __restrict__ psi,
+                                                         typename CT<R>::T* __restrict__ psiz,
+                                                         const double* __restrict__ zn,
+                                                         const double* __restrict__ ctab,
+                                                         const double2* __restrict__ twz,
+                                                         const double* __restrict__ cinv, double* scal,
+                                                         const double2* __restrict__ wall_hat) {
+  using C = typename CT<R>::T;
+  constexpr int KE = kScanKE, NT = kScanNT, RW = kScanRows;
+  extern __shared__ double2 smem2[];
+  C* A = reinterpret_cast<C*>(smem2);  // F_o, later the series of psi_i*
+  C* B = A + KE;                       // F_i, later the derivative series
+  C* tw = B + KE;                      // twiddles exp(-2 pi i k / M), k < M/2
+  const int N = g.Nz, M = 2 * (N - 1), logM = ilog2d(M);
+  const int MB = KE / M, logMB = ilog2d(KE) - logM;
+  // reduced functionals [mode][parity][f][rhs] after the tables above
+  double* sfun = reinterpret_cast<double*>(tw + M / 2);
+  __shared__ double s_k[kMaxMB], s_kap[kMaxMB];
+  __shared__ int s_keep[kMaxMB];
+  __shared__ double2 s_c[kMaxMB][2];   // free constants (y_0, y'_0) of psi_i*
+  __shared__ double2 s_ab[kMaxMB][2];  // correction alpha, beta
+  __shared__ double s_Ai[kMaxMB];
+  __shared__ double s_e[2][2][5];      // Ea, Eb of the k = 0 mode per parity and right-hand side
+
+  const int NU = N + 2;
+  const int nmodes = g.Ny * g.nkx;
+  const int m0 = xcd_block(blockIdx.x, gridDim.x) * MB;
+  const int tid = threadIdx.x;
+  const double* W = ctab + kCtabRows * N;
+  if (tid < MB) {
+    const int mi = m0 + tid;
+    double kk = 0.0;
+    int keep = 0;
+    if (mi < nmodes) mode_wave(g, mi, kk, keep);
+    s_k[tid] = kk;
+    s_kap[tid] = kk * g.zR;
+    s_keep[tid] = keep;
+  }
+  for (int i = tid; i < M / 2; i += NT) {
+    const double2 w = twz[i];
+    C c;
+    c.x = (R)w.x;
+    c.y = (R)w.y;
+    tw[i] = c;
+  }
+
+  // 1. even extension of the node values in bit-reversed order (slot p takes
+  //    node bitrev(p)), all global loads first, then the forward transforms
+  {
+    constexpr int kPer = KE / NT;
+    C va[kPer], vb[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = tid + q * NT;
+      const int j = bitrev(t >> logMB, logM), m = t & (MB - 1), mi = m0 + m;
+      const int c = j < N ? j : M - j;
+      va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
+      if (mi < nmodes) {
+        const size_t o = (size_t)c * nmodes + mi;
+        va[q] = fx_i[o];
+        if (in_band(g, c)) vb[q] = fx_o[o];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      A[tid + q * NT] = vb[q];
+      B[tid + q * NT] = va[q];
+    }
+  }
+  __syncthreads();
+  fft_lds_r22_pair<C, true, KE / 4 / NT, NT>(A, B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+
+  // 2. the chains. Lane (m, par, seg): rows r0 .. r0 + cnt - 1 of chain par
+  //    (unknowns y''_n, n = par + 2r) of mode m.
+  const int logS = logM - 4, S = 1 << logS;
+  const int seg = tid & (S - 1), par = (tid >> logS) & 1, m = tid >> (logS + 1);
+  const int half0 = (N + 1) / 2, L = par ? N / 2 : half0;
+  const int r0 = (seg * L) >> logS, cnt = (((seg + 1) * L) >> logS) - r0;
+  const int mi = m0 + m;
+  const bool live = mi < nmodes;
+  const double kap2 = s_kap[m] * s_kap[m];
+  double X[RW][5];   // per row: Re psi_i*, Im psi_i*, Re psi_o*, Im psi_o*, homogeneous
+  double gam[RW], PP[RW];
+  {
+    // forward elimination with carry 0: d_r = inv_r rhs_r + al_r d_{r-1},
+    // al_r = kappa^2 a_n inv_r; PP holds the running product of the al
+    double d[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, P = 1.0;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      gam[q] = 0.0;
+      if (q < cnt) {
+        const int r = r0 + q, n = par + 2 * r;
+        const double inv = live ? cinv[(size_t)mi * N + par * half0 + r] : 0.0;
+        const double al = kap2 * ctab[n] * inv;
+        gam[q] = kap2 * ctab[2 * N + n] * inv;  // back substitution: x_r = d_r + gam_r x_{r+1}
+        const double gs = ctab[3 * N + n];
+        const C fo = A[n * MB + m], fi = B[n * MB + m];
+        const double rhs[5] = {gs * (double)fi.x, gs * (double)fi.y, gs * (double)fo.x, gs * (double)fo.y,
+                               r == 0 ? kap2 : 0.0};
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d[k] = fma(al, d[k], inv * rhs[k]);
+        P *= al;
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k) X[q][k] = d[k];
+      PP[q] = P;
+    }
+    // the segment maps d_end = P d_in + d composed over the segments below
+    double Ps = P, Ds[5] = {d[0], d[1], d[2], d[3], d[4]};
+    for (int o = 1; o < S; o <<= 1) {
+      const double pp = __shfl_up(Ps, o, S);
+      double dp[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) dp[k] = __shfl_up(Ds[k], o, S);
+      if (seg >= o) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Ds[k] = fma(Ps, dp[k], Ds[k]);
+        Ps *= pp;
+      }
+    }
+    double din[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      din[k] = __shfl_up(Ds[k], 1, S);
+      if (seg == 0) din[k] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+      if (q < cnt) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) X[q][k] = fma(PP[q], din[k], X[q][k]);
+      }
+  }
+  {
+    // back substitution with carry 0 from the top of the segment, then the
+    // carries x_in (the first unknown of the segment above) by a reverse scan
+    double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, Q = 1.0;
+#pragma unroll
+    for (int q = RW - 1; q >= 0; --q) {
+      if (q < cnt) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          x[k] = fma(gam[q], x[k], X[q][k]);
+          X[q][k] = x[k];
+        }
+        Q *= gam[q];
+        PP[q] = Q;
+      }
+    }
+    double Qs = Q, Xs[5] = {x[0], x[1], x[2], x[3], x[4]};
+    for (int o = 1; o < S; o <<= 1) {
+      const double qn = __shfl_down(Qs, o, S);
+      double xn[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) xn[k] = __shfl_down(Xs[k], o, S);
+      if (seg + o < S) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Xs[k] = fma(Qs, xn[k], Xs[k]);
+        Qs *= qn;
+      }
+    }
+    double xin[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      xin[k] = __shfl_down(Xs[k], 1, S);
+      if (seg == S - 1) xin[k] = 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+      if (q < cnt) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) X[q][k] = fma(PP[q], xin[k], X[q][k]);
+      }
+  }
+
+  // 3. linear functionals (dot products of y'' and the free constants with
+  //    the plan's weight vectors) summed over the lane's rows, then over the
+  //    segments; the homogeneous solution of the even chain has y_0 = 1, that
+  //    of the odd chain y'_0 = 1
+  auto functionals = [&](int f0, int nf, double* dst, int dst_stride) {
+    double acc[4][5];
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int k = 0; k < 5; ++k) acc[f][k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+      if (q < cnt) {
+        const int n = par + 2 * (r0 + q);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          if (f < nf) {
+            const double w = W[(f0 + f) * NU + n];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) acc[f][k] = fma(w, X[q][k], acc[f][k]);
+          }
+        }
+      }
+    if (seg == 0) {
+#pragma unroll
+      for (int f = 0; f < 4; ++f)
+        if (f < nf) acc[f][4] += W[(f0 + f) * NU + N + par];
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      if (f < nf) {
+        for (int o = S >> 1; o > 0; o >>= 1) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) acc[f][k] += __shfl_xor(acc[f][k], o, S);
+        }
+        if (seg == 0) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) dst[f * dst_stride + k] = acc[f][k];
+        }
+      }
+    }
+  };
+  double* my_fun = sfun + (m * 2 + par) * kNumFunBC * 5;
+  functionals(0, 4, my_fun, 5);
+  functionals(4, 4, my_fun + 4 * 5, 5);
+  if (mi == 0) functionals(FUN_EA, 2, &s_e[par][0][0], 5);
+  __syncthreads();
+
+  // 4. per mode: free constants, wall values, mismatches, harmonic correction, k = 0
+  if (tid < MB) {
+    const int mm = tid;
+    const double* fe = sfun + (mm * 2 + 0) * kNumFunBC * 5;
+    const double* fo_ = sfun + (mm * 2 + 1) * kNumFunBC * 5;
+    // functional f of vector v: 0..3 the particular solutions (Re/Im psi_i*,
+    // Re/Im psi_o*), 4 the homogeneous solution of y_0 (even chain), 5 of y'_0 (odd)
+    auto F = [&](int f, int v) -> double {
+      if (f >= kNumFunBC) {
+        const double* e0 = &s_e[0][f - kNumFunBC][0];
+        const double* e1 = &s_e[1][f - kNumFunBC][0];
+        return v < 4 ? e0[v] + e1[v] : (v == 4 ? e0[4] : e1[4]);
+      }
+      return v < 4 ? fe[f * 5 + v] + fo_[f * 5 + v] : (v == 4 ? fe[f * 5 + 4] : fo_[f * 5 + 4]);
+    };
+    const double kap = s_kap[mm];
+    const bool dir = !(s_k[mm] > 0.0);
+    // boundary rows: Robin top S1 + kap S2, bottom S3 - kap S4; Dirichlet S2, S4
+    auto top = [&](int v) { return dir ? F(FUN_S2, v) : fma(kap, F(FUN_S2, v), F(FUN_S1, v)); };
+    auto bot = [&](int v) { return dir ? F(FUN_S4, v) : fma(-kap, F(FUN_S4, v), F(FUN_S3, v)); };
+    const double t1 = top(4), t2 = top(5), b1 = bot(4), b2 = bot(5);
+    const double idet = 1.0 / (t1 * b2 - t2 * b1);
+    auto solve2 = [&](double tP, double bP, double& c0, double& c1) {
+      c0 = -(tP * b2 - t2 * bP) * idet;
+      c1 = -(t1 * bP - tP * b1) * idet;
+    };
+    double ci0r, ci1r, ci0i, ci1i, co0r, co1r, co0i, co1i;
+    solve2(top(0), bot(0), ci0r, ci1r);
+    solve2(top(1), bot(1), ci0i, ci1i);
+    solve2(top(2), bot(2), co0r, co1r);
+    solve2(top(3), bot(3), co0i, co1i);
+    s_c[mm][0] = make_double2(ci0r, ci0i);
+    s_c[mm][1] = make_double2(ci1r, ci1i);
+    auto fin_i = [&](int f) {
+      return make_double2(F(f, 0) + ci0r * F(f, 4) + ci1r * F(f, 5), F(f, 1) + ci0i * F(f, 4) + ci1i * F(f, 5));
+    };
+    auto fin_o = [&](int f) {
+      return make_double2(F(f, 2) + co0r * F(f, 4) + co1r * F(f, 5), F(f, 3) + co0i * F(f, 4) + co1i * F(f, 5));
+    };
+    const double2 vi0 = fin_i(FUN_V0), viH = fin_i(FUN_VH), di0 = fin_i(FUN_D0), diH = fin_i(FUN_DH);
+    const double2 vo0 = fin_o(FUN_V0), voH = fin_o(FUN_VH), do0 = fin_o(FUN_D0), doH = fin_o(FUN_DH);
+    const double k = s_k[mm];
+    double2 al = make_double2(0, 0), be = make_double2(0, 0);
+    double Ai = 0.0;
+    if (k > 0.0 && s_keep[mm]) {
+      const double e = g.eps, eb = g.eps_b, et = g.eps_t, tb = g.tau_b, tt = g.tau_t;
+      // mismatches (eqs. mm1-mm4)
+      double2 mpb = make_double2(vi0.x - tb * vo0.x, vi0.y - tb * vo0.y);
+      double2 meb = make_double2(e * di0.x - eb * tb * do0.x, e * di0.y - eb * tb * do0.y);
+      double2 mpt = make_double2(viH.x - tt * voH.x, viH.y - tt * voH.y);
+      double2 met = make_double2(e * diH.x - et * tt * doH.x, e * diH.y - et * tt * doH.y);
+      if (wall_hat) {  // wall charges: + sigma_b in mm2, - sigma_t in mm4
+        const double2 sb = wall_hat[m0 + mm], st = wall_hat[nmodes + m0 + mm];
+        meb.x += sb.x;
+        meb.y += sb.y;
+        met.x -= st.x;
+        met.y -= st.y;
+      }
+      const double ik = 1.0 / k;
+      const double2 Rb = make_double2((eb * k * mpb.x - meb.x) * ik, (eb * k * mpb.y - meb.y) * ik);
+      const double2 Rt = make_double2(-(met.x + et * k * mpt.x) * ik, -(met.y + et * k * mpt.y) * ik);
+      const double E = exp(-k * g.H);
+      const double iD = 1.0 / ((e + eb) * (e + et) - (eb - e) * (et - e) * E * E);
+      al = make_double2((Rb.x * (et - e) * E + (e + eb) * Rt.x) * iD, (Rb.y * (et - e) * E + (e + eb) * Rt.y) * iD);
+      be = make_double2(((e - eb) * E * Rt.x - (e + et) * Rb.x) * iD, ((e - eb) * E * Rt.y - (e + et) * Rb.y) * iD);
+    }
+    if (m0 + mm == 0) {
+      if (g.flags & DPSE_UNIFORM_FAST) {
+        // free space (Sec. 3.1.1): A_i cancels psi_i*' at both domain ends
+        Ai = -0.5 * (fin_i(FUN_EA).x + fin_i(FUN_EB).x);
+      } else {
+        const double e = g.eps, tb = g.tau_b, tt = g.tau_t;
+        const double2 ea = fin_o(FUN_EA), ebd = fin_o(FUN_EB);
+        const double Ab = -tb * ea.x, At = -tt * ebd.x;
+        double A1 = (g.eps_b * (tb * do0.x + Ab) - e * di0.x) / e;
+        double A2 = (g.eps_t * (tt * doH.x + At) - e * diH.x) / e;
+        if (wall_hat) {  // wall charges in eqs. ai1, ai2
+          A1 -= wall_hat[0].x / e;
+          A2 += wall_hat[nmodes].x / e;
+        }
+        Ai = 0.5 * (A1 + A2);
+      }
+      scal[3] = Ai;
+    }
+    s_ab[mm][0] = al;
+    s_ab[mm][1] = be;
+    s_Ai[mm] = Ai;
+  }
+  __syncthreads();
+
+  // 5. final series of psi_i* (y = particular + y_0 h, y'_0 h by chain
+  //    parity): y_n = a_n x_{n-2} - b_n x_n + c_n x_{n+2}, plus the free
+  //    constant itself at n = 0, 1; its exact derivative d_j = sum over m > j,
+  //    m = j + 1 mod 2, of 2 m y_m (scaled by 1/R, d_0 halved) is a suffix sum
+  //    over this lane's chain, which gives d_{n-1} at each of the lane's rows;
+  //    both go to the transform buffers as even extensions (factor 2 at the
+  //    ends), in bit-reversed slots
+  {
+    const double2 cf = s_c[m][par];
+    double xr[RW], xi[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      xr[q] = fma(cf.x, X[q][4], X[q][0]);
+      xi[q] = fma(cf.y, X[q][4], X[q][1]);
+    }
+    double lr = xr[0], li = xi[0];
+#pragma unroll
+    for (int q = 1; q < RW; ++q)
+      if (q == cnt - 1) {
+        lr = xr[q];
+        li = xi[q];
+      }
+    double pr = __shfl_up(lr, 1, S), pi = __shfl_up(li, 1, S);
+    double nr = __shfl_down(xr[0], 1, S), ni = __shfl_down(xi[0], 1, S);
+    if (seg == 0) pr = pi = 0.0;
+    if (seg == S - 1) nr = ni = 0.0;
+    double yr[RW], yi[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+      yr[q] = 0.0;
+      yi[q] = 0.0;
+      if (q < cnt) {
+        const int n = par + 2 * (r0 + q);
+        const double xmr = q == 0 ? pr : xr[q > 0 ? q - 1 : 0], xmi = q == 0 ? pi : xi[q > 0 ? q - 1 : 0];
+        const double xpr = q + 1 < cnt ? xr[q + 1 < RW ? q + 1 : RW - 1] : nr;
+        const double xpi = q + 1 < cnt ? xi[q + 1 < RW ? q + 1 : RW - 1] : ni;
+        const double a = ctab[n], b = ctab[N + n], c = ctab[2 * N + n];
+        yr[q] = fma(a, xmr, fma(-b, xr[q], c * xpr));
+        yi[q] = fma(a, xmi, fma(-b, xi[q], c * xpi));
+        if (n <= 1) {
+          yr[q] += cf.x;
+          yi[q] += cf.y;
+        }
+      }
+    }
+    // suffix sums of 2 n y_n inside the segment, then over the segments above
+    double sr = 0.0, si = 0.0, sufr[RW], sufi[RW];
+#pragma unroll
+    for (int q = RW - 1; q >= 0; --q) {
+      sufr[q] = 0.0;
+      sufi[q] = 0.0;
+      if (q < cnt) {
+        const double f = 2.0 * (par + 2 * (r0 + q));
+        sr = fma(f, yr[q], sr);
+        si = fma(f, yi[q], si);
+        sufr[q] = sr;
+        sufi[q] = si;
+      }
+    }
+    double ar = sr, ai = si;
+    for (int o = 1; o < S; o <<= 1) {
+      const double ur = __shfl_down(ar, o, S), ui = __shfl_down(ai, o, S);
+      if (seg + o < S) {
+        ar += ur;
+        ai += ui;
+      }
+    }
+    double abr = __shfl_down(ar, 1, S), abi = __shfl_down(ai, 1, S);
+    if (seg == S - 1) abr = abi = 0.0;
+    const double ir = 1.0 / g.zR;
+    auto put = [&](C* buf, int j, double vr, double vi) {
+      const double f = (j == 0 || j == N - 1) ? 2.0 : 1.0;
+      C c;
+      c.x = (R)(f * vr);
+      c.y = (R)(f * vi);
+      buf[bitrev(j, logM) * MB + m] = c;
+      if (j > 0 && j < N - 1) buf[bitrev(M - j, logM) * MB + m] = c;
+    };
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+      if (q < cnt) {
+        const int n = par + 2 * (r0 + q);
+        put(A, n, yr[q], yi[q]);
+        if (n >= 1) {
+          const double sc = n == 1 ? 0.5 * ir : ir;
+          put(B, n - 1, sc * (sufr[q] + abr), sc * (sufi[q] + abi));
+        }
+        if (n == N - 1) put(B, N - 1, 0.0, 0.0);
+      }
+  }
+  __syncthreads();
+  fft_lds_r22_pair<C, true, KE / 4 / NT, NT>(A, B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+
+  // 6. add the correction at the window nodes and the k = 0 linear mode; write out
+  for (int t = tid; t < N * MB; t += NT) {
+    const int j = t >> logMB, mm = t & (MB - 1), mo = m0 + mm;
+    if (mo >= nmodes) continue;
+    const C v = A[j * MB + mm], d = B[j * MB + mm];
+    double ps_x = 0.5 * (double)v.x, ps_y = 0.5 * (double)v.y, pz_x = 0.5 * (double)d.x, pz_y = 0.5 * (double)d.y;
+    const double z = zn[j];
+    const double k = s_k[mm];
+    if (k > 0.0 && s_keep[mm] && z >= -g.H_E && z <= g.H + g.H_E) {
+      // the exponentials in the storage precision of Psi, the sums in FP64
+      double e1, e2;
+      if (sizeof(R) == 8) {
+        e1 = exp(k * (z - g.H));
+        e2 = exp(-k * z);
+      } else {
+        e1 = (double)expf((float)(k * (z - g.H)));
+        e2 = (double)expf((float)(-k * z));
+      }
+      const double2 al = s_ab[mm][0], be = s_ab[mm][1];
+      ps_x += al.x * e1 + be.x * e2;
+      ps_y += al.y * e1 + be.y * e2;
+      pz_x += k * (al.x * e1 - be.x * e2);
+      pz_y += k * (al.y * e1 - be.y * e2);
+    }
+    if (mo == 0) {
+      ps_x += s_Ai[mm] * z;
+      pz_x += s_Ai[mm];
+    }
+    const size_t o = (size_t)j * nmodes + mo;
+    C a, b;
+    a.x = (R)ps_x; a.y = (R)ps_y;
+    b.x = (R)pz_x; b.y = (R)pz_y;
+    psi[o] = a;
+    psiz[o] = b;
+  }
+}
+
 }  // namespace
 
 namespace {
@@ -721,6 +1221,28 @@ size_t column_lds(const Geom& g, int KE) {
   const int M = 2 * (g.Nz - 1);
   const int MB = KE / M;
   return (size_t)(2 * KE + M / 2) * sizeof(double2) + (size_t)(kCtabRows * g.Nz + MB * 60) * sizeof(double);
+}
+
+// Whether a plan's chains use k_column_scan (and its factor table layout).
+bool scan_applies(const Geom& g) { return !(g.flags & DPSE_TRIPLY) && g.Nz >= 33 && g.Nz <= 257; }
+
+size_t column_scan_lds(const Geom& g, size_t creal) {
+  const int M = 2 * (g.Nz - 1), MB = kScanKE / M;
+  return (2 * (size_t)kScanKE + M / 2) * 2 * creal + (size_t)MB * 2 * kNumFunBC * 5 * sizeof(double);
+}
+
+template <typename R>
+void column_scan_as(dpse_plan* p) {
+  using C = typename CT<R>::T;
+  const Geom& g = p->g;
+  const int M = 2 * (g.Nz - 1);
+  const int MB = kScanKE / M;
+  const int nmodes = g.Ny * g.nkx;
+  const int nb = (nmodes + MB - 1) / MB;
+  hipLaunchKernelGGL(k_column_scan<R>, dim3(nb), dim3(kScanNT), column_scan_lds(g, sizeof(R)), p->stream, g,
+                     (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
+                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal,
+                     p->walls_on ? (const double2*)p->walls.hat : nullptr);
 }
 
 template <typename R, int KE, int NT>
@@ -930,8 +1452,12 @@ int column_candidates() { return kNumColumn; }
 hipError_t launch_pivots(dpse_plan* p, hipStream_t s) {
   const Geom& g = p->g;
   const int nt = 2 * g.Ny * g.nkx;
-  hipLaunchKernelGGL(k_pivots, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
-                     (const double*)p->t.ctab, p->t.cpiv);
+  if (scan_applies(g))
+    hipLaunchKernelGGL(k_pivots_scan, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
+                       (const double*)p->t.ctab, p->t.cpiv);
+  else
+    hipLaunchKernelGGL(k_pivots, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
+                       (const double*)p->t.ctab, p->t.cpiv);
   return hipGetLastError();
 }
 
@@ -941,6 +1467,9 @@ int column_threads(int i) { return kColumnNT[i]; }
 // A block of KE / M modes needs M <= KE, at most kMaxMB modes and its LDS.
 bool column_valid(const Geom& g, int i) {
   if (i < 0 || i >= kNumColumn) return false;
+  // the plan's factor table has the layout of one kernel family
+  if (i == kScanCand) return g_column_ok[i] && scan_applies(g);
+  if (scan_applies(g)) return false;
   const int KE = kColumnKE[i], M = 2 * (g.Nz - 1);
   return g_column_ok[i] && M <= KE && KE / M <= kMaxMB && 16 * (KE / M) <= kColumnNT[i] &&
          column_lds(g, KE) <= kMaxLds;
@@ -959,8 +1488,17 @@ hipError_t launch_column(dpse_plan* p) {
     return hipGetLastError();
   }
   int c = p->column_cfg;
-  if (!column_valid(p->g, c)) c = column_valid(p->g, 0) ? 0 : (column_valid(p->g, 1) ? 1 : 2);
+  if (!column_valid(p->g, c)) {
+    const int order[] = {kScanCand, 0, 1, 2, 3, 4};
+    c = 2;
+    for (int i : order)
+      if (column_valid(p->g, i)) {
+        c = i;
+        break;
+      }
+  }
   switch (c) {
+    case kScanCand: column_scan_as<R>(p); break;
     case 0: column_as<R, 2048, 256>(p); break;
     case 1: column_as<R, 1024, 256>(p); break;
     case 2: column_as<R, 4096, 256>(p); break;
@@ -980,7 +1518,8 @@ hipError_t prepare_kernels() {
       {(const void*)k_column<double, 1024, 256>, (const void*)k_column<float, 1024, 256>},
       {(const void*)k_column<double, 4096, 256>, (const void*)k_column<float, 4096, 256>},
       {(const void*)k_column<double, 2048, 512>, (const void*)k_column<float, 2048, 512>},
-      {(const void*)k_column<double, 4096, 512>, (const void*)k_column<float, 4096, 512>}};
+      {(const void*)k_column<double, 4096, 512>, (const void*)k_column<float, 4096, 512>},
+      {(const void*)k_column_scan<double>, (const void*)k_column_scan<float>}};
   bool any = false;
   for (int i = 0; i < kNumColumn; ++i) {
     bool ok = true;
