@@ -103,6 +103,10 @@ struct Workspace {
   double* scal = nullptr;
   double* partials = nullptr;  // block partial sums
   double* qpart = nullptr;     // per-block sums of q and |q| of the prep kernel, [2][ceil(max_n / 256)]
+  // block sums and their offsets of the multi-block counting-sort scans
+  // (bins on the plan's stream, cells on the side stream), [3 (nb + 1)] each
+  int* scan_bin = nullptr;
+  int* scan_cell = nullptr;
   int* status = nullptr;
 };
 
@@ -246,6 +250,9 @@ __device__ inline int xcd_block(int b, int nb) {
   const int x = b % kXcd, per = nb / kXcd, extra = nb % kXcd;
   return x * per + min(x, extra) + b / kXcd;
 }
+
+// Blocks of the multi-block exclusive scan over m counters (0: one block).
+int scan_blocks(int64_t m);
 
 // Small helpers.
 hipError_t fill_int(int* ptr, int value, int64_t count, hipStream_t s);

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "dpse_internal.h"
 #include "fft_lds.h"
@@ -728,16 +729,21 @@ __global__ void __launch_bounds__(NT) k_column(Geom g, const typename CT<R>::T* 
 //    sides (Re/Im of psi_i*, Re/Im of psi_o*, the unit free constant), sweeps
 //    them with carry 0 while forming the product of the multipliers, and the
 //    carries of the segments come from an inclusive scan of those affine maps
-//    over the lanes of the chain (wave shuffles); back substitution likewise,
-//    from the top segment down;
+//    over the lanes of the chain; back substitution likewise, from the top;
 //  * the linear functionals are partial dot products over each lane's rows,
-//    summed over the segments by shuffles;
-//  * the final series, its exact derivative (a suffix sum over the other
-//    parity, again a segmented scan) and the even extension for the inverse
-//    transform are formed in the same lanes and written straight to LDS.
-// KE = 2048 complex elements per transform buffer, 256 threads: MB = KE / M
-// modes per block (M = 2(Nz - 1)), S = M / 16 segments per chain, 2 S MB =
-// 256 lanes; 4 <= MB <= 32 for 33 <= Nz <= 257.
+//    summed over the segments by a reduce-scatter (each lane ends with a few
+//    of the sums, which it stores);
+//  * the final series, its exact derivative (a segmented suffix sum) and the
+//    even extension for the inverse transform are formed in the same lanes
+//    and written straight to LDS.
+// Cross-lane steps use DPP row and wave moves (VALU) where the partner lies
+// in the same row of 16 lanes or one lane away, LDS permutes otherwise.
+// KE = 2048 complex elements per transform buffer, 256 threads: for S = 2^LOGS
+// segments per chain, M = 2(Nz - 1) = 16 S, MB = KE / M = 128 / S modes per
+// block, 2 S MB = 256 lanes; LOGS = 2..5 for Nz = 33..257. LDS rows j of a
+// buffer are padded by one element every 2^(LOGS - 2) rows (element (j, m) at
+// j MB + m + (j >> (LOGS - 2))), which keeps the chain lanes' row reads and
+// the bit-reversed stores of the inverse transform off shared banks.
 constexpr int kScanKE = 2048;
 constexpr int kScanNT = 256;
 constexpr int kScanRows = 5;   // rows per lane: ceil(L / S) <= ceil(4 (Nz + 1) / (Nz - 1)) = 5
@@ -768,7 +774,95 @@ __global__ void __launch_bounds__(kThreads) k_pivots_scan(Geom g, const double* 
   }
 }
 
-template <typename R>
+// DPP controls (GFX9 encoding).
+constexpr int kDppQuadXor1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppRowShl = 0x100;       // + n: lane i takes lane i + n of its row of 16
+constexpr int kDppRowShr = 0x110;       // + n: lane i takes lane i - n of its row of 16
+constexpr int kDppWaveShl1 = 0x130;     // lane i takes lane i + 1 of the wave
+constexpr int kDppWaveShr1 = 0x138;     // lane i takes lane i - 1 of the wave
+constexpr int kDppRowMirror = 0x140;    // lane i takes lane 15 - i of its row
+constexpr int kDppRowHalfMirror = 0x141;  // lane i takes lane 7 - i of its half row
+constexpr int kDppRowBcast15 = 0x142;   // rows 1, 3 take lane 15 of the row below
+
+// A DPP move of a double (both halves); lanes without a source read 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// Radix-2^2 decimation-in-time FFTs of the MB sequences of both buffers in
+// lockstep (input in bit-reversed order, output natural), with the padded
+// row layout; forward twiddles tw[k] = exp(-2 pi i k / M).
+template <typename C, int LOGS>
+__device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) {
+  constexpr int LOGM = LOGS + 4, M = 1 << LOGM, LOGMB = 7 - LOGS, MB = 1 << LOGMB, PS = LOGS - 2;
+  constexpr int NT = kScanNT, BPT4 = M * MB / 4 / NT;
+  auto ix = [](int k, int s) { return k * MB + s + (k >> PS); };
+  int lh = 0;
+  if constexpr (LOGM & 1) {
+#pragma unroll
+    for (int q = 0; q < 2 * BPT4; ++q) {
+      const int t = tid + q * NT, s = t & (MB - 1), b = t >> LOGMB;
+      const int i0 = ix(2 * b, s), i1 = ix(2 * b + 1, s);
+      const C u0 = A[i0], v0 = A[i1], u1 = B[i0], v1 = B[i1];
+      A[i0] = cadd(u0, v0);
+      A[i1] = csub(u0, v0);
+      B[i0] = cadd(u1, v1);
+      B[i1] = csub(u1, v1);
+    }
+    __syncthreads();
+    lh = 1;
+  }
+  // passes not unrolled: unrolled, their hoisted addresses cost ~80 VGPRs
+#pragma nounroll
+  for (; lh < LOGM; lh += 2) {
+    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1;
+    C a[2][BPT4][4], w1[BPT4], w2[BPT4];
+    int k0[BPT4], s0[BPT4];
+#pragma unroll
+    for (int q = 0; q < BPT4; ++q) {
+      const int t = tid + q * NT, s = t & (MB - 1), b = t >> LOGMB;
+      const int grp = b >> lh, pos = b & (half - 1);
+      k0[q] = (grp << (lh + 2)) + pos;
+      s0[q] = s;
+      w1[q] = tw[pos * ts1];
+      w2[q] = tw[pos * ts2];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        a[0][q][e] = A[ix(k0[q] + e * half, s)];
+        a[1][q][e] = B[ix(k0[q] + e * half, s)];
+      }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      C* buf = bi == 0 ? A : B;
+#pragma unroll
+      for (int q = 0; q < BPT4; ++q) {
+        const C t1 = cmul(a[bi][q][1], w1[q]), t3 = cmul(a[bi][q][3], w1[q]);
+        const C b0 = cadd(a[bi][q][0], t1), b1 = csub(a[bi][q][0], t1);
+        const C b2 = cadd(a[bi][q][2], t3), b3 = csub(a[bi][q][2], t3);
+        const C u2 = cmul(b2, w2[q]);
+        C u3 = cmul(b3, w2[q]);  // times -i
+        {
+          const auto re = u3.x;
+          u3.x = u3.y;
+          u3.y = -re;
+        }
+        buf[ix(k0[q], s0[q])] = cadd(b0, u2);
+        buf[ix(k0[q] + 2 * half, s0[q])] = csub(b0, u2);
+        buf[ix(k0[q] + half, s0[q])] = cadd(b1, u3);
+        buf[ix(k0[q] + 3 * half, s0[q])] = csub(b1, u3);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename R, int LOGS>
 __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename CT<R>::T* __restrict__ fx_i,
                                                          const typename CT<R>::T* __restrict__ fx_o,
                                                          typename CT<R>::T* __restrict__ psi,
@@ -780,25 +874,27 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
                                                          const double2* __restrict__ wall_hat) {
   using C = typename CT<R>::T;
   constexpr int KE = kScanKE, NT = kScanNT, RW = kScanRows;
+  constexpr int S = 1 << LOGS, LOGM = LOGS + 4, M = 1 << LOGM, N = M / 2 + 1;
+  constexpr int LOGMB = 7 - LOGS, MB = 1 << LOGMB, PS = LOGS - 2;
+  constexpr int KEP = KE + (M >> PS);    // padded buffer length
+  auto ix = [](int j, int m) { return j * MB + m + (j >> PS); };
   extern __shared__ double2 smem2[];
   C* A = reinterpret_cast<C*>(smem2);  // F_o, later the series of psi_i*
-  C* B = A + KE;                       // F_i, later the derivative series
-  C* tw = B + KE;                      // twiddles exp(-2 pi i k / M), k < M/2
-  const int N = g.Nz, M = 2 * (N - 1), logM = ilog2d(M);
-  const int MB = KE / M, logMB = ilog2d(KE) - logM;
+  C* B = A + KEP;                      // F_i, later the derivative series
+  C* tw = B + KEP;                     // twiddles exp(-2 pi i k / M), k < M/2
   // reduced functionals [mode][parity][f][rhs] after the tables above
   double* sfun = reinterpret_cast<double*>(tw + M / 2);
-  __shared__ double s_k[kMaxMB], s_kap[kMaxMB];
-  __shared__ int s_keep[kMaxMB];
-  __shared__ double2 s_c[kMaxMB][2];   // free constants (y_0, y'_0) of psi_i*
-  __shared__ double2 s_ab[kMaxMB][2];  // correction alpha, beta
-  __shared__ double s_Ai[kMaxMB];
-  __shared__ double s_e[2][2][5];      // Ea, Eb of the k = 0 mode per parity and right-hand side
+  __shared__ double s_k[MB], s_kap[MB];
+  __shared__ int s_keep[MB];
+  __shared__ double2 s_c[MB][2];   // free constants (y_0, y'_0) of psi_i*
+  __shared__ double2 s_ab[MB][2];  // correction alpha, beta
+  __shared__ double s_Ai[MB];
+  __shared__ double s_e[2][2][5];  // Ea, Eb of the k = 0 mode per parity and right-hand side
 
-  const int NU = N + 2;
+  constexpr int NU = N + 2;
   const int nmodes = g.Ny * g.nkx;
   const int m0 = xcd_block(blockIdx.x, gridDim.x) * MB;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const double* W = ctab + kCtabRows * N;
   if (tid < MB) {
     const int mi = m0 + tid;
@@ -825,7 +921,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int t = tid + q * NT;
-      const int j = bitrev(t >> logMB, logM), m = t & (MB - 1), mi = m0 + m;
+      const int j = bitrev(t >> LOGMB, LOGM), m = t & (MB - 1), mi = m0 + m;
       const int c = j < N ? j : M - j;
       va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
       if (mi < nmodes) {
@@ -836,19 +932,21 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      A[tid + q * NT] = vb[q];
-      B[tid + q * NT] = va[q];
+      const int t = tid + q * NT, p = ix(t >> LOGMB, t & (MB - 1));
+      A[p] = vb[q];
+      B[p] = va[q];
     }
   }
   __syncthreads();
-  fft_lds_r22_pair<C, true, KE / 4 / NT, NT>(A, B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+  fft_scan_pair<C, LOGS>(A, B, tw, tid);
 
   // 2. the chains. Lane (m, par, seg): rows r0 .. r0 + cnt - 1 of chain par
-  //    (unknowns y''_n, n = par + 2r) of mode m.
-  const int logS = logM - 4, S = 1 << logS;
-  const int seg = tid & (S - 1), par = (tid >> logS) & 1, m = tid >> (logS + 1);
-  const int half0 = (N + 1) / 2, L = par ? N / 2 : half0;
-  const int r0 = (seg * L) >> logS, cnt = (((seg + 1) * L) >> logS) - r0;
+  //    (unknowns y''_n, n = par + 2r) of mode m; a chain's S lanes are
+  //    consecutive lanes of one wave.
+  const int seg = tid & (S - 1), par = (tid >> LOGS) & 1, m = tid >> (LOGS + 1);
+  constexpr int half0 = (N + 1) / 2;
+  const int L = par ? N / 2 : half0;
+  const int r0 = (seg * L) >> LOGS, cnt = (((seg + 1) * L) >> LOGS) - r0;
   const int mi = m0 + m;
   const bool live = mi < nmodes;
   const double kap2 = s_kap[m] * s_kap[m];
@@ -867,7 +965,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
         const double al = kap2 * ctab[n] * inv;
         gam[q] = kap2 * ctab[2 * N + n] * inv;  // back substitution: x_r = d_r + gam_r x_{r+1}
         const double gs = ctab[3 * N + n];
-        const C fo = A[n * MB + m], fi = B[n * MB + m];
+        const C fo = A[ix(n, m)], fi = B[ix(n, m)];
         const double rhs[5] = {gs * (double)fi.x, gs * (double)fi.y, gs * (double)fo.x, gs * (double)fo.y,
                                r == 0 ? kap2 : 0.0};
 #pragma unroll
@@ -878,23 +976,38 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       for (int k = 0; k < 5; ++k) X[q][k] = d[k];
       PP[q] = P;
     }
-    // the segment maps d_end = P d_in + d composed over the segments below
+    // inclusive scan of the segment maps d_end = P d_in + d over the chain:
+    // within rows of 16 lanes by DPP row shifts, then across the two rows
     double Ps = P, Ds[5] = {d[0], d[1], d[2], d[3], d[4]};
-    for (int o = 1; o < S; o <<= 1) {
-      const double pp = __shfl_up(Ps, o, S);
+    auto fstep = [&](auto ctrl_tag, int o, bool take, auto rows_tag) {
+      constexpr int CT_ = decltype(ctrl_tag)::value, RM = decltype(rows_tag)::value;
+      const double pp = dpp_d<CT_, RM>(Ps);
       double dp[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) dp[k] = __shfl_up(Ds[k], o, S);
-      if (seg >= o) {
+      for (int k = 0; k < 5; ++k) dp[k] = dpp_d<CT_, RM>(Ds[k]);
+      if (take) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) Ds[k] = fma(Ps, dp[k], Ds[k]);
         Ps *= pp;
       }
-    }
+      (void)o;
+    };
+    using I1 = std::integral_constant<int, kDppRowShr + 1>;
+    using I2 = std::integral_constant<int, kDppRowShr + 2>;
+    using I4 = std::integral_constant<int, kDppRowShr + 4>;
+    using I8 = std::integral_constant<int, kDppRowShr + 8>;
+    using IB = std::integral_constant<int, kDppRowBcast15>;
+    using RA = std::integral_constant<int, 0xF>;
+    using RB = std::integral_constant<int, 0xA>;
+    fstep(I1{}, 1, seg >= 1 && (lane & 15) >= 1, RA{});
+    fstep(I2{}, 2, seg >= 2 && (lane & 15) >= 2, RA{});
+    if constexpr (S > 4) fstep(I4{}, 4, seg >= 4 && (lane & 15) >= 4, RA{});
+    if constexpr (S > 8) fstep(I8{}, 8, seg >= 8 && (lane & 15) >= 8, RA{});
+    if constexpr (S > 16) fstep(IB{}, 16, seg >= 16, RB{});
     double din[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      din[k] = __shfl_up(Ds[k], 1, S);
+      din[k] = dpp_d<kDppWaveShr1>(Ds[k]);
       if (seg == 0) din[k] = 0.0;
     }
 #pragma unroll
@@ -921,12 +1034,34 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       }
     }
     double Qs = Q, Xs[5] = {x[0], x[1], x[2], x[3], x[4]};
-    for (int o = 1; o < S; o <<= 1) {
-      const double qn = __shfl_down(Qs, o, S);
+    auto bstep = [&](auto ctrl_tag, bool take) {
+      constexpr int CT_ = decltype(ctrl_tag)::value;
+      const double qn = dpp_d<CT_>(Qs);
       double xn[5];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) xn[k] = __shfl_down(Xs[k], o, S);
-      if (seg + o < S) {
+      for (int k = 0; k < 5; ++k) xn[k] = dpp_d<CT_>(Xs[k]);
+      if (take) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Xs[k] = fma(Qs, xn[k], Xs[k]);
+        Qs *= qn;
+      }
+    };
+    using J1 = std::integral_constant<int, kDppRowShl + 1>;
+    using J2 = std::integral_constant<int, kDppRowShl + 2>;
+    using J4 = std::integral_constant<int, kDppRowShl + 4>;
+    using J8 = std::integral_constant<int, kDppRowShl + 8>;
+    bstep(J1{}, seg + 1 < S && (lane & 15) + 1 < 16);
+    bstep(J2{}, seg + 2 < S && (lane & 15) + 2 < 16);
+    if constexpr (S > 4) bstep(J4{}, seg + 4 < S && (lane & 15) + 4 < 16);
+    if constexpr (S > 8) bstep(J8{}, seg + 8 < S && (lane & 15) + 8 < 16);
+    if constexpr (S > 16) {
+      // the lower row of the chain takes the upper row's composition (lane 16 of the chain)
+      const int src = (lane & ~31) | 16;
+      const double qn = __shfl(Qs, src, 64);
+      double xn[5];
+#pragma unroll
+      for (int k = 0; k < 5; ++k) xn[k] = __shfl(Xs[k], src, 64);
+      if (seg < 16) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) Xs[k] = fma(Qs, xn[k], Xs[k]);
         Qs *= qn;
@@ -935,7 +1070,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     double xin[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      xin[k] = __shfl_down(Xs[k], 1, S);
+      xin[k] = dpp_d<kDppWaveShl1>(Xs[k]);
       if (seg == S - 1) xin[k] = 0.0;
     }
 #pragma unroll
@@ -948,50 +1083,100 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
 
   // 3. linear functionals (dot products of y'' and the free constants with
   //    the plan's weight vectors) summed over the lane's rows, then over the
-  //    segments; the homogeneous solution of the even chain has y_0 = 1, that
-  //    of the odd chain y'_0 = 1
-  auto functionals = [&](int f0, int nf, double* dst, int dst_stride) {
-    double acc[4][5];
+  //    chain's segments by a reduce-scatter: the 4 x 5 partials of a pass,
+  //    padded to 32, are halved at each step (partners at distance 16, 8, 4,
+  //    2, 1 within the chain), and lane seg ends with the sums of entries
+  //    [seg K, seg K + K), K = 32 / S. The homogeneous solution of the even
+  //    chain has y_0 = 1, that of the odd chain y'_0 = 1.
+  auto functionals = [&](int f0, double* dst) {
+    double v[32];
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int k = 0; k < 5; ++k) acc[f][k] = 0.0;
+    for (int i = 0; i < 32; ++i) v[i] = 0.0;
 #pragma unroll
     for (int q = 0; q < RW; ++q)
       if (q < cnt) {
         const int n = par + 2 * (r0 + q);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
-          if (f < nf) {
-            const double w = W[(f0 + f) * NU + n];
+          const double w = W[(f0 + f) * NU + n];
 #pragma unroll
-            for (int k = 0; k < 5; ++k) acc[f][k] = fma(w, X[q][k], acc[f][k]);
-          }
+          for (int k = 0; k < 5; ++k) v[f * 5 + k] = fma(w, X[q][k], v[f * 5 + k]);
         }
       }
     if (seg == 0) {
 #pragma unroll
-      for (int f = 0; f < 4; ++f)
-        if (f < nf) acc[f][4] += W[(f0 + f) * NU + N + par];
+      for (int f = 0; f < 4; ++f) v[f * 5 + 4] += W[(f0 + f) * NU + N + par];
     }
+    // reduce-scatter over the S lanes of the chain
+    auto halve = [&](auto ctrl_tag, int h, bool upper) {
+      constexpr int CT_ = decltype(ctrl_tag)::value;
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if (f < nf) {
-        for (int o = S >> 1; o > 0; o >>= 1) {
-#pragma unroll
-          for (int k = 0; k < 5; ++k) acc[f][k] += __shfl_xor(acc[f][k], o, S);
-        }
-        if (seg == 0) {
-#pragma unroll
-          for (int k = 0; k < 5; ++k) dst[f * dst_stride + k] = acc[f][k];
+      for (int i = 0; i < 16; ++i) {
+        if (i < h) {
+          const double snd = upper ? v[i] : v[h + i];
+          const double kp = upper ? v[h + i] : v[i];
+          double rcv;
+          if constexpr (CT_ < 0) rcv = __shfl_xor(snd, 16, 64);
+          else rcv = dpp_d<CT_>(snd);
+          v[i] = kp + rcv;
         }
       }
+    };
+    using X16 = std::integral_constant<int, -1>;
+    using X8 = std::integral_constant<int, kDppRowMirror>;
+    using X4 = std::integral_constant<int, kDppRowHalfMirror>;
+    using X2 = std::integral_constant<int, kDppQuadXor2>;
+    using X1 = std::integral_constant<int, kDppQuadXor1>;
+    int h = 16;
+    if constexpr (S > 16) { halve(X16{}, h, (seg & 16) != 0); h >>= 1; }
+    if constexpr (S > 8) { halve(X8{}, h, (seg & 8) != 0); h >>= 1; }
+    if constexpr (S > 4) { halve(X4{}, h, (seg & 4) != 0); h >>= 1; }
+    halve(X2{}, h, (seg & 2) != 0);
+    h >>= 1;
+    halve(X1{}, h, (seg & 1) != 0);
+    constexpr int K = 32 / S;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int e = seg * K + i;
+      if (e < 20) dst[(e / 5) * 5 + (e % 5)] = v[i];
     }
   };
   double* my_fun = sfun + (m * 2 + par) * kNumFunBC * 5;
-  functionals(0, 4, my_fun, 5);
-  functionals(4, 4, my_fun + 4 * 5, 5);
-  if (mi == 0) functionals(FUN_EA, 2, &s_e[par][0][0], 5);
+  functionals(0, my_fun);
+  functionals(4, my_fun + 4 * 5);
+  if (mi == 0) {
+    // Ea, Eb of the k = 0 mode (FUN_EA, FUN_EB follow DH): a plain reduction
+    double ea[5] = {0, 0, 0, 0, 0}, eb[5] = {0, 0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+      if (q < cnt) {
+        const int n = par + 2 * (r0 + q);
+        const double wa = W[FUN_EA * NU + n], wb = W[FUN_EB * NU + n];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          ea[k] = fma(wa, X[q][k], ea[k]);
+          eb[k] = fma(wb, X[q][k], eb[k]);
+        }
+      }
+    if (seg == 0) {
+      ea[4] += W[FUN_EA * NU + N + par];
+      eb[4] += W[FUN_EB * NU + N + par];
+    }
+    for (int o = S >> 1; o > 0; o >>= 1) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        ea[k] += __shfl_xor(ea[k], o, S);
+        eb[k] += __shfl_xor(eb[k], o, S);
+      }
+    }
+    if (seg == 0) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        s_e[par][0][k] = ea[k];
+        s_e[par][1][k] = eb[k];
+      }
+    }
+  }
   __syncthreads();
 
   // 4. per mode: free constants, wall values, mismatches, harmonic correction, k = 0
@@ -1106,8 +1291,8 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
         lr = xr[q];
         li = xi[q];
       }
-    double pr = __shfl_up(lr, 1, S), pi = __shfl_up(li, 1, S);
-    double nr = __shfl_down(xr[0], 1, S), ni = __shfl_down(xi[0], 1, S);
+    double pr = dpp_d<kDppWaveShr1>(lr), pi = dpp_d<kDppWaveShr1>(li);
+    double nr = dpp_d<kDppWaveShl1>(xr[0]), ni = dpp_d<kDppWaveShl1>(xi[0]);
     if (seg == 0) pr = pi = 0.0;
     if (seg == S - 1) nr = ni = 0.0;
     double yr[RW], yi[RW];
@@ -1144,14 +1329,31 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       }
     }
     double ar = sr, ai = si;
-    for (int o = 1; o < S; o <<= 1) {
-      const double ur = __shfl_down(ar, o, S), ui = __shfl_down(ai, o, S);
-      if (seg + o < S) {
+    auto sstep = [&](auto ctrl_tag, bool take) {
+      constexpr int CT_ = decltype(ctrl_tag)::value;
+      const double ur = dpp_d<CT_>(ar), ui = dpp_d<CT_>(ai);
+      if (take) {
+        ar += ur;
+        ai += ui;
+      }
+    };
+    using K1 = std::integral_constant<int, kDppRowShl + 1>;
+    using K2 = std::integral_constant<int, kDppRowShl + 2>;
+    using K4 = std::integral_constant<int, kDppRowShl + 4>;
+    using K8 = std::integral_constant<int, kDppRowShl + 8>;
+    sstep(K1{}, seg + 1 < S && (lane & 15) + 1 < 16);
+    sstep(K2{}, seg + 2 < S && (lane & 15) + 2 < 16);
+    if constexpr (S > 4) sstep(K4{}, seg + 4 < S && (lane & 15) + 4 < 16);
+    if constexpr (S > 8) sstep(K8{}, seg + 8 < S && (lane & 15) + 8 < 16);
+    if constexpr (S > 16) {
+      const int src = (lane & ~31) | 16;
+      const double ur = __shfl(ar, src, 64), ui = __shfl(ai, src, 64);
+      if (seg < 16) {
         ar += ur;
         ai += ui;
       }
     }
-    double abr = __shfl_down(ar, 1, S), abi = __shfl_down(ai, 1, S);
+    double abr = dpp_d<kDppWaveShl1>(ar), abi = dpp_d<kDppWaveShl1>(ai);
     if (seg == S - 1) abr = abi = 0.0;
     const double ir = 1.0 / g.zR;
     auto put = [&](C* buf, int j, double vr, double vi) {
@@ -1159,8 +1361,8 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       C c;
       c.x = (R)(f * vr);
       c.y = (R)(f * vi);
-      buf[bitrev(j, logM) * MB + m] = c;
-      if (j > 0 && j < N - 1) buf[bitrev(M - j, logM) * MB + m] = c;
+      buf[ix(bitrev(j, LOGM), m)] = c;
+      if (j > 0 && j < N - 1) buf[ix(bitrev(M - j, LOGM), m)] = c;
     };
 #pragma unroll
     for (int q = 0; q < RW; ++q)
@@ -1175,13 +1377,13 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       }
   }
   __syncthreads();
-  fft_lds_r22_pair<C, true, KE / 4 / NT, NT>(A, B, logM, logMB, 1, 1 << logMB, tw, false, tid);
+  fft_scan_pair<C, LOGS>(A, B, tw, tid);
 
   // 6. add the correction at the window nodes and the k = 0 linear mode; write out
   for (int t = tid; t < N * MB; t += NT) {
-    const int j = t >> logMB, mm = t & (MB - 1), mo = m0 + mm;
+    const int j = t >> LOGMB, mm = t & (MB - 1), mo = m0 + mm;
     if (mo >= nmodes) continue;
-    const C v = A[j * MB + mm], d = B[j * MB + mm];
+    const C v = A[ix(j, mm)], d = B[ix(j, mm)];
     double ps_x = 0.5 * (double)v.x, ps_y = 0.5 * (double)v.y, pz_x = 0.5 * (double)d.x, pz_y = 0.5 * (double)d.y;
     const double z = zn[j];
     const double k = s_k[mm];
@@ -1226,23 +1428,37 @@ size_t column_lds(const Geom& g, int KE) {
 // Whether a plan's chains use k_column_scan (and its factor table layout).
 bool scan_applies(const Geom& g) { return !(g.flags & DPSE_TRIPLY) && g.Nz >= 33 && g.Nz <= 257; }
 
+// Dynamic LDS of k_column_scan: two padded transform buffers, the twiddles
+// and the reduced functionals.
 size_t column_scan_lds(const Geom& g, size_t creal) {
   const int M = 2 * (g.Nz - 1), MB = kScanKE / M;
-  return (2 * (size_t)kScanKE + M / 2) * 2 * creal + (size_t)MB * 2 * kNumFunBC * 5 * sizeof(double);
+  int logS = -4;
+  while ((1 << (logS + 4)) < M) ++logS;
+  const size_t kep = (size_t)kScanKE + (M >> (logS - 2));
+  return (2 * kep + M / 2) * 2 * creal + (size_t)MB * 2 * kNumFunBC * 5 * sizeof(double);
 }
 
-template <typename R>
+template <typename R, int LOGS>
 void column_scan_as(dpse_plan* p) {
   using C = typename CT<R>::T;
   const Geom& g = p->g;
-  const int M = 2 * (g.Nz - 1);
-  const int MB = kScanKE / M;
+  constexpr int MB = 128 >> LOGS;
   const int nmodes = g.Ny * g.nkx;
   const int nb = (nmodes + MB - 1) / MB;
-  hipLaunchKernelGGL(k_column_scan<R>, dim3(nb), dim3(kScanNT), column_scan_lds(g, sizeof(R)), p->stream, g,
-                     (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
+  hipLaunchKernelGGL((k_column_scan<R, LOGS>), dim3(nb), dim3(kScanNT), column_scan_lds(g, sizeof(R)), p->stream,
+                     g, (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
                      (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal,
                      p->walls_on ? (const double2*)p->walls.hat : nullptr);
+}
+
+template <typename R>
+void column_scan_dispatch(dpse_plan* p) {
+  switch (p->g.Nz) {
+    case 33: column_scan_as<R, 2>(p); break;
+    case 65: column_scan_as<R, 3>(p); break;
+    case 129: column_scan_as<R, 4>(p); break;
+    default: column_scan_as<R, 5>(p); break;
+  }
 }
 
 template <typename R, int KE, int NT>
@@ -1498,7 +1714,7 @@ hipError_t launch_column(dpse_plan* p) {
       }
   }
   switch (c) {
-    case kScanCand: column_scan_as<R>(p); break;
+    case kScanCand: column_scan_dispatch<R>(p); break;
     case 0: column_as<R, 2048, 256>(p); break;
     case 1: column_as<R, 1024, 256>(p); break;
     case 2: column_as<R, 4096, 256>(p); break;
@@ -1513,18 +1729,21 @@ hipError_t launch_column(dpse_plan* p) {
 // (which may be captured into a graph).
 // A candidate whose limit cannot be raised is left out of column_valid().
 hipError_t prepare_kernels() {
-  const void* fns[kNumColumn][2] = {
+  const void* fns[kNumColumn][8] = {
       {(const void*)k_column<double, 2048, 256>, (const void*)k_column<float, 2048, 256>},
       {(const void*)k_column<double, 1024, 256>, (const void*)k_column<float, 1024, 256>},
       {(const void*)k_column<double, 4096, 256>, (const void*)k_column<float, 4096, 256>},
       {(const void*)k_column<double, 2048, 512>, (const void*)k_column<float, 2048, 512>},
       {(const void*)k_column<double, 4096, 512>, (const void*)k_column<float, 4096, 512>},
-      {(const void*)k_column_scan<double>, (const void*)k_column_scan<float>}};
+      {(const void*)k_column_scan<double, 2>, (const void*)k_column_scan<float, 2>,
+       (const void*)k_column_scan<double, 3>, (const void*)k_column_scan<float, 3>,
+       (const void*)k_column_scan<double, 4>, (const void*)k_column_scan<float, 4>,
+       (const void*)k_column_scan<double, 5>, (const void*)k_column_scan<float, 5>}};
   bool any = false;
   for (int i = 0; i < kNumColumn; ++i) {
     bool ok = true;
     for (const void* f : fns[i])
-      ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) == hipSuccess;
+      if (f) ok = ok && hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds) == hipSuccess;
     g_column_ok[i] = ok;
     any = any || ok;
   }

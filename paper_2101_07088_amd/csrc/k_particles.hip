@@ -264,6 +264,80 @@ __global__ void __launch_bounds__(1024) k_scan(const int* __restrict__ cnt, int*
   if (threadIdx.x == T - 1) off[m] = wofs + incl;
 }
 
+// Multi-block form of the same scan for long counter arrays: block sums of
+// chunks of kScanChunk counters, one-block scan of the sums, then every chunk
+// scanned again with its offset (each thread a run of 8 consecutive counters).
+constexpr int kScanChunk = 8192;
+
+__global__ void __launch_bounds__(1024) k_scan_sums(const int* __restrict__ cnt, int m, int* __restrict__ part) {
+  __shared__ int ws[1024 / 64];
+  const int base = blockIdx.x * kScanChunk, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int s = 0;
+  for (int i = threadIdx.x; i < kScanChunk; i += 1024)
+    if (base + i < m) s += cnt[base + i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (lane == 0) ws[w] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int i = 0; i < 1024 / 64; ++i) t += ws[i];
+    part[blockIdx.x] = t;
+  }
+}
+
+__global__ void __launch_bounds__(1024) k_scan_apply(const int* __restrict__ cnt, int m, const int* __restrict__ pofs,
+                                                     int nb, int* off, int* cur) {
+  __shared__ int wsum[1024 / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int b = blockIdx.x * kScanChunk + threadIdx.x * 8;
+  int v[8], s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    v[k] = b + k < m ? cnt[b + k] : 0;
+    s += v[k];
+  }
+  int incl = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += u;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  int run = pofs[blockIdx.x] + incl - s;
+  for (int i = 0; i < w; ++i) run += wsum[i];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (b + k < m) {
+      off[b + k] = run;
+      cur[b + k] = run;
+    }
+    run += v[k];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) off[m] = pofs[nb];
+}
+
+// Exclusive scan of cnt[0..m) into off[0..m] and cur[0..m); scratch holds
+// 3 (scan_blocks(m) + 1) ints.
+void launch_scan(const int* cnt, int* off, int* cur, int m, int* scratch, hipStream_t s) {
+  const int nb = scan_blocks(m);
+  if (nb == 0) {
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, cnt, off, cur, m);
+    return;
+  }
+  int* part = scratch;
+  int* pofs = scratch + (nb + 1);
+  int* pcur = scratch + 2 * (nb + 1);
+  hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(1024), 0, s, cnt, m, part);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)part, pofs, pcur, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(1024), 0, s, cnt, m, (const int*)pofs, nb, off, cur);
+}
+
+}  // namespace
+
+int scan_blocks(int64_t m) { return m <= 4 * kScanChunk ? 0 : (int)((m + kScanChunk - 1) / kScanChunk); }
+
+namespace {
+
 // --- near field -------------------------------------------------------------
 
 template <typename R>
@@ -544,7 +618,7 @@ hipError_t launch_bin_grid(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   int nb3 = (int)((3 * n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys);
+  launch_scan((const int*)w.bin_cnt, w.bin_off, w.bin_cur, p->nkeys, w.scan_bin, s);
   const int nqb = (int)((n + kThreads - 1) / kThreads);  // blocks of the prep kernel
   hipLaunchKernelGGL(k_scatter_ext, dim3(nb3), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      (const int*)w.ext_meta, (const int*)w.n_img, w.bin_cur, w.srt, w.srt_meta,
@@ -562,8 +636,7 @@ hipError_t launch_bin_cells(dpse_plan* p, int64_t n) {
   hipStream_t s = p->stream;
   Workspace& w = p->w;
   int nb = (int)((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, (const int*)w.cell_cnt, w.cell_off, w.cell_cur,
-                     p->ncells);
+  launch_scan((const int*)w.cell_cnt, w.cell_off, w.cell_cur, p->ncells, w.scan_cell, s);
   hipLaunchKernelGGL(k_scatter_cells, dim3(nb), dim3(kThreads), 0, s, p->g, n, (const Part*)w.ext,
                      w.cell_cur, w.nsrt, w.nsrt_idx);
   if (p->g.flags & DPSE_DETERMINISTIC)

@@ -304,6 +304,8 @@ size_t carve_workspace(dpse_plan* p, char* base) {
   // node (two blocks of npartials: Nz <= 2 npartials), wall energy
   c.take(&w.scal, 16); c.take(&w.partials, 5 * (size_t)p->npartials);
   c.take(&w.qpart, 2 * ((max_n + 255) / 256));
+  c.take(&w.scan_bin, 3 * (size_t)(dpse::scan_blocks(p->nkeys) + 1));
+  c.take(&w.scan_cell, 3 * (size_t)(dpse::scan_blocks(p->ncells) + 1));
   return (c.off + 255) & ~size_t(255);
 }
 
