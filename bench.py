@@ -54,7 +54,7 @@ INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4)]
 COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512), (2048, 256)]  # (KE, threads)
 
 
-def kernel_name(stage, tiles, mixed):
+def kernel_name(stage, tiles, mixed, p):
     """Name (as rocprofv3 prints it, spaces removed) of the single kernel of a
     grid stage for the tuned launch shapes, or None for multi-kernel stages."""
     r = "float" if mixed else "double"
@@ -69,7 +69,7 @@ def kernel_name(stage, tiles, mixed):
         return f"k_interp_gather<{r},{t},{pz},false>" if i >= 5 else f"k_interp<{r},{t},{pz}>"
     if stage == "column":
         if tiles[2] == 5:   # the segmented-scan kernel of the grids with Nz <= 257
-            return f"k_column_scan<{r}>"
+            return f"k_column_scan<{r},{int(math.log2((p.Nz - 1) // 8))}>"
         ke, nt = COLUMN_SHAPES[tiles[2]]
         return f"k_column<{r},{ke},{nt}>"
     return None
@@ -718,7 +718,7 @@ def main(argv=None):
     dom = max(single, key=lambda k: r["stages"][k])
     t_dom = r["stages"][dom] * 1e-3
     achieved = sb[dom] / t_dom / 1e9
-    dom_kernel = kernel_name(dom, r["tiles"], head == "mixed")
+    dom_kernel = kernel_name(dom, r["tiles"], head == "mixed", p)
     traffic = profiled_traffic(dom_kernel)
     line = {
         "metric": "charge-force evals/s at <=1e-5 rel RMS force err vs FP64; p50/p99 solve ms",

@@ -794,32 +794,85 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
-// Radix-2^2 decimation-in-time FFTs of the MB sequences of both buffers in
-// lockstep (input in bit-reversed order, output natural), with the padded
-// row layout; forward twiddles tw[k] = exp(-2 pi i k / M).
+// Decimation-in-time FFTs of the MB sequences of both buffers in lockstep
+// (input in bit-reversed order, output natural), with the padded row layout,
+// in passes of three radix-2 stages (two where the stage count requires);
+// forward twiddles tw[k] = exp(-2 pi i k / M).
 template <typename C, int LOGS>
 __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) {
   constexpr int LOGM = LOGS + 4, M = 1 << LOGM, LOGMB = 7 - LOGS, MB = 1 << LOGMB, PS = LOGS - 2;
-  constexpr int NT = kScanNT, BPT4 = M * MB / 4 / NT;
+  constexpr int NT = kScanNT;
   auto ix = [](int k, int s) { return k * MB + s + (k >> PS); };
-  int lh = 0;
-  if constexpr (LOGM & 1) {
+  using Rr = decltype(C{}.x);
+  // radix-2^3 pass fusing the stages lh, lh + 1, lh + 2 on eight elements
+  // k0 + e half (one group per thread and buffer); the twiddles of the two
+  // later stages are those of the first kind times -i and powers of
+  // exp(-i pi / 4). The first pass maps consecutive threads to consecutive
+  // groups of one sequence where that keeps its LDS accesses off shared banks.
+  auto pass8 = [&](int lh, bool gfast) {
+    constexpr int LG = LOGM - 3;  // groups per sequence: M / 8
+    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1, ts3 = ts1 >> 2;
+    int s, b;
+    if (gfast) {
+      b = tid & ((1 << LG) - 1);
+      s = tid >> LG;
+    } else {
+      s = tid & (MB - 1);
+      b = tid >> LOGMB;
+    }
+    const int grp = b >> lh, pos = b & (half - 1);
+    const int k0 = (grp << (lh + 3)) + pos;
+    const C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+    C a[2][8];
 #pragma unroll
-    for (int q = 0; q < 2 * BPT4; ++q) {
-      const int t = tid + q * NT, s = t & (MB - 1), b = t >> LOGMB;
-      const int i0 = ix(2 * b, s), i1 = ix(2 * b + 1, s);
-      const C u0 = A[i0], v0 = A[i1], u1 = B[i0], v1 = B[i1];
-      A[i0] = cadd(u0, v0);
-      A[i1] = csub(u0, v0);
-      B[i0] = cadd(u1, v1);
-      B[i1] = csub(u1, v1);
+    for (int e = 0; e < 8; ++e) {
+      a[0][e] = A[ix(k0 + e * half, s)];
+      a[1][e] = B[ix(k0 + e * half, s)];
+    }
+    const Rr r2 = (Rr)0.70710678118654752440;
+    C w2m, w3e[4];  // w2 times -i; w3 times exp(-i pi e / 4)
+    w2m.x = w2.y;
+    w2m.y = -w2.x;
+    w3e[0] = w3;
+    w3e[1].x = r2 * (w3.x + w3.y);
+    w3e[1].y = r2 * (w3.y - w3.x);
+    w3e[2].x = w3.y;
+    w3e[2].y = -w3.x;
+    w3e[3].x = r2 * (w3.y - w3.x);
+    w3e[3].y = -r2 * (w3.x + w3.y);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      C* v = a[bi];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const C t = cmul(v[e + 1], w1);
+        v[e + 1] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (e & 2) continue;
+        const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
+        v[e + 2] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const C t = cmul(v[e + 4], w3e[e]);
+        v[e + 4] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      A[ix(k0 + e * half, s)] = a[0][e];
+      B[ix(k0 + e * half, s)] = a[1][e];
     }
     __syncthreads();
-    lh = 1;
-  }
-  // passes not unrolled: unrolled, their hoisted addresses cost ~80 VGPRs
-#pragma nounroll
-  for (; lh < LOGM; lh += 2) {
+  };
+  // radix-2^2 pass (stages lh, lh + 1), two groups per thread and buffer
+  auto pass4 = [&](int lh) {
+    constexpr int BPT4 = M * MB / 4 / NT;
     const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1;
     C a[2][BPT4][4], w1[BPT4], w2[BPT4];
     int k0[BPT4], s0[BPT4];
@@ -859,7 +912,15 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
       }
     }
     __syncthreads();
-  }
+  };
+  // stage plans: 2^9 = 8 8 8, 2^8 = 8 8 4, 2^7 = 8 4 4, 2^6 = 8 8 (passes
+  // in loops that are not unrolled: unrolled, their hoisted addresses cost
+  // ~40 VGPRs)
+  constexpr int n8 = LOGM == 7 ? 1 : LOGM / 3, n4 = (LOGM - 3 * n8) / 2;
+#pragma nounroll
+  for (int p = 0; p < n8; ++p) pass8(3 * p, p == 0 && LOGS >= 4);
+#pragma nounroll
+  for (int p = 0; p < n4; ++p) pass4(3 * n8 + 2 * p);
 }
 
 template <typename R, int LOGS>
