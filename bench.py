@@ -50,11 +50,11 @@ def stage_bytes(p, beta, s):
 
 
 SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4)]
-INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4)]
+INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4), (0, 0)]
 COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512), (2048, 256)]  # (KE, threads)
 
 
-def kernel_name(stage, tiles, mixed, p):
+def kernel_name(stage, tiles, mixed, p, support):
     """Name (as rocprofv3 prints it, spaces removed) of the single kernel of a
     grid stage for the tuned launch shapes, or None for multi-kernel stages."""
     r = "float" if mixed else "double"
@@ -64,6 +64,9 @@ def kernel_name(stage, tiles, mixed, p):
         return f"k_spread{'_gather' if i >= 6 else ''}<{r},{t},{pz}>"
     if stage == "interp":
         i = tiles[1]
+        if i == 7:   # one wave per charge in bin order (columns in 4 passes of 64 lanes for n_g <= 16)
+            c, gn = (4, 4 if mixed else 2) if support * support <= 256 else (16, 1)
+            return f"k_interp_wave<{r},{c},{gn}>"
         t, pz = INTERP_SHAPES[i]
         # the gather shapes carry the wall-term switch (off on this workload)
         return f"k_interp_gather<{r},{t},{pz},false>" if i >= 5 else f"k_interp<{r},{t},{pz}>"
@@ -718,7 +721,7 @@ def main(argv=None):
     dom = max(single, key=lambda k: r["stages"][k])
     t_dom = r["stages"][dom] * 1e-3
     achieved = sb[dom] / t_dom / 1e9
-    dom_kernel = kernel_name(dom, r["tiles"], head == "mixed", p)
+    dom_kernel = kernel_name(dom, r["tiles"], head == "mixed", p, r["info"]["support"])
     traffic = profiled_traffic(dom_kernel)
     line = {
         "metric": "charge-force evals/s at <=1e-5 rel RMS force err vs FP64; p50/p99 solve ms",
