@@ -237,3 +237,102 @@ __device__ void fft_lds_r22_pair(C* buf0, C* buf1, int logL, int lognseq, int ss
 }
 
 }  // namespace dpse
+
+namespace dpse {
+
+// Row-major batches of nseq sequences of length N = 2^logN in LDS, element k of
+// sequence s at rowpad_ix(s, k, N) (one padding element after every 8, which
+// keeps the radix-2^3 passes below off shared banks). Input in bit-reversed
+// order, output natural; tw[k] = exp(-2 pi i k / N) for k < N/2 (conjugated
+// when inverse). Passes of three radix-2 stages (k0 + e half, e < 8), two where
+// the stage count requires: 2^10 = 8 8 4 4, 2^9 = 8 8 8, 2^8 = 8 8 4, 2^7 =
+// 8 4 4, 2^6 = 8 8, 2^5 = 8 4. nseq N == NTHR 8. Threads take consecutive
+// groups of one sequence.
+__device__ __forceinline__ int rowpad_ix(int s, int k, int N) { return s * (N + (N >> 3)) + k + (k >> 3); }
+
+template <typename C, int NTHR>
+__device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid) {
+  using Rr = decltype(C{}.x);
+  const int N = 1 << logN;
+  auto pass8 = [&](int lh) {
+    const int half = 1 << lh, ts1 = (N >> 1) >> lh, ts2 = ts1 >> 1, ts3 = ts1 >> 2;
+    const int G = N >> 3, b = tid & (G - 1), s = tid / G;
+    const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 3)) + pos;
+    C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+    if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+    C v[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) v[e] = buf[rowpad_ix(s, k0 + e * half, N)];
+    const Rr r2 = (Rr)0.70710678118654752440;
+    const Rr sg = inverse ? (Rr)-1 : (Rr)1;  // forward: times -i and exp(-i pi/4); inverse: the conjugates
+    C w2m, w3e[4];
+    w2m.x = sg * w2.y;
+    w2m.y = -sg * w2.x;
+    w3e[0] = w3;
+    w3e[1].x = r2 * (w3.x + sg * w3.y);
+    w3e[1].y = r2 * (w3.y - sg * w3.x);
+    w3e[2].x = sg * w3.y;
+    w3e[2].y = -sg * w3.x;
+    w3e[3].x = r2 * (sg * w3.y - w3.x);
+    w3e[3].y = -r2 * (sg * w3.x + w3.y);
+#pragma unroll
+    for (int e = 0; e < 8; e += 2) {
+      const C t = cmul(v[e + 1], w1);
+      v[e + 1] = csub(v[e], t);
+      v[e] = cadd(v[e], t);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      if (e & 2) continue;
+      const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
+      v[e + 2] = csub(v[e], t);
+      v[e] = cadd(v[e], t);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const C t = cmul(v[e + 4], w3e[e]);
+      v[e + 4] = csub(v[e], t);
+      v[e] = cadd(v[e], t);
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) buf[rowpad_ix(s, k0 + e * half, N)] = v[e];
+    __syncthreads();
+  };
+  auto pass4 = [&](int lh) {
+    const int half = 1 << lh, ts1 = (N >> 1) >> lh, ts2 = ts1 >> 1;
+    const int G = N >> 2;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int t = tid + q * NTHR, b = t & (G - 1), s = t / G;
+      const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 2)) + pos;
+      C x1 = tw[pos * ts1], x2 = tw[pos * ts2];
+      if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
+      C a[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = buf[rowpad_ix(s, k0 + e * half, N)];
+      const C t1 = cmul(a[1], x1), t3 = cmul(a[3], x1);
+      const C b0 = cadd(a[0], t1), b1 = csub(a[0], t1);
+      const C b2 = cadd(a[2], t3), b3 = csub(a[2], t3);
+      const C u2 = cmul(b2, x2);
+      C u3 = cmul(b3, x2);  // times -i (forward) or +i (inverse)
+      {
+        const auto re = u3.x;
+        if (inverse) { u3.x = -u3.y; u3.y = re; }
+        else { u3.x = u3.y; u3.y = -re; }
+      }
+      buf[rowpad_ix(s, k0, N)] = cadd(b0, u2);
+      buf[rowpad_ix(s, k0 + 2 * half, N)] = csub(b0, u2);
+      buf[rowpad_ix(s, k0 + half, N)] = cadd(b1, u3);
+      buf[rowpad_ix(s, k0 + 3 * half, N)] = csub(b1, u3);
+    }
+    __syncthreads();
+  };
+  const int n8 = logN % 3 == 0 ? logN / 3 : (logN % 3 == 1 ? (logN - 4) / 3 : (logN - 2) / 3);
+  const int n4 = (logN - 3 * n8) / 2;
+#pragma nounroll
+  for (int p = 0; p < n8; ++p) pass8(3 * p);
+#pragma nounroll
+  for (int p = 0; p < n4; ++p) pass4(3 * n8 + 2 * p);
+}
+
+}  // namespace dpse

@@ -21,7 +21,7 @@ constexpr int kElems = 2048;  // complex elements per LDS FFT buffer (x passes)
 // KB = kYElems / Ny consecutive kx columns (row pieces of KB values; the
 // XCD-aware block order keeps the neighbours that share their lines in one L2)
 template <typename R>
-constexpr int kYElems = 2048;
+constexpr int kYElems = sizeof(R) == 4 ? 4096 : 2048;
 
 template <typename R>
 struct CT;
@@ -64,7 +64,7 @@ template <typename R>
 __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R> J,
                                                         const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
-  __shared__ C buf[kElems];
+  __shared__ C buf[kElems + kElems / 8];
   __shared__ C tw[512];
   const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
   const int nseq = kElems / Nx;              // row pairs per block
@@ -94,14 +94,14 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     C d;
     d.x = v0[q];
     d.y = v1[q];
-    buf[i] = d;
+    buf[rowpad_ix(i >> logN, i & (Nx - 1), Nx)] = d;
   }
   __syncthreads();
-  fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(nseq), Nx, 1, tw, false, threadIdx.x);
+  fft_rows_r8<C, kThreads>(buf, logN, tw, false, threadIdx.x);
   const R scale = (R)(1.0 / ((double)g.Nx * (double)g.Ny));
   for (int i = threadIdx.x; i < nseq * nkx; i += kThreads) {
     int s = i / nkx, k = i % nkx;
-    C z = buf[s * Nx + k], zc = buf[s * Nx + ((Nx - k) & (Nx - 1))];
+    C z = buf[rowpad_ix(s, k, Nx)], zc = buf[rowpad_ix(s, (Nx - k) & (Nx - 1), Nx)];
     zc.y = -zc.y;
     C a, b;
     a.x = (R)0.5 * (z.x + zc.x) * scale;
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
                                                          const typename CT<R>::T* __restrict__ pz, R* __restrict__ u4,
                                                          int64_t nrows, const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
-  __shared__ C buf[kElems];
+  __shared__ C buf[kElems + kElems / 8];
   __shared__ C tw[512];
   const int Nx = g.Nx, logN = ilog2(Nx), nkx = g.nkx;
   const int nrow_blk = kElems / (2 * Nx);  // rows per block (2 sequences per row)
@@ -298,16 +298,16 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
       z1.x = a.x - ex.y; z1.y = a.y + ex.x;
       z2.x = b.x - ez.y; z2.y = b.y + ez.x;
     }
-    buf[(2 * rl) * Nx + pos] = z1;
-    buf[(2 * rl + 1) * Nx + pos] = z2;
+    buf[rowpad_ix(2 * rl, pos, Nx)] = z1;
+    buf[rowpad_ix(2 * rl + 1, pos, Nx)] = z2;
   }
   __syncthreads();
-  fft_lds_r22<C, false, kElems / 4 / kThreads, kThreads>(buf, logN, ilog2(2 * nrow_blk), Nx, 1, tw, true, threadIdx.x);
+  fft_rows_r8<C, kThreads>(buf, logN, tw, true, threadIdx.x);
   using V = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
   V* out = reinterpret_cast<V*>(u4);
   for (int i = threadIdx.x; i < nr * Nx; i += kThreads) {
     int rl = i / Nx, x = i % Nx;
-    C z1 = buf[(2 * rl) * Nx + x], z2 = buf[(2 * rl + 1) * Nx + x];
+    C z1 = buf[rowpad_ix(2 * rl, x, Nx)], z2 = buf[rowpad_ix(2 * rl + 1, x, Nx)];
     V v;
     v.x = z1.x; v.y = z1.y; v.z = z2.x; v.w = z2.y;
     out[(size_t)(r_base + rl) * Nx + x] = v;

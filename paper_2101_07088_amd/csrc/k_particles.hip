@@ -431,12 +431,19 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
             for (int s = off[c] + (BY_CELL ? 0 : sub); s < off[c + 1]; s += (BY_CELL ? 1 : L)) {
               if (fam == 0 && s == t) continue;
               const Part o = srt[s];
+              // minimal image: the coordinates were wrapped into [0, L), so
+              // |dx| < L and one shift at most (no division)
               double dx = me.x - o.x, dy = me.y - o.y;
-              dx -= g.Lx * rint(dx / g.Lx);
-              dy -= g.Ly * rint(dy / g.Ly);
+              if (dx > 0.5 * g.Lx) dx -= g.Lx;
+              else if (dx < -0.5 * g.Lx) dx += g.Lx;
+              if (dy > 0.5 * g.Ly) dy -= g.Ly;
+              else if (dy < -0.5 * g.Ly) dy += g.Ly;
               const double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
               double dz = me.z - zs;
-              if (tp) dz -= g.H * rint(dz / g.H);
+              if (tp) {
+                if (dz > 0.5 * g.H) dz -= g.H;
+                else if (dz < -0.5 * g.H) dz += g.H;
+              }
               near_pair<R>(g, dx, dy, dz, qf * o.q, ph, ex, ey, ez);
             }
           }
