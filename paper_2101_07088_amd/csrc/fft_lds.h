@@ -336,3 +336,140 @@ __device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid
 }
 
 }  // namespace dpse
+
+namespace dpse {
+
+// Column-interleaved batches: 2^logS sequences (columns) of length M = 2^logM
+// stored row by row, element k of sequence s at colpad_ix(k, s) (with fewer
+// than 32 columns, one padding element every 2^ps rows, ps = colpad_shift: the
+// passes below then stay off shared banks). Input in bit-reversed order, output
+// natural; tw[k] = exp(-2 pi i k / M), k < M/2 (conjugated when inverse).
+// Radix-2^3 passes (two stages where the count requires, as fft_rows_r8), on
+// one buffer or on two in lockstep (PAIR); with fewer than 32 columns the first
+// pass gives a wave consecutive groups of one column. M 2^logS == KE.
+template <typename C>
+__device__ __forceinline__ int colpad_shift(int logS) {
+  return logS >= 5 ? 30 : (sizeof(C) == 8 ? 3 : 4);
+}
+__device__ __forceinline__ int colpad_ix(int k, int s, int logS, int ps) { return (k << logS) + s + (k >> ps); }
+// LDS elements a column-interleaved buffer of KE elements takes with padding
+template <typename C>
+constexpr int colpad_elems(int KE) { return KE + 1024 / (sizeof(C) == 8 ? 8 : 16); }
+
+template <typename C, int KE, int NTHR, bool PAIR>
+__device__ void fft_cols_r8(C* A, C* B, int logM, int logS, const C* tw, bool inverse, int tid) {
+  using Rr = decltype(C{}.x);
+  static_assert(KE % (8 * NTHR) == 0, "whole radix-8 groups per thread");
+  const int M = 1 << logM, S = 1 << logS, ps = colpad_shift<C>(logS);
+  const bool gfirst = logS < 5;
+  auto pass8 = [&](int lh, bool gfast) {
+    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1, ts3 = ts1 >> 2;
+    const int logG = logM - 3;
+#pragma nounroll
+    for (int q = 0; q < KE / (8 * NTHR); ++q) {
+    const int t = tid + q * NTHR;
+    int s, b;
+    if (gfast) {
+      b = t & ((1 << logG) - 1);
+      s = t >> logG;
+    } else {
+      s = t & (S - 1);
+      b = t >> logS;
+    }
+    const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 3)) + pos;
+    C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+    if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+    const Rr r2 = (Rr)0.70710678118654752440;
+    const Rr sg = inverse ? (Rr)-1 : (Rr)1;
+    C w2m, w3e[4];
+    w2m.x = sg * w2.y;
+    w2m.y = -sg * w2.x;
+    w3e[0] = w3;
+    w3e[1].x = r2 * (w3.x + sg * w3.y);
+    w3e[1].y = r2 * (w3.y - sg * w3.x);
+    w3e[2].x = sg * w3.y;
+    w3e[2].y = -sg * w3.x;
+    w3e[3].x = r2 * (sg * w3.y - w3.x);
+    w3e[3].y = -r2 * (sg * w3.x + w3.y);
+    constexpr int NB = PAIR ? 2 : 1;
+    C v[NB][8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ix = colpad_ix(k0 + e * half, s, logS, ps);
+      v[0][e] = A[ix];
+      if (PAIR) v[NB - 1][e] = B[ix];
+    }
+#pragma unroll
+    for (int bi = 0; bi < NB; ++bi) {
+      C* u = v[bi];
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const C t = cmul(u[e + 1], w1);
+        u[e + 1] = csub(u[e], t);
+        u[e] = cadd(u[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (e & 2) continue;
+        const C t = cmul(u[e + 2], (e & 1) ? w2m : w2);
+        u[e + 2] = csub(u[e], t);
+        u[e] = cadd(u[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const C t = cmul(u[e + 4], w3e[e]);
+        u[e + 4] = csub(u[e], t);
+        u[e] = cadd(u[e], t);
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int ix = colpad_ix(k0 + e * half, s, logS, ps);
+      A[ix] = v[0][e];
+      if (PAIR) B[ix] = v[NB - 1][e];
+    }
+    }
+    __syncthreads();
+  };
+  auto pass4 = [&](int lh) {
+    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1;
+#pragma nounroll
+    for (int q = 0; q < KE / (4 * NTHR); ++q) {
+      const int t = tid + q * NTHR, s = t & (S - 1), b = t >> logS;
+      const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 2)) + pos;
+      C x1 = tw[pos * ts1], x2 = tw[pos * ts2];
+      if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
+      constexpr int NB = PAIR ? 2 : 1;
+#pragma unroll
+      for (int bi = 0; bi < NB; ++bi) {
+        C* buf = bi == 0 ? A : B;
+        C a[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[e] = buf[colpad_ix(k0 + e * half, s, logS, ps)];
+        const C t1 = cmul(a[1], x1), t3 = cmul(a[3], x1);
+        const C b0 = cadd(a[0], t1), b1 = csub(a[0], t1);
+        const C b2 = cadd(a[2], t3), b3 = csub(a[2], t3);
+        const C u2 = cmul(b2, x2);
+        C u3 = cmul(b3, x2);  // times -i (forward) or +i (inverse)
+        {
+          const auto re = u3.x;
+          if (inverse) { u3.x = -u3.y; u3.y = re; }
+          else { u3.x = u3.y; u3.y = -re; }
+        }
+        buf[colpad_ix(k0, s, logS, ps)] = cadd(b0, u2);
+        buf[colpad_ix(k0 + 2 * half, s, logS, ps)] = csub(b0, u2);
+        buf[colpad_ix(k0 + half, s, logS, ps)] = cadd(b1, u3);
+        buf[colpad_ix(k0 + 3 * half, s, logS, ps)] = csub(b1, u3);
+      }
+    }
+    __syncthreads();
+  };
+  const int n8 = logM % 3 == 0 ? logM / 3 : (logM % 3 == 1 ? (logM - 4) / 3 : (logM - 2) / 3);
+  const int n4 = (logM - 3 * n8) / 2;
+#pragma nounroll
+  for (int p = 0; p < n8; ++p) pass8(3 * p, p == 0 && gfirst);
+#pragma nounroll
+  for (int p = 0; p < n4; ++p) pass4(3 * n8 + 2 * p);
+}
+
+}  // namespace dpse

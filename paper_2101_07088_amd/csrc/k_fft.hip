@@ -17,11 +17,13 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kElems = 2048;  // complex elements per LDS FFT buffer (x passes)
-// y passes: 2048 complex elements per LDS buffer, a block spanning
-// KB = kYElems / Ny consecutive kx columns (row pieces of KB values; the
-// XCD-aware block order keeps the neighbours that share their lines in one L2)
+// y passes: kYElems complex elements per LDS buffer in blocks of kYThreads, a
+// block spanning KB = kYElems / Ny consecutive kx columns (row pieces of KB
+// values, 64 B; the XCD-aware block order keeps the neighbours that share
+// their lines in one L2)
 template <typename R>
-constexpr int kYElems = sizeof(R) == 4 ? 4096 : 2048;
+constexpr int kYElems = sizeof(R) == 4 ? 8192 : 4096;
+constexpr int kYThreads = 512;
 
 template <typename R>
 struct CT;
@@ -114,17 +116,45 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
   }
 }
 
+// Where thread t's values of a y-pass block go. Value q (of kPer) belongs to
+// column kl = t mod KB and LDS slot p = t / KB + q step (step = kYThreads / KB
+// = Ny / kPer rows), which holds row bitrev(p) = rev_t + bitrev(q) on input
+// (the top bits of p are q's) and row p on output. The LDS index is
+// lds0 + q lds_step: step is a multiple of the padding period wherever
+// there is padding.
+template <typename C, int kPer>
+struct YMap {
+  int kl, row_in, row_out, step, lds0, lds_step;
+  __device__ YMap(int t, int logN, int logKB, int ps) {
+    constexpr int logQ = kPer == 16 ? 4 : (kPer == 8 ? 3 : 2);
+    static_assert((1 << logQ) == kPer, "kPer a power of two");
+    const int a = t >> logKB;
+    kl = t & ((1 << logKB) - 1);
+    step = kYThreads >> logKB;
+    row_out = a;
+    row_in = bitrev(a, logN);
+    lds0 = colpad_ix(a, kl, logKB, ps);
+    lds_step = kYThreads + (step >> ps);
+  }
+  static __device__ constexpr int rev(int q) {
+    constexpr int logQ = kPer == 16 ? 4 : (kPer == 8 ? 3 : 2);
+    int r = 0;
+    for (int b = 0; b < logQ; ++b) r |= ((q >> b) & 1) << (logQ - 1 - b);
+    return r;
+  }
+};
+
 // Forward C2C along y, in place, for the plane ranges of J.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, const FftJobs<R> J,
+__global__ void __launch_bounds__(kYThreads) k_fft_y(Geom g, const FftJobs<R> J,
                                                     const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
   constexpr int KE = kYElems<R>;
-  constexpr int kPer = KE / kThreads;
-  __shared__ C buf[KE];
+  constexpr int kPer = KE / kYThreads;
+  __shared__ C buf[colpad_elems<C>(KE)];
   __shared__ C tw[512];
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
-  const int KB = KE / Ny, logKB = ilog2(KB);
+  const int KB = KE / Ny, logKB = ilog2(KB), ps = colpad_shift<C>(logKB);
   const int nblk = (nkx + KB - 1) / KB;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int js = job_of(J, blk);
@@ -132,116 +162,108 @@ __global__ void __launch_bounds__(kThreads) k_fft_y(Geom g, const FftJobs<R> J,
   const int lb = blk - pick3(J.first, js);
   const int plane = pick3(J.lo, js) + lb / nblk;
   const int kb = (lb % nblk) * KB;
-  for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
-  C* base = data + (size_t)plane * Ny * nkx;
-  // slot p of column kl takes row ky = bitrev(p): every row piece is read
-  // on its own, so the reversal costs the loads nothing and the LDS stores
-  // run in order
+  for (int i = threadIdx.x; i < Ny / 2; i += kYThreads) tw[i] = twg[i];
+  // rows in bit-reversed order into the LDS slots (every row piece is read
+  // on its own, so the reversal costs the loads nothing)
+  const YMap<C, kPer> m(threadIdx.x, logN, logKB, ps);
+  const bool valid = kb + m.kl < nkx;
+  C* base = data + (size_t)plane * Ny * nkx + kb + m.kl;
+  const C* src = base + (size_t)m.row_in * nkx;
   C v[kPer];
+  if (valid) {
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = bitrev(i >> logKB, logN), kl = i & (KB - 1);
-    v[q].x = 0; v[q].y = 0;
-    if (kb + kl < nkx) v[q] = base[(size_t)ky * nkx + kb + kl];
+    for (int q = 0; q < kPer; ++q) v[q] = src[(size_t)YMap<C, kPer>::rev(q) * nkx];
+  } else {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) { v[q].x = 0; v[q].y = 0; }
   }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) buf[threadIdx.x + q * kThreads] = v[q];
+  for (int q = 0; q < kPer; ++q) buf[m.lds0 + q * m.lds_step] = v[q];
   __syncthreads();
-  fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf, logN, logKB, 1, KB, tw, false, threadIdx.x);
+  fft_cols_r8<C, KE, kYThreads, false>(buf, nullptr, logN, logKB, tw, false, threadIdx.x);
+  if (valid) {
+    C* dst = base + (size_t)m.row_out * nkx;
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-    if (kb + kl < nkx) base[(size_t)ky * nkx + kb + kl] = buf[ky * KB + kl];
+    for (int q = 0; q < kPer; ++q) dst[(size_t)q * m.step * nkx] = buf[m.lds0 + q * m.lds_step];
   }
 }
 
 // Inverse C2C along y: (Psi, Psi_z) -> (P0 = Psi, PY = -i ky Psi, PZ = Psi_z),
-// y-transformed. Psi and Psi_z are read once into registers. In FP32 the
-// transforms of Psi and -i ky Psi run in lockstep in two LDS buffers, then
-// Psi_z's; in FP64 (where the pair measured slower) the three take turns in
-// one buffer.
+// y-transformed. The three transforms take turns in one LDS buffer (two
+// buffers, with Psi's and -i ky Psi's transforms in lockstep, would leave room
+// for one block per CU); Psi stays in registers for -i ky Psi, and Psi_z's
+// loads are issued when Psi's registers are free, ahead of the second transform.
 template <typename R>
-__global__ void __launch_bounds__(kThreads) k_ifft_y(Geom g, const typename CT<R>::T* __restrict__ psi,
-                                                     const typename CT<R>::T* __restrict__ psiz,
-                                                     typename CT<R>::T* p0, typename CT<R>::T* py,
-                                                     typename CT<R>::T* pz,
-                                                     const typename CT<R>::T* __restrict__ twg) {
+__global__ void __launch_bounds__(kYThreads) k_ifft_y(Geom g, const typename CT<R>::T* __restrict__ psi,
+                                                      const typename CT<R>::T* __restrict__ psiz,
+                                                      typename CT<R>::T* p0, typename CT<R>::T* py,
+                                                      typename CT<R>::T* pz,
+                                                      const typename CT<R>::T* __restrict__ twg) {
   using C = typename CT<R>::T;
   constexpr int KE = kYElems<R>;
-  constexpr int kPer = KE / kThreads;
-  constexpr bool kPair = sizeof(R) == 4;
-  __shared__ C buf0[KE];
-  __shared__ C buf1[kPair ? KE : 1];
+  constexpr int kPer = KE / kYThreads;
+  __shared__ C buf[colpad_elems<C>(KE)];
   __shared__ C tw[512];
   const int Ny = g.Ny, logN = ilog2(Ny), nkx = g.nkx;
-  const int KB = KE / Ny, logKB = ilog2(KB);
+  const int KB = KE / Ny, logKB = ilog2(KB), ps = colpad_shift<C>(logKB);
   const int nblk = (nkx + KB - 1) / KB;
   const int blk = xcd_block(blockIdx.x, gridDim.x);
   const int plane = blk / nblk;
   const int kb = (blk % nblk) * KB;
-  for (int i = threadIdx.x; i < Ny / 2; i += kThreads) tw[i] = twg[i];
-  const size_t off = (size_t)plane * Ny * nkx;
-  // slot p of column kl takes row ky = bitrev(p) (separate row pieces: the
-  // reversal costs the loads nothing, the LDS stores run in order)
-  C a[kPer], c[kPer];
+  for (int i = threadIdx.x; i < Ny / 2; i += kYThreads) tw[i] = twg[i];
+  // rows in bit-reversed order into the LDS slots (separate row pieces: the
+  // reversal costs the loads nothing)
+  const YMap<C, kPer> m(threadIdx.x, logN, logKB, ps);
+  const bool valid = kb + m.kl < nkx;
+  const size_t off = (size_t)plane * Ny * nkx + kb + m.kl;
+  const size_t in0 = off + (size_t)m.row_in * nkx, out0 = off + (size_t)m.row_out * nkx;
+  auto load = [&](C (&v)[kPer], const C* __restrict__ src) {
+    if (valid) {
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, ky = bitrev(i >> logKB, logN), kl = i & (KB - 1);
-    a[q].x = 0; a[q].y = 0; c[q].x = 0; c[q].y = 0;
-    if (kb + kl < nkx) {
-      a[q] = psi[off + (size_t)ky * nkx + kb + kl];
-      c[q] = psiz[off + (size_t)ky * nkx + kb + kl];
+      for (int q = 0; q < kPer; ++q) v[q] = src[in0 + (size_t)YMap<C, kPer>::rev(q) * nkx];
+    } else {
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) { v[q].x = 0; v[q].y = 0; }
     }
-  }
+  };
   const double kyf = 2.0 * kPi / g.Ly;
-  // -i ky Psi at slot i
-  auto dy = [&](int i, C v) -> C {
-    const int ky = bitrev(i >> logKB, logN);
-    const int ny = ky < Ny / 2 ? ky : ky - Ny;
-    const R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
-    C d;
-    d.x = kyv * v.y;
-    d.y = -kyv * v.x;
-    return d;
-  };
-  auto store = [&](C* dst, const C* src) {
+  auto put = [&](const C (&v)[kPer], bool deriv) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int i = threadIdx.x + q * kThreads, ky = i >> logKB, kl = i & (KB - 1);
-      if (kb + kl < nkx) dst[off + (size_t)ky * nkx + kb + kl] = src[i];
-    }
-  };
-  if constexpr (kPair) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int i = threadIdx.x + q * kThreads;
-      buf0[i] = a[q];
-      buf1[i] = dy(i, a[q]);
-    }
-    __syncthreads();
-    fft_lds_r22_pair<C, true, KE / 4 / kThreads, kThreads>(buf0, buf1, logN, logKB, 1, KB, tw, true, threadIdx.x);
-    store(p0, buf0);
-    store(py, buf1);
-  } else {
-#pragma nounroll
-    for (int f = 0; f < 2; ++f) {
-#pragma unroll
-      for (int q = 0; q < kPer; ++q) {
-        const int i = threadIdx.x + q * kThreads;
-        buf0[i] = f == 0 ? a[q] : dy(i, a[q]);
+      C d = v[q];
+      if (deriv) {  // -i ky Psi
+        const int ky = m.row_in + YMap<C, kPer>::rev(q);
+        const int ny = ky < Ny / 2 ? ky : ky - Ny;
+        const R kyv = (ky == Ny / 2) ? (R)0 : (R)(kyf * ny);
+        d.x = kyv * v[q].y;
+        d.y = -kyv * v[q].x;
       }
-      __syncthreads();
-      fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf0, logN, logKB, 1, KB, tw, true, threadIdx.x);
-      store(f == 0 ? p0 : py, buf0);
-      __syncthreads();
+      buf[m.lds0 + q * m.lds_step] = d;
     }
-  }
-  __syncthreads();
+  };
+  auto store = [&](C* dst) {
+    if (valid) {
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) buf0[threadIdx.x + q * kThreads] = c[q];
+      for (int q = 0; q < kPer; ++q) dst[out0 + (size_t)q * m.step * nkx] = buf[m.lds0 + q * m.lds_step];
+    }
+  };
+  C v[kPer];
+  load(v, psi);
+  put(v, false);
   __syncthreads();
-  fft_lds_r22<C, true, KE / 4 / kThreads, kThreads>(buf0, logN, logKB, 1, KB, tw, true, threadIdx.x);
-  store(pz, buf0);
+  fft_cols_r8<C, KE, kYThreads, false>(buf, nullptr, logN, logKB, tw, true, threadIdx.x);
+  store(p0);
+  __syncthreads();
+  put(v, true);
+  load(v, psiz);
+  __syncthreads();
+  fft_cols_r8<C, KE, kYThreads, false>(buf, nullptr, logN, logKB, tw, true, threadIdx.x);
+  store(py);
+  __syncthreads();
+  put(v, false);
+  __syncthreads();
+  fft_cols_r8<C, KE, kYThreads, false>(buf, nullptr, logN, logKB, tw, true, threadIdx.x);
+  store(pz);
 }
 
 // Inverse C2R along x: rows of (P0, PY, PZ) -> u4[row][x] = (phi, Ex, Ey, Ez).
@@ -368,7 +390,7 @@ void launch_x(dpse_plan* p, const FftJobs<R>& J) {
 template <typename R>
 void launch_y(dpse_plan* p, const FftJobs<R>& J) {
   if (J.n > 0)
-    hipLaunchKernelGGL(k_fft_y<R>, dim3(J.first[J.n]), dim3(kThreads), 0, p->stream, p->g, J, twy<R>(p));
+    hipLaunchKernelGGL(k_fft_y<R>, dim3(J.first[J.n]), dim3(kYThreads), 0, p->stream, p->g, J, twy<R>(p));
 }
 
 }  // namespace
@@ -402,7 +424,7 @@ hipError_t launch_fft_inverse(dpse_plan* p) {
   const Geom& g = p->g;
   int KB = kYElems<R> / g.Ny;
   int nblk = (g.nkx + KB - 1) / KB;
-  hipLaunchKernelGGL(k_ifft_y<R>, dim3(nblk * g.Nz), dim3(kThreads), 0, p->stream, g, (const C*)p->w.psi,
+  hipLaunchKernelGGL(k_ifft_y<R>, dim3(nblk * g.Nz), dim3(kYThreads), 0, p->stream, g, (const C*)p->w.psi,
                      (const C*)p->w.psiz, (C*)p->w.p0, (C*)p->w.py, (C*)p->w.pz, twy<R>(p));
   int64_t nrows = (int64_t)g.Nz * g.Ny;
   int rows_per = kElems / (2 * g.Nx);
