@@ -308,7 +308,9 @@ def bench_batch(dp, torch, steps, n_sys=64, n_branches=8):
     out.update({"sequential_fp64_evals_per_s": n_total / t_seq64, "sequential_fp64_ms": 1e3 * t_seq64})
     br = BatchRunner(tens, precision=dp.DPSE_MIXED, n_branches=n_branches, use_graph=True)
     t_b = timed(br, steps)
-    out.update({"evals_per_s": n_total / t_b, "ms_per_batch": 1e3 * t_b,
+    grid_points = sum(p.Nx * p.Ny * p.Nz for p, _, _ in systems)
+    out.update({"grid_points": grid_points, "grid_points_per_s": grid_points / t_b,
+                "evals_per_s": n_total / t_b, "ms_per_batch": 1e3 * t_b,
                 "sequential_evals_per_s": n_total / t_seq, "sequential_ms": 1e3 * t_seq,
                 "speedup_vs_sequential": t_seq / t_b, "speedup_vs_sequential_fp64": t_seq64 / t_b,
                 "arena_bytes": br.workspace_bytes})
@@ -476,7 +478,7 @@ def bench_walls(dp, torch, steps):
             "mixed_vs_fp64_rel_energy": abs(rw["U"] - r64["U"]) / abs(r64["U"])}
 
 
-def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_slots=8, max_queue=256):
+def bench_serve(dp, torch, rate, duration, warm, n_traj=256, budget_gb=16.0, n_slots=4, max_queue=256):
     """Serving stream: Poisson arrivals of solves from n_traj Brownian-like
     trajectories (N log-uniform in [512, 262144], box and permittivities
     fixed per trajectory, each request moves every charge by N(0, 0.05^2)
@@ -662,6 +664,8 @@ def main(argv=None):
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-duration", type=float, default=10.0)
     ap.add_argument("--serve-warmup", type=float, default=1.0)
+    ap.add_argument("--serve-slots", type=int, default=4,
+                    help="concurrent requests of the serving stream (execution slots, one stream each)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one device copy of this many MiB first (calibrates HBM byte counters)")
     a = ap.parse_args(argv)
@@ -744,6 +748,9 @@ def main(argv=None):
                                         "frac": v / (r["stages"][k] * 1e-3) / 1e9 / HBM_PEAK_GBS}
                                     for k, v in sb.items()}},
         "workspace_bytes": r["workspace_bytes"],
+        # grid points solved per second: the batch line's figure of the same kind
+        # tells whether its 64 small systems keep the chip as busy as one large one
+        "grid_points_per_s": p.Nx * p.Ny * p.Nz / (r["wall_s"] / steps),
     }
     for prec, rr in res.items():
         line[f"{prec}_evals_per_s"] = n / (rr["wall_s"] / rr["steps"])
@@ -775,13 +782,13 @@ def main(argv=None):
         line["batch"] = bench_batch(dp, torch, a.steps, n_branches=a.batch_branches)
         print(f"[bench] batch: {line['batch']}", file=sys.stderr, flush=True)
     if a.serve:
-        line["serving"] = bench_serve(dp, torch, a.serve_rate, a.serve_duration, a.serve_warmup)
+        line["serving"] = bench_serve(dp, torch, a.serve_rate, a.serve_duration, a.serve_warmup, n_slots=a.serve_slots)
         print(f"[bench] serving: {line['serving']}", file=sys.stderr, flush=True)
         cap = line["serving"]["served_req_s"]
         if a.serve_rate > 0.8 * cap:
             # the offered stream exceeds what one GPU serves: also report latency at 70% of that capacity
             line["serving_at_70pct_capacity"] = bench_serve(dp, torch, 0.7 * cap, a.serve_duration / 2,
-                                                            a.serve_warmup)
+                                                            a.serve_warmup, n_slots=a.serve_slots)
             print(f"[bench] serving at 70%: {line['serving_at_70pct_capacity']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, pos, q)

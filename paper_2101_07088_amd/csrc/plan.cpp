@@ -924,25 +924,28 @@ int dpse_solve_batch(int n_sys, dpse_plan* const* plans, const int64_t* n,
     if (n[i] <= 0) return DPSE_EINVAL;
     if (n[i] > plans[i]->max_n) return DPSE_ETOOMANY;
   }
+  // Each solve is independent. Solves of plans on stream 0 (the first plan's)
+  // run in order on it; the others run on their own streams, and stream 0
+  // waits for each of them through an event, so that the whole batch is done
+  // when stream 0's work is. The events are released on every return.
   hipStream_t s0 = plans[0]->stream;
-  hipEvent_t ev = nullptr;
-  // every plan's stream first waits for the work already queued on stream 0's
-  // timeline is not required: each solve is independent. Solves of plans that
-  // share s0 run in order; the others run on their own streams and s0 waits.
   std::vector<hipEvent_t> done;
-  for (int i = 0; i < n_sys; ++i) {
-    int st = solve_impl(plans[i], n[i], pos[i], q[i], energy ? energy[i] : nullptr,
+  int status = DPSE_OK;
+  for (int i = 0; i < n_sys && status == DPSE_OK; ++i) {
+    status = solve_impl(plans[i], n[i], pos[i], q[i], energy ? energy[i] : nullptr,
                         phi ? phi[i] : nullptr, force ? force[i] : nullptr);
-    if (st != DPSE_OK) return st;
-    if (plans[i]->stream != s0) {
-      if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return DPSE_EHIP;
-      if (hipEventRecord(ev, plans[i]->stream) != hipSuccess) return DPSE_EHIP;
-      if (hipStreamWaitEvent(s0, ev, 0) != hipSuccess) return DPSE_EHIP;
-      done.push_back(ev);
+    if (status != DPSE_OK || plans[i]->stream == s0) continue;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      status = DPSE_EHIP;
+      break;
     }
+    done.push_back(ev);
+    if (hipEventRecord(ev, plans[i]->stream) != hipSuccess || hipStreamWaitEvent(s0, ev, 0) != hipSuccess)
+      status = DPSE_EHIP;
   }
   for (hipEvent_t d : done) (void)hipEventDestroy(d);
-  return DPSE_OK;
+  return status;
 }
 
 // Tuned launch shapes: stage 0 spreading tiles, 1 interpolation tiles, 2

@@ -65,15 +65,23 @@ class Request:
 
 
 class DpseBackend:
-    """Runs admitted requests with libdpse on a set of HIP streams."""
+    """Runs admitted requests with libdpse on a set of HIP streams.
 
-    def __init__(self, precision: int, device=None):
+    With autotune, the first request of every grid shape (Nx, Ny, Nz,
+    support) tunes the launch shapes of spreading, interpolation and the
+    column kernel on its own charges (dpse_plan_autotune, synchronous, before
+    its solve is queued); every later plan of that shape takes the stored
+    choice once."""
+
+    def __init__(self, precision: int, device=None, autotune: bool = True):
         import torch
         from . import native
         self.torch = torch
         self.native = native
         self.precision = precision
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self.autotune = autotune
+        self.tiles = {}        # grid shape -> tuned choice
 
     def make_streams(self, n: int):
         return [self.torch.cuda.Stream(device=self.device) for _ in range(n)]
@@ -94,6 +102,14 @@ class DpseBackend:
             PH = torch.empty(req.n, dtype=torch.float64, device=self.device)
             F = torch.empty((req.n, 3), dtype=torch.float64, device=self.device)
             plan.bind(ws, stream)
+            if self.autotune and not getattr(plan, "_serve_tuned", False):
+                p = plan.params
+                key = (p.Nx, p.Ny, p.Nz, plan.info["support"])
+                if key in self.tiles:
+                    plan.set_tiles(self.tiles[key])
+                else:
+                    self.tiles[key], _ = plan.autotune(req.pos, req.q, reps=2)
+                plan._serve_tuned = True
             plan.solve(req.pos, req.q, E, PH, F)
             ev = torch.cuda.Event()
             ev.record(stream)
@@ -119,10 +135,10 @@ class Server:
     """Continuous-batching request loop (see the module docstring)."""
 
     def __init__(self, budget_bytes: int, n_slots: int = 8, backend=None, precision: Optional[int] = None,
-                 clock: Callable[[], float] = time.perf_counter, max_queue: int = 1 << 30):
+                 clock: Callable[[], float] = time.perf_counter, max_queue: int = 1 << 30, autotune: bool = True):
         if backend is None:
             from .native import DPSE_MIXED
-            backend = DpseBackend(DPSE_MIXED if precision is None else precision)
+            backend = DpseBackend(DPSE_MIXED if precision is None else precision, autotune=autotune)
         self.backend = backend
         self.budget = int(budget_bytes)
         self.clock = clock

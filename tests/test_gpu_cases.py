@@ -89,6 +89,26 @@ def test_only_inner_charges_and_only_wall_charges():
     check(p, pos, q, 1e-9, label="bottom band only")
 
 
+@pytest.mark.parametrize("nz,H,precs", [(513, 24.0, (0, 1)), (1025, 48.0, (0,))])
+def test_tall_slabs_beyond_the_scan_column_range(nz, H, precs):
+    """N_z above 257 takes the general column kernel (the scan kernel covers
+    33 <= N_z <= 257); 513 and the largest accepted N_z, 1025, against the oracle."""
+    _need_gpu()
+    p = W.SlabParams(Lx=8.0, Ly=8.0, H=H, eps=1.0, eps_b=0.05, eps_t=20.0, xi=1.0, Nx=32, Ny=32, Nz=nz, r_cut=3.0)
+    pos, q = W.charges(nz, 30, 30, 8.0, 8.0, 0.5, H - 0.5)
+    print(f"[case] tall slab 32x32x{nz}: oracle solve ...", flush=True)
+    U0, phi0, F0, _ = O.solve(p, pos, q)
+    for prec, tol in ((0, 1e-9), (1, 1e-5)):
+        if prec not in precs:
+            continue
+        _, st, U, phi, F = run(p, pos, q, prec)
+        assert st == 0
+        eF, ep = rel_rms(F, F0), rel_rms(phi, phi0)
+        print(f"[case] tall slab Nz={nz} prec={prec} relRMS F {eF:.2e} phi {ep:.2e}", flush=True)
+        assert eF < tol and ep < tol
+        assert abs(U - U0) < tol * 0.5 * np.sum(np.abs(q * phi0))
+
+
 def test_gaussian_charges_and_gauge_off():
     _need_gpu()
     p, pos, q = small_jump(6, 50)
