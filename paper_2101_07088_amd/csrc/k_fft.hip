@@ -77,26 +77,60 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
   const int64_t r_base = row0 + (int64_t)(blockIdx.x - pick3(J.first, js)) * 2 * nseq;
   const int nr = (int)min((int64_t)2 * nseq, row0 + nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
-  // slot p of sequence s (nseq * Nx == kElems) takes x = bitrev(p) of rows
-  // 2s and 2s + 1: the bit reversal is a gather within the row's 128-byte
-  // lines and the LDS stores run in order (no bank conflicts); all global
-  // loads of the thread are issued before the LDS stores
-  constexpr int kPer = kElems / kThreads;
-  R v0[kPer], v1[kPer];
+  if constexpr (sizeof(R) == 4) {
+    // slot p of sequence s (nseq * Nx == kElems) takes x = bitrev(p) of rows
+    // 2s and 2s + 1. Each thread loads 4 consecutive x of both rows (16-byte
+    // loads, consecutive across the lanes) and stores them to the slots
+    // bitrev(x + j) = bitrev(x) + bitrev(j) Nx / 4, which the row padding
+    // keeps off shared banks
+    constexpr int kQ = kElems / 4 / kThreads;
+    const int nq = Nx >> 2;
+    float4 v0[kQ], v1[kQ];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, s = i >> logN, x = bitrev(i & (Nx - 1), logN);
-    const int64_t r = r_base + 2 * s;
-    v0[q] = 2 * s < nr ? in[r * Nx + x] : (R)0;
-    v1[q] = 2 * s + 1 < nr ? in[(r + 1) * Nx + x] : (R)0;
-  }
+    for (int q = 0; q < kQ; ++q) {
+      const int gq = threadIdx.x + q * kThreads, s = gq / nq, u = gq - s * nq;
+      const int64_t r = r_base + 2 * s;
+      v0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+      v1[q] = v0[q];
+      if (2 * s < nr) v0[q] = *reinterpret_cast<const float4*>(in + r * Nx + 4 * u);
+      if (2 * s + 1 < nr) v1[q] = *reinterpret_cast<const float4*>(in + (r + 1) * Nx + 4 * u);
+    }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads;
-    C d;
-    d.x = v0[q];
-    d.y = v1[q];
-    buf[rowpad_ix(i >> logN, i & (Nx - 1), Nx)] = d;
+    for (int q = 0; q < kQ; ++q) {
+      const int gq = threadIdx.x + q * kThreads, s = gq / nq, u = gq - s * nq;
+      const int p = bitrev(4 * u, logN), qn = Nx >> 2;
+      C d;
+      d.x = v0[q].x; d.y = v1[q].x;
+      buf[rowpad_ix(s, p, Nx)] = d;
+      d.x = v0[q].y; d.y = v1[q].y;
+      buf[rowpad_ix(s, p + 2 * qn, Nx)] = d;
+      d.x = v0[q].z; d.y = v1[q].z;
+      buf[rowpad_ix(s, p + qn, Nx)] = d;
+      d.x = v0[q].w; d.y = v1[q].w;
+      buf[rowpad_ix(s, p + 3 * qn, Nx)] = d;
+    }
+  } else {
+    // slot p of sequence s (nseq * Nx == kElems) takes x = bitrev(p) of rows
+    // 2s and 2s + 1: the bit reversal is a gather within the row's 128-byte
+    // lines and the LDS stores run in order (no bank conflicts); all global
+    // loads of the thread are issued before the LDS stores
+    constexpr int kPer = kElems / kThreads;
+    R v0[kPer], v1[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, s = i >> logN, x = bitrev(i & (Nx - 1), logN);
+      const int64_t r = r_base + 2 * s;
+      v0[q] = 2 * s < nr ? in[r * Nx + x] : (R)0;
+      v1[q] = 2 * s + 1 < nr ? in[(r + 1) * Nx + x] : (R)0;
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads;
+      C d;
+      d.x = v0[q];
+      d.y = v1[q];
+      buf[rowpad_ix(i >> logN, i & (Nx - 1), Nx)] = d;
+    }
   }
   __syncthreads();
   fft_rows_r8<C, kThreads>(buf, logN, tw, false, threadIdx.x);
@@ -281,47 +315,98 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   const double kxf = 2.0 * kPi / g.Lx;
-  // nrow_blk * Nx == kElems / 2 slots; slot p of row rl takes k = bitrev(p)
-  // (a gather within the row's lines; LDS stores in order); all global loads
-  // of the thread are issued before the LDS stores
-  constexpr int kPer = kElems / 2 / kThreads;
-  C la[kPer], lb[kPer], lc[kPer];
+  // the two sequences of row rl at wavenumber k (slot bitrev(k)), formed from
+  // the stored half spectrum at kk = min(k, Nx - k) (conjugated for k > Nx/2):
+  // z1 = phi_hat + i Ex_hat, z2 = Ey_hat + i Ez_hat, Ex_hat = -i kx phi_hat,
+  // Ez_hat = -Psi_z_hat
+  auto seqs = [&](C a, C b, C c, int kk, bool cj, C& z1, C& z2) {
+    if (kk == 0 || kk == Nx / 2) { a.y = 0; b.y = 0; c.y = 0; }
+    const R kxv = (kk == Nx / 2) ? (R)0 : (R)(kxf * kk);
+    C ex;
+    ex.x = kxv * a.y;
+    ex.y = -kxv * a.x;
+    C ez;
+    ez.x = -c.x;
+    ez.y = -c.y;
+    if (cj) { a.y = -a.y; ex.y = -ex.y; b.y = -b.y; ez.y = -ez.y; }
+    z1.x = a.x - ex.y; z1.y = a.y + ex.x;
+    z2.x = b.x - ez.y; z2.y = b.y + ez.x;
+  };
+  if constexpr (sizeof(R) == 4) {
+    // each stored coefficient kk < Nx/2 is loaded once (consecutive across
+    // the lanes) and fills the slots of k = kk and k = Nx - kk; the Nyquist
+    // coefficients by one thread per row
+    constexpr int kQ = kElems / 4 / kThreads;
+    const int hx = Nx >> 1;
+    C la[kQ], lb[kQ], lc[kQ];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = bitrev(i & (Nx - 1), logN);
-    la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
-    if (rl < nr) {
-      const int kk = k <= Nx / 2 ? k : Nx - k;
-      const size_t o = (size_t)(r_base + rl) * nkx + kk;
-      la[q] = p0[o];
-      lb[q] = py[o];
-      lc[q] = pz[o];
+    for (int q = 0; q < kQ; ++q) {
+      const int gq = threadIdx.x + q * kThreads, rl = gq / hx, kk = gq - rl * hx;
+      la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
+      if (rl < nr) {
+        const size_t o = (size_t)(r_base + rl) * nkx + kk;
+        la[q] = p0[o];
+        lb[q] = py[o];
+        lc[q] = pz[o];
+      }
     }
-  }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int i = threadIdx.x + q * kThreads, rl = i >> logN, pos = i & (Nx - 1), k = bitrev(pos, logN);
-    C z1, z2;
-    z1.x = 0; z1.y = 0; z2.x = 0; z2.y = 0;
-    if (rl < nr) {
-      int kk = k <= Nx / 2 ? k : Nx - k;
-      bool cj = k > Nx / 2;
-      C a = la[q], b = lb[q], c = lc[q];
-      if (kk == 0 || kk == Nx / 2) { a.y = 0; b.y = 0; c.y = 0; }
-      R kxv = (kk == Nx / 2) ? (R)0 : (R)(kxf * kk);
-      C ex;  // -i kx a
-      ex.x = kxv * a.y;
-      ex.y = -kxv * a.x;
-      C ez;  // -Psi_z
-      ez.x = -c.x;
-      ez.y = -c.y;
-      if (cj) { a.y = -a.y; ex.y = -ex.y; b.y = -b.y; ez.y = -ez.y; }
-      // z1 = phi_hat + i Ex_hat, z2 = Ey_hat + i Ez_hat
-      z1.x = a.x - ex.y; z1.y = a.y + ex.x;
-      z2.x = b.x - ez.y; z2.y = b.y + ez.x;
+    for (int q = 0; q < kQ; ++q) {
+      const int gq = threadIdx.x + q * kThreads, rl = gq / hx, kk = gq - rl * hx;
+      C z1, z2;
+      seqs(la[q], lb[q], lc[q], kk, false, z1, z2);
+      const int p = bitrev(kk, logN);
+      buf[rowpad_ix(2 * rl, p, Nx)] = z1;
+      buf[rowpad_ix(2 * rl + 1, p, Nx)] = z2;
+      if (kk > 0) {
+        seqs(la[q], lb[q], lc[q], kk, true, z1, z2);
+        const int pm = bitrev(Nx - kk, logN);
+        buf[rowpad_ix(2 * rl, pm, Nx)] = z1;
+        buf[rowpad_ix(2 * rl + 1, pm, Nx)] = z2;
+      }
     }
-    buf[rowpad_ix(2 * rl, pos, Nx)] = z1;
-    buf[rowpad_ix(2 * rl + 1, pos, Nx)] = z2;
+    if (threadIdx.x < nrow_blk) {
+      const int rl = threadIdx.x;
+      C a, b, c;
+      a.x = 0; a.y = 0; b = a; c = a;
+      if (rl < nr) {
+        const size_t o = (size_t)(r_base + rl) * nkx + hx;
+        a = p0[o];
+        b = py[o];
+        c = pz[o];
+      }
+      C z1, z2;
+      seqs(a, b, c, hx, false, z1, z2);
+      buf[rowpad_ix(2 * rl, 1, Nx)] = z1;  // bitrev(Nx / 2) = 1
+      buf[rowpad_ix(2 * rl + 1, 1, Nx)] = z2;
+    }
+  } else {
+    // nrow_blk * Nx == kElems / 2 slots; slot p of row rl takes k = bitrev(p)
+    // (a gather within the row's lines; LDS stores in order); all global loads
+    // of the thread are issued before the LDS stores
+    constexpr int kPer = kElems / 2 / kThreads;
+    C la[kPer], lb[kPer], lc[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, rl = i >> logN, k = bitrev(i & (Nx - 1), logN);
+      la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
+      if (rl < nr) {
+        const int kk = k <= Nx / 2 ? k : Nx - k;
+        const size_t o = (size_t)(r_base + rl) * nkx + kk;
+        la[q] = p0[o];
+        lb[q] = py[o];
+        lc[q] = pz[o];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int i = threadIdx.x + q * kThreads, rl = i >> logN, pos = i & (Nx - 1), k = bitrev(pos, logN);
+      C z1, z2;
+      z1.x = 0; z1.y = 0; z2.x = 0; z2.y = 0;
+      if (rl < nr) seqs(la[q], lb[q], lc[q], k <= Nx / 2 ? k : Nx - k, k > Nx / 2, z1, z2);
+      buf[rowpad_ix(2 * rl, pos, Nx)] = z1;
+      buf[rowpad_ix(2 * rl + 1, pos, Nx)] = z2;
+    }
   }
   __syncthreads();
   fft_rows_r8<C, kThreads>(buf, logN, tw, true, threadIdx.x);
