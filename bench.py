@@ -49,7 +49,8 @@ def stage_bytes(p, beta, s):
     }
 
 
-SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4)]
+SPREAD_SHAPES = [(32, 4), (32, 8), (16, 4), (16, 8), (32, 2), (16, 2), (16, 8), (16, 4), (32, 8), (32, 4), (16, 16),
+                 (32, 16)]
 INTERP_SHAPES = [(16, 4), (16, 8), (32, 2), (32, 4), (16, 2), (16, 8), (16, 4), (0, 0)]
 COLUMN_SHAPES = [(2048, 256), (1024, 256), (4096, 256), (2048, 512), (4096, 512), (2048, 256)]  # (KE, threads)
 
@@ -160,7 +161,7 @@ def time_path(dp, torch, p, tpos, tq, precision, steps, warmup, walls=None, live
     torch.cuda.synchronize()
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     plan.sync()
-    out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]), tiles=tiles,
+    out = dict(wall_s=wall, lat_ms=lat, stages=stages, status=st, U=float(E.cpu()[0]), tiles=tiles, tile_ms=tile_ms,
                phi=PH.cpu().numpy(), F=F.cpu().numpy(), far=plan.debug(dp.Stage.FAR)[: len(tq)], info=plan.info,
                workspace_bytes=plan.info["workspace_bytes"])
     plan.close()
@@ -739,6 +740,9 @@ def main(argv=None):
         "latency_solves": int(len(r["lat_ms"])),
         "stages_ms": {k: round(v, 5) for k, v in r["stages"].items()},
         "tiles": {"spread": r["tiles"][0], "interp": r["tiles"][1], "column": r["tiles"][2]},
+        # the autotuner's timings of the candidate launch shapes that apply (ms per solve)
+        "tile_ms": {name: {i: round(float(v), 4) for (st, i), v in sorted(r["tile_ms"].items()) if st == s}
+                    for s, name in enumerate(("spread", "interp", "column"))},
         "accuracy": acc,
         "roofline": {"bound": "hbm", "kernel": dom_kernel or dom, "stage": dom, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,

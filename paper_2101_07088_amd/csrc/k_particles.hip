@@ -402,8 +402,8 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
     const bool xall = g.ncx < 3, yall = g.ncy < 3;
     if (xall) { xlo = 0; xhi = g.ncx - 1; }
     if (yall) { ylo = 0; yhi = g.ncy - 1; }
-    int visit = 0;  // running index of the visited cells (BY_CELL: this lane takes visit % L == sub)
     const bool tp = (g.flags & DPSE_TRIPLY) != 0;  // z periodic: wrapped cells, minimal image in z
+    const int nxc = xhi - xlo + 1, nyc = yhi - ylo + 1;
     // three source families: direct (mirror sign +1), bottom images, top images
     for (int fam = 0; fam < 3; ++fam) {
       double zt, qf;  // z of the point whose neighbours are searched; strength factor
@@ -420,33 +420,33 @@ __global__ void __launch_bounds__(kThreads) k_near(Geom g, int64_t n, const Part
         zlo = max(zlo, 0);
         zhi = min(zhi, g.ncz - 1);
       }
-      for (int oz = zlo; oz <= zhi; ++oz) {
+      // the family's cells, x fastest; with BY_CELL lane sub takes cells
+      // sub, sub + L, ... (all lanes of a group busy at once)
+      const int ncell = (zhi - zlo + 1) * nyc * nxc;
+      for (int v = BY_CELL ? sub : 0; v < ncell; v += BY_CELL ? L : 1) {
+        const int vyz = v / nxc, ox = xlo + (v - vyz * nxc);
+        const int oz = zlo + vyz / nyc, oy = ylo + (vyz - (vyz / nyc) * nyc);
         const int cz = !tp ? oz : (g.ncz < 3 ? oz : (cz0 + oz + g.ncz) % g.ncz);
-        for (int oy = ylo; oy <= yhi; ++oy) {
-          const int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
-          for (int ox = xlo; ox <= xhi; ++ox, ++visit) {
-            if (BY_CELL && visit % L != sub) continue;
-            const int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
-            const int c = (cz * g.ncy + yy) * g.ncx + xx;
-            for (int s = off[c] + (BY_CELL ? 0 : sub); s < off[c + 1]; s += (BY_CELL ? 1 : L)) {
-              if (fam == 0 && s == t) continue;
-              const Part o = srt[s];
-              // minimal image: the coordinates were wrapped into [0, L), so
-              // |dx| < L and one shift at most (no division)
-              double dx = me.x - o.x, dy = me.y - o.y;
-              if (dx > 0.5 * g.Lx) dx -= g.Lx;
-              else if (dx < -0.5 * g.Lx) dx += g.Lx;
-              if (dy > 0.5 * g.Ly) dy -= g.Ly;
-              else if (dy < -0.5 * g.Ly) dy += g.Ly;
-              const double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
-              double dz = me.z - zs;
-              if (tp) {
-                if (dz > 0.5 * g.H) dz -= g.H;
-                else if (dz < -0.5 * g.H) dz += g.H;
-              }
-              near_pair<R>(g, dx, dy, dz, qf * o.q, ph, ex, ey, ez);
-            }
+        const int yy = yall ? oy : (cy + oy + g.ncy) % g.ncy;
+        const int xx = xall ? ox : (cx + ox + g.ncx) % g.ncx;
+        const int c = (cz * g.ncy + yy) * g.ncx + xx;
+        for (int s = off[c] + (BY_CELL ? 0 : sub); s < off[c + 1]; s += (BY_CELL ? 1 : L)) {
+          if (fam == 0 && s == t) continue;
+          const Part o = srt[s];
+          // minimal image: the coordinates were wrapped into [0, L), so
+          // |dx| < L and one shift at most (no division)
+          double dx = me.x - o.x, dy = me.y - o.y;
+          if (dx > 0.5 * g.Lx) dx -= g.Lx;
+          else if (dx < -0.5 * g.Lx) dx += g.Lx;
+          if (dy > 0.5 * g.Ly) dy -= g.Ly;
+          else if (dy < -0.5 * g.Ly) dy += g.Ly;
+          const double zs = fam == 0 ? o.z : (fam == 1 ? -o.z : 2.0 * g.H - o.z);
+          double dz = me.z - zs;
+          if (tp) {
+            if (dz > 0.5 * g.H) dz -= g.H;
+            else if (dz < -0.5 * g.H) dz += g.H;
           }
+          near_pair<R>(g, dx, dy, dz, qf * o.q, ph, ex, ey, ez);
         }
       }
     }
