@@ -112,18 +112,31 @@ __global__ void __launch_bounds__(kThreads) k_prep(Geom g, int64_t n, const doub
     cp_hi = tp && z >= g.H - g.H_E;
     if (st) atomicOr(status, st);
   }
-  // slots of the extra entries: one atomic per wave and kind on the shared
-  // counter, the lanes in order after it
-  auto claim = [&](bool want) -> int {
-    const unsigned long long m = __ballot(want);
-    if (m == 0) return 0;
-    const int lead = __ffsll((long long)m) - 1;
-    int base = 0;
-    if (lane == lead) base = atomicAdd(n_img, __popcll(m));
-    base = __shfl(base, lead, 64);
-    return base + __popcll(m & ((1ull << lane) - 1));
+  // slots of the extra entries: one atomic per block and kind on the shared
+  // counter (the waves in order after it, the lanes in order in their wave)
+  __shared__ int wcnt[4][kThreads / 64];
+  __shared__ int bbase[4];
+  const int wv = threadIdx.x >> 6;
+  const bool want[4] = {img_b, img_t, cp_lo, cp_hi};
+  unsigned long long msk[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    msk[k] = __ballot(want[k]);
+    if (lane == 0) wcnt[k][wv] = __popcll(msk[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    int tot = 0;
+    for (int w = 0; w < kThreads / 64; ++w) tot += wcnt[threadIdx.x][w];
+    bbase[threadIdx.x] = tot ? atomicAdd(n_img, tot) : 0;
+  }
+  __syncthreads();
+  auto claim = [&](int k) -> int {
+    int base = bbase[k];
+    for (int w = 0; w < wv; ++w) base += wcnt[k][w];
+    return base + __popcll(msk[k] & ((1ull << lane) - 1));
   };
-  const int sb = claim(img_b), stt = claim(img_t), sl = claim(cp_lo), sh_ = claim(cp_hi);
+  const int sb = claim(0), stt = claim(1), sl = claim(2), sh_ = claim(3);
   if (img_b) {
     ext[n + sb] = Part{x, y, -z, g.gamma_b * qq};
     meta[n + sb] = GRP_IMAGE | (int)(i << 2);
