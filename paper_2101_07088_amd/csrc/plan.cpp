@@ -628,27 +628,34 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   p->wall_part = nullptr;  // set by whichever kernel forms the wall term
   p->wall_nparts = 0;
   start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
-  // The near field (stage 7) and its part of the gauge go to the side stream
-  // once the forward transforms are queued: they then share the CUs with the
-  // column solve, whose workgroups are bound by latency and LDS and leave
-  // issue slots and registers free, rather than with the bandwidth-bound
-  // spreading. Inside a graph capture they stay on the capturing stream (see
+  // The near field (stage 7) and its part of the gauge go to the side stream.
+  // In the FP32 path they are forked right after validation and share the
+  // CUs with the grid binning, spreading and forward transforms; in the FP64
+  // path (whose near field is several times longer) once the forward
+  // transforms are queued, beside the column solve. Measured on the large
+  // slab: 14.2-14.5 -> 14.0 ms mixed with the early fork, 24.0 -> 24.4 ms in
+  // FP64. Inside a graph capture they stay on the capturing stream (see
   // dpse_solve_graph).
   const bool fork = !p->capturing;
   hipStream_t ns = fork ? p->side : main;
+  auto near_field = [&]() {
+    if (fork && e == hipSuccess) e = hipEventRecord(p->fork_ev, main);
+    if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
+    p->stream = ns;
+    start(7, ns);
+    if (e == hipSuccess) e = dpse::launch_bin_cells(p, n);  // only the near field needs the cell list
+    if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
+    if (e == hipSuccess) e = dpse::launch_near_origin(p, n);
+    end(7, ns);
+    if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
+    p->stream = main;
+  };
+  constexpr bool early_near = sizeof(R) == 4;
+  if (early_near) near_field();
   start(1, main); if (e == hipSuccess) e = dpse::launch_bin_grid(p, n); end(1, main);
   start(2, main); run(dpse::launch_spread<R>); end(2, main);
   start(3, main); run(dpse::launch_fft_forward<R>); end(3, main);
-  if (fork && e == hipSuccess) e = hipEventRecord(p->fork_ev, main);
-  if (fork && e == hipSuccess) e = hipStreamWaitEvent(p->side, p->fork_ev, 0);
-  p->stream = ns;
-  start(7, ns);
-  if (e == hipSuccess) e = dpse::launch_bin_cells(p, n);  // only the near field needs the cell list
-  if (e == hipSuccess) e = dpse::launch_near<R>(p, n);
-  if (e == hipSuccess) e = dpse::launch_near_origin(p, n);
-  end(7, ns);
-  if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
-  p->stream = main;
+  if (!early_near) near_field();
   start(4, main); run(dpse::launch_column<R>); end(4, main);
   start(5, main); run(dpse::launch_fft_inverse<R>); end(5, main);
   start(6, main); if (e == hipSuccess) e = dpse::launch_interp<R>(p, n); end(6, main);
