@@ -233,7 +233,7 @@ template <typename R> hipError_t launch_wall_modes(dpse_plan* p);
 template <typename R> hipError_t launch_wall_keep_phi(dpse_plan* p);
 template <typename R> hipError_t launch_wall_energy(dpse_plan* p, int64_t n);
 int wall_energy_blocks(const dpse_plan* p, int64_t n);
-int interp_splits(int blocks);
+int gather_splits(const dpse_plan* p, int blocks, int T, int P);
 
 // Sets kernel attributes once (before any stream capture).
 hipError_t prepare_kernels();

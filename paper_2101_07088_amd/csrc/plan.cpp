@@ -629,12 +629,14 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
   p->wall_nparts = 0;
   start(0, main); if (e == hipSuccess) e = dpse::launch_prep(p, n, pos, q); end(0, main);
   // The near field (stage 7) and its part of the gauge go to the side stream.
-  // In the FP32 path they are forked right after validation and share the
-  // CUs with the grid binning, spreading and forward transforms; in the FP64
-  // path (whose near field is several times longer) once the forward
-  // transforms are queued, beside the column solve. Measured on the large
-  // slab: 14.2-14.5 -> 14.0 ms mixed with the early fork, 24.0 -> 24.4 ms in
-  // FP64. Inside a graph capture they stay on the capturing stream (see
+  // In the FP32 path of the slab they are forked right after validation and
+  // share the CUs with the grid binning, spreading and forward transforms;
+  // in the FP64 path (whose near field is several times longer) and in the
+  // triply periodic variant (whose column solve is short and near field
+  // long) once the forward transforms are queued, beside the column solve.
+  // Measured: large slab 14.2-14.5 -> 14.0 ms mixed with the early fork,
+  // 24.0 -> 24.4 ms in FP64; triply periodic workload 0.42 -> 0.49 ms mixed.
+  // Inside a graph capture they stay on the capturing stream (see
   // dpse_solve_graph).
   const bool fork = !p->capturing;
   hipStream_t ns = fork ? p->side : main;
@@ -650,7 +652,7 @@ static hipError_t solve_stages(dpse_plan* p, int64_t n, const double* pos, const
     if (fork && e == hipSuccess) e = hipEventRecord(p->join_ev, p->side);
     p->stream = main;
   };
-  constexpr bool early_near = sizeof(R) == 4;
+  const bool early_near = sizeof(R) == 4 && !(p->g.flags & DPSE_TRIPLY);
   if (early_near) near_field();
   start(1, main); if (e == hipSuccess) e = dpse::launch_bin_grid(p, n); end(1, main);
   start(2, main); run(dpse::launch_spread<R>); end(2, main);
