@@ -135,8 +135,8 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
   __syncthreads();
   fft_rows_r8<C, kThreads>(buf, logN, tw, false, threadIdx.x);
   const R scale = (R)(1.0 / ((double)g.Nx * (double)g.Ny));
-  for (int i = threadIdx.x; i < nseq * nkx; i += kThreads) {
-    int s = i / nkx, k = i % nkx;
+  for (int s = 0; s < nseq; ++s)
+  for (int k = threadIdx.x; k < nkx; k += kThreads) {
     C z = buf[rowpad_ix(s, k, Nx)], zc = buf[rowpad_ix(s, (Nx - k) & (Nx - 1), Nx)];
     zc.y = -zc.y;
     C a, b;
@@ -413,7 +413,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   using V = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
   V* out = reinterpret_cast<V*>(u4);
   for (int i = threadIdx.x; i < nr * Nx; i += kThreads) {
-    int rl = i / Nx, x = i % Nx;
+    const int rl = i >> logN, x = i & (Nx - 1);
     C z1 = buf[rowpad_ix(2 * rl, x, Nx)], z2 = buf[rowpad_ix(2 * rl + 1, x, Nx)];
     V v;
     v.x = z1.x; v.y = z1.y; v.z = z2.x; v.w = z2.y;
