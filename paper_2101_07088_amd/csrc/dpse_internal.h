@@ -130,6 +130,9 @@ struct Tables {
   // factorised per-mode chains: elimination multipliers, [Nz][Ny (Nx/2+1)]
   // (chain-major rows, see k_pivots in k_column.hip)
   double* cpiv = nullptr;
+  // the linear functionals S1..DH of each mode's homogeneous chain solutions
+  // (even chain y_0 = 1, odd chain y'_0 = 1), [Ny (Nx/2+1)][2][8] (scan kernel)
+  double* hfun = nullptr;
 };
 
 // Fixed wall charge densities (dpse_plan_set_walls), one allocation per plan.

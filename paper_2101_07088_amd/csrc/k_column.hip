@@ -752,8 +752,15 @@ constexpr int kNumFunBC = 8;   // S1..S4, V0, VH, D0, DH (Ea, Eb only for k = 0)
 // Plan-time LU factorisation of the chains of k_column_scan: for each mode
 // and parity, the inverse pivots 1 / (dia_r - sub_r c_{r-1}) with c_r = sup_r
 // times the inverse pivot, at cinv[mode * Nz + parity * ceil(Nz/2) + r].
+// The same pass forms the functionals S1..DH of the chain's homogeneous
+// solution (right-hand side kappa^2 in row 0): with the forward sweep
+// d_r = al_r d_{r-1} + inv_r rhs_r and the back substitution x_r = d_r +
+// gam_r x_{r+1} (U x = d), a functional w.x equals y.d with U^T y = w, i.e.
+// y_r = w_r + gam_{r-1} y_{r-1}: both recurrences run forward, so one sweep
+// gives all eight (plus the free constant's weight), stored at
+// hfun[mode * 16 + parity * 8 + f].
 __global__ void __launch_bounds__(kThreads) k_pivots_scan(Geom g, const double* __restrict__ ctab,
-                                                          double* __restrict__ cinv) {
+                                                          double* __restrict__ cinv, double* __restrict__ hfun) {
   const int nmodes = g.Ny * g.nkx, N = g.Nz;
   const int t = blockIdx.x * kThreads + threadIdx.x;
   if (t >= 2 * nmodes) return;
@@ -763,15 +770,32 @@ __global__ void __launch_bounds__(kThreads) k_pivots_scan(Geom g, const double* 
   mode_wave(g, mi, kk, keep);
   const double kap = kk * g.zR, kap2 = kap * kap;
   const int half0 = (N + 1) / 2, L = par == 0 ? half0 : N / 2;
+  const int NU = N + 2;
+  const double* W = ctab + kCtabRows * N;
   double* out = cinv + (size_t)mi * N + par * half0;
-  double cp = 0.0;
+  double cp = 0.0, d = 0.0, gprev = 0.0;
+  double y[kNumFunBC], F[kNumFunBC];
+#pragma unroll
+  for (int f = 0; f < kNumFunBC; ++f) { y[f] = 0.0; F[f] = 0.0; }
   for (int r = 0; r < L; ++r) {
     const int n = par + 2 * r;
     const double sub = -kap2 * ctab[n], dia = fma(kap2, ctab[N + n], 1.0), sup = -kap2 * ctab[2 * N + n];
     const double inv = rcp_refined(fma(-sub, cp, dia));
     out[r] = inv;
     cp = sup * inv;
+    // the column kernel's multipliers: al_r = kappa^2 a_n inv_r, gam_r = kappa^2 c_n inv_r
+    const double al = kap2 * ctab[n] * inv, gam = kap2 * ctab[2 * N + n] * inv;
+    d = fma(al, d, inv * (r == 0 ? kap2 : 0.0));
+#pragma unroll
+    for (int f = 0; f < kNumFunBC; ++f) {
+      y[f] = fma(gprev, y[f], W[f * NU + n]);
+      F[f] = fma(y[f], d, F[f]);
+    }
+    gprev = gam;
   }
+  double* h = hfun + (size_t)mi * 16 + par * 8;
+#pragma unroll
+  for (int f = 0; f < kNumFunBC; ++f) h[f] = F[f] + W[f * NU + N + par];
 }
 
 // DPP controls (GFX9 encoding).
@@ -931,7 +955,8 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
                                                          const double* __restrict__ zn,
                                                          const double* __restrict__ ctab,
                                                          const double2* __restrict__ twz,
-                                                         const double* __restrict__ cinv, double* scal,
+                                                         const double* __restrict__ cinv,
+                                                         const double* __restrict__ hfun, double* scal,
                                                          const double2* __restrict__ wall_hat) {
   using C = typename CT<R>::T;
   constexpr int KE = kScanKE, NT = kScanNT, RW = kScanRows;
@@ -1011,6 +1036,15 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
   const int mi = m0 + m;
   const bool live = mi < nmodes;
   const double kap2 = s_kap[m] * s_kap[m];
+  // the plan's functionals of the homogeneous solutions that this lane stores
+  // in phase 3 (loaded now, used after the chains)
+  constexpr int NH = (kNumFunBC + S - 1) / S;
+  double hpre[NH];
+#pragma unroll
+  for (int j = 0; j < NH; ++j) {
+    const int f = seg + j * S;
+    hpre[j] = live && f < kNumFunBC ? hfun[(size_t)mi * 16 + par * 8 + f] : 0.0;
+  }
   double X[RW][5];   // per row: Re psi_i*, Im psi_i*, Re psi_o*, Im psi_o*, homogeneous
   double gam[RW], PP[RW];
   {
@@ -1142,69 +1176,90 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       }
   }
 
-  // 3. linear functionals (dot products of y'' and the free constants with
-  //    the plan's weight vectors) summed over the lane's rows, then over the
-  //    chain's segments by a reduce-scatter: the 4 x 5 partials of a pass,
-  //    padded to 32, are halved at each step (partners at distance 16, 8, 4,
-  //    2, 1 within the chain), and lane seg ends with the sums of entries
-  //    [seg K, seg K + K), K = 32 / S. The homogeneous solution of the even
-  //    chain has y_0 = 1, that of the odd chain y'_0 = 1.
-  auto functionals = [&](int f0, double* dst) {
-    double v[32];
+  // 3. linear functionals (dot products of y'' with the plan's weight
+  //    vectors) of the four particular solutions, summed over the lane's rows,
+  //    then over the chain's segments by a reduce-scatter: in passes of NF
+  //    functionals (all eight at once for 32 segments, two passes of four
+  //    otherwise, which keeps the registers at three waves per SIMD), the V =
+  //    4 NF partials are halved at each step (partners at distance S/2, ...,
+  //    1 within the chain); a lane ends with entries [seg K, seg K + K), K =
+  //    V / S, or, with fewer values than segments, the groups of S / V lanes
+  //    add their one entry (all-reduce steps) and its first lane keeps it.
+  //    Those of the homogeneous solutions (the even chain with y_0 = 1, the
+  //    odd one with y'_0 = 1) depend on the mode only and come from the plan
+  //    (hfun).
+  {
+    constexpr int NF = S == 32 ? kNumFunBC : kNumFunBC / 2;
+    constexpr int V = 4 * NF;
+    double* my_fun = sfun + (m * 2 + par) * kNumFunBC * 5;
 #pragma unroll
-    for (int i = 0; i < 32; ++i) v[i] = 0.0;
+    for (int f0 = 0; f0 < kNumFunBC; f0 += NF) {
+      double v[V];
 #pragma unroll
-    for (int q = 0; q < RW; ++q)
-      if (q < cnt) {
-        const int n = par + 2 * (r0 + q);
+      for (int i = 0; i < V; ++i) v[i] = 0.0;
 #pragma unroll
-        for (int f = 0; f < 4; ++f) {
-          const double w = W[(f0 + f) * NU + n];
+      for (int q = 0; q < RW; ++q)
+        if (q < cnt) {
+          const int n = par + 2 * (r0 + q);
 #pragma unroll
-          for (int k = 0; k < 5; ++k) v[f * 5 + k] = fma(w, X[q][k], v[f * 5 + k]);
+          for (int f = 0; f < NF; ++f) {
+            const double w = W[(f0 + f) * NU + n];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[f * 4 + k] = fma(w, X[q][k], v[f * 4 + k]);
+          }
+        }
+      // one step at partner distance D (its DPP or LDS move): halve the
+      // entries held (h of them kept) or, down to one, add the partner's
+      auto step = [&](auto ctrl_tag, int h, bool upper) {
+        constexpr int CT_ = decltype(ctrl_tag)::value;
+        auto mv = [&](double x) {
+          if constexpr (CT_ < 0) return __shfl_xor(x, 16, 64);
+          else return dpp_d<CT_>(x);
+        };
+        if (h == 0) {
+          v[0] += mv(v[0]);
+          return;
+        }
+#pragma unroll
+        for (int i = 0; i < V / 2; ++i) {
+          if (i < h) {
+            const double snd = upper ? v[i] : v[h + i];
+            const double kp = upper ? v[h + i] : v[i];
+            v[i] = kp + mv(snd);
+          }
+        }
+      };
+      using X16 = std::integral_constant<int, -1>;
+      using X8 = std::integral_constant<int, kDppRowMirror>;
+      using X4 = std::integral_constant<int, kDppRowHalfMirror>;
+      using X2 = std::integral_constant<int, kDppQuadXor2>;
+      using X1 = std::integral_constant<int, kDppQuadXor1>;
+      int h = V / 2;
+      if constexpr (S > 16) { step(X16{}, h, (seg & 16) != 0); h >>= 1; }
+      if constexpr (S > 8) { step(X8{}, h, (seg & 8) != 0); h >>= 1; }
+      if constexpr (S > 4) { step(X4{}, h, (seg & 4) != 0); h >>= 1; }
+      step(X2{}, h, (seg & 2) != 0);
+      h >>= 1;
+      step(X1{}, h, (seg & 1) != 0);
+      if constexpr (V >= S) {
+        constexpr int K = V / S;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+          const int e = seg * K + i;
+          my_fun[(f0 + (e >> 2)) * 5 + (e & 3)] = v[i];
+        }
+      } else {
+        constexpr int GS = S / V;
+        if (seg % GS == 0) {
+          const int e = seg / GS;
+          my_fun[(f0 + (e >> 2)) * 5 + (e & 3)] = v[0];
         }
       }
-    if (seg == 0) {
-#pragma unroll
-      for (int f = 0; f < 4; ++f) v[f * 5 + 4] += W[(f0 + f) * NU + N + par];
     }
-    // reduce-scatter over the S lanes of the chain
-    auto halve = [&](auto ctrl_tag, int h, bool upper) {
-      constexpr int CT_ = decltype(ctrl_tag)::value;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        if (i < h) {
-          const double snd = upper ? v[i] : v[h + i];
-          const double kp = upper ? v[h + i] : v[i];
-          double rcv;
-          if constexpr (CT_ < 0) rcv = __shfl_xor(snd, 16, 64);
-          else rcv = dpp_d<CT_>(snd);
-          v[i] = kp + rcv;
-        }
-      }
-    };
-    using X16 = std::integral_constant<int, -1>;
-    using X8 = std::integral_constant<int, kDppRowMirror>;
-    using X4 = std::integral_constant<int, kDppRowHalfMirror>;
-    using X2 = std::integral_constant<int, kDppQuadXor2>;
-    using X1 = std::integral_constant<int, kDppQuadXor1>;
-    int h = 16;
-    if constexpr (S > 16) { halve(X16{}, h, (seg & 16) != 0); h >>= 1; }
-    if constexpr (S > 8) { halve(X8{}, h, (seg & 8) != 0); h >>= 1; }
-    if constexpr (S > 4) { halve(X4{}, h, (seg & 4) != 0); h >>= 1; }
-    halve(X2{}, h, (seg & 2) != 0);
-    h >>= 1;
-    halve(X1{}, h, (seg & 1) != 0);
-    constexpr int K = 32 / S;
-#pragma unroll
-    for (int i = 0; i < K; ++i) {
-      const int e = seg * K + i;
-      if (e < 20) dst[(e / 5) * 5 + (e % 5)] = v[i];
-    }
-  };
-  double* my_fun = sfun + (m * 2 + par) * kNumFunBC * 5;
-  functionals(0, my_fun);
-  functionals(4, my_fun + 4 * 5);
+    for (int j = 0; j < NH; ++j)
+      if (seg + j * S < kNumFunBC) my_fun[(seg + j * S) * 5 + 4] = hpre[j];
+  }
   if (mi == 0) {
     // Ea, Eb of the k = 0 mode (FUN_EA, FUN_EB follow DH): a plain reduction
     double ea[5] = {0, 0, 0, 0, 0}, eb[5] = {0, 0, 0, 0, 0};
@@ -1508,8 +1563,8 @@ void column_scan_as(dpse_plan* p) {
   const int nb = (nmodes + MB - 1) / MB;
   hipLaunchKernelGGL((k_column_scan<R, LOGS>), dim3(nb), dim3(kScanNT), column_scan_lds(g, sizeof(R)), p->stream,
                      g, (const C*)p->w.fx_i, (const C*)p->w.fx_o, (C*)p->w.psi, (C*)p->w.psiz, (const double*)p->t.z,
-                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv, p->w.scal,
-                     p->walls_on ? (const double2*)p->walls.hat : nullptr);
+                     (const double*)p->t.ctab, (const double2*)p->t.twz, (const double*)p->t.cpiv,
+                     (const double*)p->t.hfun, p->w.scal, p->walls_on ? (const double2*)p->walls.hat : nullptr);
 }
 
 template <typename R>
@@ -1731,7 +1786,7 @@ hipError_t launch_pivots(dpse_plan* p, hipStream_t s) {
   const int nt = 2 * g.Ny * g.nkx;
   if (scan_applies(g))
     hipLaunchKernelGGL(k_pivots_scan, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
-                       (const double*)p->t.ctab, p->t.cpiv);
+                       (const double*)p->t.ctab, p->t.cpiv, p->t.hfun);
   else
     hipLaunchKernelGGL(k_pivots, dim3((nt + kThreads - 1) / kThreads), dim3(kThreads), 0, s, g,
                        (const double*)p->t.ctab, p->t.cpiv);

@@ -319,6 +319,7 @@ size_t carve_tables(dpse_plan* p, char* base) {
   c.take(&t.twx_f, g.Nx / 2); c.take(&t.twy_f, g.Ny / 2);
   c.take(&t.ctab, dpse::kCtabRows * g.Nz + dpse::kNumFun * (g.Nz + 2));
   c.take(&t.cpiv, (size_t)g.Nz * g.Ny * g.nkx);
+  c.take(&t.hfun, 16 * (size_t)g.Ny * g.nkx);
   return c.off;
 }
 
