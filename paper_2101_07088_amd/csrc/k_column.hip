@@ -864,27 +864,65 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
     w3e[2].y = -w3.x;
     w3e[3].x = r2 * (w3.y - w3.x);
     w3e[3].y = -r2 * (w3.x + w3.y);
+    if (sizeof(Rr) == 4 && lh == 0) {
+      // first pass: every twiddle is 1, -i or exp(-i pi e / 4) (no products
+      // with table values; FP32 only, where the registers allow the second
+      // code path)
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      C* v = a[bi];
+      for (int bi = 0; bi < 2; ++bi) {
+        C* v = a[bi];
 #pragma unroll
-      for (int e = 0; e < 8; e += 2) {
-        const C t = cmul(v[e + 1], w1);
-        v[e + 1] = csub(v[e], t);
-        v[e] = cadd(v[e], t);
+        for (int e = 0; e < 8; e += 2) {
+          const C t = v[e + 1];
+          v[e + 1] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (e & 2) continue;
+          C t = v[e + 2];
+          if (e & 1) {  // times -i
+            const Rr re = t.x;
+            t.x = t.y;
+            t.y = -re;
+          }
+          v[e + 2] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          C t = v[e + 4];
+          const Rr x = t.x, y = t.y;
+          if (e == 1) { t.x = r2 * (x + y); t.y = r2 * (y - x); }
+          if (e == 2) { t.x = y; t.y = -x; }
+          if (e == 3) { t.x = r2 * (y - x); t.y = -r2 * (x + y); }
+          v[e + 4] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
       }
+    } else {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        if (e & 2) continue;
-        const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
-        v[e + 2] = csub(v[e], t);
-        v[e] = cadd(v[e], t);
-      }
+      for (int bi = 0; bi < 2; ++bi) {
+        C* v = a[bi];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const C t = cmul(v[e + 4], w3e[e]);
-        v[e + 4] = csub(v[e], t);
-        v[e] = cadd(v[e], t);
+        for (int e = 0; e < 8; e += 2) {
+          const C t = cmul(v[e + 1], w1);
+          v[e + 1] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          if (e & 2) continue;
+          const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
+          v[e + 2] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const C t = cmul(v[e + 4], w3e[e]);
+          v[e + 4] = csub(v[e], t);
+          v[e] = cadd(v[e], t);
+        }
       }
     }
 #pragma unroll
