@@ -254,62 +254,100 @@ template <typename C, int NTHR>
 __device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid) {
   using Rr = decltype(C{}.x);
   const int N = 1 << logN;
+  const Rr r2 = (Rr)0.70710678118654752440;
+  const Rr sg = inverse ? (Rr)-1 : (Rr)1;  // forward: times -i and exp(-i pi/4); inverse: the conjugates
+  // a pass's elements k0 + e half sit at base + e stride: for rows of 32 and
+  // more, half is 1 (k0 a multiple of 8) or a multiple of 8, so the padding
+  // adds e (half / 8)
   auto pass8 = [&](int lh) {
     const int half = 1 << lh, ts1 = (N >> 1) >> lh, ts2 = ts1 >> 1, ts3 = ts1 >> 2;
-    const int G = N >> 3, b = tid & (G - 1), s = tid / G;
+    const int lg = logN - 3, b = tid & ((1 << lg) - 1), s = tid >> lg;
     const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 3)) + pos;
-    C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
-    if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+    const int base = rowpad_ix(s, k0, N), stride = half + (half >> 3);
     C v[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) v[e] = buf[rowpad_ix(s, k0 + e * half, N)];
-    const Rr r2 = (Rr)0.70710678118654752440;
-    const Rr sg = inverse ? (Rr)-1 : (Rr)1;  // forward: times -i and exp(-i pi/4); inverse: the conjugates
-    C w2m, w3e[4];
-    w2m.x = sg * w2.y;
-    w2m.y = -sg * w2.x;
-    w3e[0] = w3;
-    w3e[1].x = r2 * (w3.x + sg * w3.y);
-    w3e[1].y = r2 * (w3.y - sg * w3.x);
-    w3e[2].x = sg * w3.y;
-    w3e[2].y = -sg * w3.x;
-    w3e[3].x = r2 * (sg * w3.y - w3.x);
-    w3e[3].y = -r2 * (sg * w3.x + w3.y);
+    for (int e = 0; e < 8; ++e) v[e] = buf[base + e * stride];
+    if (lh == 0) {
+      // first pass: the twiddles are 1, -i and exp(-i pi e / 4) (conjugated
+      // when inverse), no table products
 #pragma unroll
-    for (int e = 0; e < 8; e += 2) {
-      const C t = cmul(v[e + 1], w1);
-      v[e + 1] = csub(v[e], t);
-      v[e] = cadd(v[e], t);
+      for (int e = 0; e < 8; e += 2) {
+        const C t = v[e + 1];
+        v[e + 1] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (e & 2) continue;
+        C t = v[e + 2];
+        if (e & 1) {
+          const Rr x = t.x;
+          t.x = sg * t.y;
+          t.y = -sg * x;
+        }
+        v[e + 2] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        C t = v[e + 4];
+        const Rr x = t.x, y = t.y;
+        if (e == 1) { t.x = r2 * (x + sg * y); t.y = r2 * (y - sg * x); }
+        if (e == 2) { t.x = sg * y; t.y = -sg * x; }
+        if (e == 3) { t.x = r2 * (sg * y - x); t.y = -r2 * (y + sg * x); }
+        v[e + 4] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+    } else {
+      C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+      if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
+      C w2m, w3e[4];
+      w2m.x = sg * w2.y;
+      w2m.y = -sg * w2.x;
+      w3e[0] = w3;
+      w3e[1].x = r2 * (w3.x + sg * w3.y);
+      w3e[1].y = r2 * (w3.y - sg * w3.x);
+      w3e[2].x = sg * w3.y;
+      w3e[2].y = -sg * w3.x;
+      w3e[3].x = r2 * (sg * w3.y - w3.x);
+      w3e[3].y = -r2 * (sg * w3.x + w3.y);
+#pragma unroll
+      for (int e = 0; e < 8; e += 2) {
+        const C t = cmul(v[e + 1], w1);
+        v[e + 1] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        if (e & 2) continue;
+        const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
+        v[e + 2] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const C t = cmul(v[e + 4], w3e[e]);
+        v[e + 4] = csub(v[e], t);
+        v[e] = cadd(v[e], t);
+      }
     }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      if (e & 2) continue;
-      const C t = cmul(v[e + 2], (e & 1) ? w2m : w2);
-      v[e + 2] = csub(v[e], t);
-      v[e] = cadd(v[e], t);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const C t = cmul(v[e + 4], w3e[e]);
-      v[e + 4] = csub(v[e], t);
-      v[e] = cadd(v[e], t);
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) buf[rowpad_ix(s, k0 + e * half, N)] = v[e];
+    for (int e = 0; e < 8; ++e) buf[base + e * stride] = v[e];
     __syncthreads();
   };
   auto pass4 = [&](int lh) {
     const int half = 1 << lh, ts1 = (N >> 1) >> lh, ts2 = ts1 >> 1;
-    const int G = N >> 2;
+    const int lg = logN - 2, stride = half + (half >> 3);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      const int t = tid + q * NTHR, b = t & (G - 1), s = t / G;
+      const int t = tid + q * NTHR, b = t & ((1 << lg) - 1), s = t >> lg;
       const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 2)) + pos;
+      const int base = rowpad_ix(s, k0, N);
       C x1 = tw[pos * ts1], x2 = tw[pos * ts2];
       if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
       C a[4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[e] = buf[rowpad_ix(s, k0 + e * half, N)];
+      for (int e = 0; e < 4; ++e) a[e] = buf[base + e * stride];
       const C t1 = cmul(a[1], x1), t3 = cmul(a[3], x1);
       const C b0 = cadd(a[0], t1), b1 = csub(a[0], t1);
       const C b2 = cadd(a[2], t3), b3 = csub(a[2], t3);
@@ -320,10 +358,10 @@ __device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid
         if (inverse) { u3.x = -u3.y; u3.y = re; }
         else { u3.x = u3.y; u3.y = -re; }
       }
-      buf[rowpad_ix(s, k0, N)] = cadd(b0, u2);
-      buf[rowpad_ix(s, k0 + 2 * half, N)] = csub(b0, u2);
-      buf[rowpad_ix(s, k0 + half, N)] = cadd(b1, u3);
-      buf[rowpad_ix(s, k0 + 3 * half, N)] = csub(b1, u3);
+      buf[base] = cadd(b0, u2);
+      buf[base + 2 * stride] = csub(b0, u2);
+      buf[base + stride] = cadd(b1, u3);
+      buf[base + 3 * stride] = csub(b1, u3);
     }
     __syncthreads();
   };

@@ -88,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     float4 v0[kQ], v1[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int gq = threadIdx.x + q * kThreads, s = gq / nq, u = gq - s * nq;
+      const int gq = threadIdx.x + q * kThreads, s = gq >> (logN - 2), u = gq & (nq - 1);
       const int64_t r = r_base + 2 * s;
       v0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       v1[q] = v0[q];
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     }
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int gq = threadIdx.x + q * kThreads, s = gq / nq, u = gq - s * nq;
+      const int gq = threadIdx.x + q * kThreads, s = gq >> (logN - 2), u = gq & (nq - 1);
       const int p = bitrev(4 * u, logN), qn = Nx >> 2;
       C d;
       d.x = v0[q].x; d.y = v1[q].x;
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
     C la[kQ], lb[kQ], lc[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int gq = threadIdx.x + q * kThreads, rl = gq / hx, kk = gq - rl * hx;
+      const int gq = threadIdx.x + q * kThreads, rl = gq >> (logN - 1), kk = gq & (hx - 1);
       la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
       if (rl < nr) {
         const size_t o = (size_t)(r_base + rl) * nkx + kk;
@@ -352,7 +352,7 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
     }
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
-      const int gq = threadIdx.x + q * kThreads, rl = gq / hx, kk = gq - rl * hx;
+      const int gq = threadIdx.x + q * kThreads, rl = gq >> (logN - 1), kk = gq & (hx - 1);
       C z1, z2;
       seqs(la[q], lb[q], lc[q], kk, false, z1, z2);
       const int p = bitrev(kk, logN);
