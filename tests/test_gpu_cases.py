@@ -109,6 +109,19 @@ def test_tall_slabs_beyond_the_scan_column_range(nz, H, precs):
         assert abs(U - U0) < tol * 0.5 * np.sum(np.abs(q * phi0))
 
 
+@pytest.mark.parametrize("Lx,Ly", [(32.0, 8.0), (8.0, 32.0), (128.0, 8.0), (8.0, 128.0), (256.0, 8.0)])
+def test_rectangular_boxes_cover_every_transform_length(Lx, Ly):
+    """N_x and N_y of 128, 512 and 1024 against 32 on the other side: the x
+    and y transforms take different pass schedules (radix-8 and radix-4
+    passes) for each power of two; FP64 at 1e-9, mixed at 1e-5."""
+    _need_gpu()
+    p = W.SlabParams(Lx=Lx, Ly=Ly, H=6.0, eps=1.0, eps_b=0.5, eps_t=0.05, xi=1.0, Nx=int(Lx / 0.25),
+                     Ny=int(Ly / 0.25), Nz=33, r_cut=3.0)
+    pos, q = W.charges(int(Lx + 3 * Ly), 30, 30, Lx, Ly, 0.5, 5.5)
+    for prec, tol in ((0, 1e-9), (1, 1e-5)):
+        check(p, pos, q, tol, precision=prec, label=f"box {p.Nx}x{p.Ny}x{p.Nz}")
+
+
 def test_gaussian_charges_and_gauge_off():
     _need_gpu()
     p, pos, q = small_jump(6, 50)
