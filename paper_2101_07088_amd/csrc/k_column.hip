@@ -1061,18 +1061,28 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       B[p] = va[q];
     }
   }
-  __syncthreads();
-  fft_scan_pair<C, LOGS>(A, B, tw, tid);
-
   // 2. the chains. Lane (m, par, seg): rows r0 .. r0 + cnt - 1 of chain par
   //    (unknowns y''_n, n = par + 2r) of mode m; a chain's S lanes are
-  //    consecutive lanes of one wave.
+  //    consecutive lanes of one wave. The lane's elimination multipliers are
+  //    loaded before the forward transforms, which then cover their latency.
   const int seg = tid & (S - 1), par = (tid >> LOGS) & 1, m = tid >> (LOGS + 1);
   constexpr int half0 = (N + 1) / 2;
   const int L = par ? N / 2 : half0;
   const int r0 = (seg * L) >> LOGS, cnt = (((seg + 1) * L) >> LOGS) - r0;
+  // a chain has 4 S or 4 S + 1 rows, so every lane has at least RW - 1 rows
+  // (the last segment of the even chain has RW): with FP32 transforms the
+  // rows below RW - 1 are taken without a test, which lets their table loads
+  // issue together (large slab column 4.43 -> 4.16 ms); the FP64 kernel
+  // measured slower that way (6.7 -> 6.9 ms) and keeps the test
+  static_assert((N / 2) == (RW - 1) * S && half0 == (RW - 1) * S + 1, "rows per lane");
+  auto rows_all = [&](int q) { return (sizeof(R) == 4 && q < RW - 1) || q < cnt; };
   const int mi = m0 + m;
   const bool live = mi < nmodes;
+  double invp[RW];
+#pragma unroll
+  for (int q = 0; q < RW; ++q) invp[q] = live && rows_all(q) ? cinv[(size_t)mi * N + par * half0 + r0 + q] : 0.0;
+  __syncthreads();
+  fft_scan_pair<C, LOGS>(A, B, tw, tid);
   const double kap2 = s_kap[m] * s_kap[m];
   // the plan's functionals of the homogeneous solutions that this lane stores
   // in phase 3 (loaded now, used after the chains)
@@ -1092,9 +1102,9 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
 #pragma unroll
     for (int q = 0; q < RW; ++q) {
       gam[q] = 0.0;
-      if (q < cnt) {
+      if (rows_all(q)) {
         const int r = r0 + q, n = par + 2 * r;
-        const double inv = live ? cinv[(size_t)mi * N + par * half0 + r] : 0.0;
+        const double inv = invp[q];
         const double al = kap2 * ctab[n] * inv;
         gam[q] = kap2 * ctab[2 * N + n] * inv;  // back substitution: x_r = d_r + gam_r x_{r+1}
         const double gs = ctab[3 * N + n];
@@ -1145,7 +1155,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     }
 #pragma unroll
     for (int q = 0; q < RW; ++q)
-      if (q < cnt) {
+      if (rows_all(q)) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) X[q][k] = fma(PP[q], din[k], X[q][k]);
       }
@@ -1156,7 +1166,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     double x[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, Q = 1.0;
 #pragma unroll
     for (int q = RW - 1; q >= 0; --q) {
-      if (q < cnt) {
+      if (rows_all(q)) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
           x[k] = fma(gam[q], x[k], X[q][k]);
@@ -1208,7 +1218,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     }
 #pragma unroll
     for (int q = 0; q < RW; ++q)
-      if (q < cnt) {
+      if (rows_all(q)) {
 #pragma unroll
         for (int k = 0; k < 5; ++k) X[q][k] = fma(PP[q], xin[k], X[q][k]);
       }
@@ -1225,7 +1235,31 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
   //    add their one entry (all-reduce steps) and its first lane keeps it.
   //    Those of the homogeneous solutions (the even chain with y_0 = 1, the
   //    odd one with y'_0 = 1) depend on the mode only and come from the plan
-  //    (hfun).
+  //    (hfun). The weight rows are staged in LDS first, over the transform
+  //    buffers (free until the final series), with a row's entry n at
+  //    n + n / 8 (the lanes of a chain, eight entries apart, then meet
+  //    distinct banks): their loads issue together instead of one round trip
+  //    to the cache per few rows.
+  constexpr int NUP = N + (N >> 3) + 1;
+  static_assert(kNumFunBC * NUP * sizeof(double) <= 2 * KEP * sizeof(C), "weight rows fit the buffers");
+  const double* sW = reinterpret_cast<const double*>(A);
+  {
+    __syncthreads();  // every lane has read its transform values
+    double* dW = reinterpret_cast<double*>(A);
+    constexpr int kWq = (kNumFunBC * N + NT - 1) / NT;
+    double wv[kWq];
+#pragma unroll
+    for (int q = 0; q < kWq; ++q) {
+      const int i = tid + q * NT, f = i / N, n = i - f * N;
+      wv[q] = i < kNumFunBC * N ? W[f * NU + n] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kWq; ++q) {
+      const int i = tid + q * NT, f = i / N, n = i - f * N;
+      if (i < kNumFunBC * N) dW[f * NUP + n + (n >> 3)] = wv[q];
+    }
+    __syncthreads();
+  }
   {
     constexpr int NF = S == 32 ? kNumFunBC : kNumFunBC / 2;
     constexpr int V = 4 * NF;
@@ -1237,11 +1271,11 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       for (int i = 0; i < V; ++i) v[i] = 0.0;
 #pragma unroll
       for (int q = 0; q < RW; ++q)
-        if (q < cnt) {
+        if (rows_all(q)) {
           const int n = par + 2 * (r0 + q);
 #pragma unroll
           for (int f = 0; f < NF; ++f) {
-            const double w = W[(f0 + f) * NU + n];
+            const double w = sW[(f0 + f) * NUP + n + (n >> 3)];
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[f * 4 + k] = fma(w, X[q][k], v[f * 4 + k]);
           }
@@ -1303,7 +1337,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     double ea[5] = {0, 0, 0, 0, 0}, eb[5] = {0, 0, 0, 0, 0};
 #pragma unroll
     for (int q = 0; q < RW; ++q)
-      if (q < cnt) {
+      if (rows_all(q)) {
         const int n = par + 2 * (r0 + q);
         const double wa = W[FUN_EA * NU + n], wb = W[FUN_EB * NU + n];
 #pragma unroll
@@ -1454,7 +1488,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     for (int q = 0; q < RW; ++q) {
       yr[q] = 0.0;
       yi[q] = 0.0;
-      if (q < cnt) {
+      if (rows_all(q)) {
         const int n = par + 2 * (r0 + q);
         const double xmr = q == 0 ? pr : xr[q > 0 ? q - 1 : 0], xmi = q == 0 ? pi : xi[q > 0 ? q - 1 : 0];
         const double xpr = q + 1 < cnt ? xr[q + 1 < RW ? q + 1 : RW - 1] : nr;
@@ -1474,7 +1508,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     for (int q = RW - 1; q >= 0; --q) {
       sufr[q] = 0.0;
       sufi[q] = 0.0;
-      if (q < cnt) {
+      if (rows_all(q)) {
         const double f = 2.0 * (par + 2 * (r0 + q));
         sr = fma(f, yr[q], sr);
         si = fma(f, yi[q], si);
@@ -1520,7 +1554,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     };
 #pragma unroll
     for (int q = 0; q < RW; ++q)
-      if (q < cnt) {
+      if (rows_all(q)) {
         const int n = par + 2 * (r0 + q);
         put(A, n, yr[q], yi[q]);
         if (n >= 1) {
