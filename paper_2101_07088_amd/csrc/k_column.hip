@@ -1067,14 +1067,15 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
   //    loaded before the forward transforms, which then cover their latency.
   const int seg = tid & (S - 1), par = (tid >> LOGS) & 1, m = tid >> (LOGS + 1);
   constexpr int half0 = (N + 1) / 2;
-  const int L = par ? N / 2 : half0;
-  const int r0 = (seg * L) >> LOGS, cnt = (((seg + 1) * L) >> LOGS) - r0;
-  // a chain has 4 S or 4 S + 1 rows, so every lane has at least RW - 1 rows
-  // (the last segment of the even chain has RW): with FP32 transforms the
+  // a chain has 4 S or 4 S + 1 rows: lane seg takes rows 4 seg .. 4 seg + 3,
+  // and the last segment of the even chain one more (the partition
+  // [seg L / S, (seg + 1) L / S) written out), so every lane has at least
+  // RW - 1 rows; with FP32 transforms the
   // rows below RW - 1 are taken without a test, which lets their table loads
   // issue together (large slab column 4.43 -> 4.16 ms); the FP64 kernel
   // measured slower that way (6.7 -> 6.9 ms) and keeps the test
   static_assert((N / 2) == (RW - 1) * S && half0 == (RW - 1) * S + 1, "rows per lane");
+  const int r0 = (RW - 1) * seg, cnt = RW - 1 + (par == 0 && seg == S - 1 ? 1 : 0);
   auto rows_all = [&](int q) { return (sizeof(R) == 4 && q < RW - 1) || q < cnt; };
   const int mi = m0 + m;
   const bool live = mi < nmodes;
@@ -1262,8 +1263,36 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
   }
   {
     constexpr int NF = S == 32 ? kNumFunBC : kNumFunBC / 2;
+    constexpr int FB = NF == 8 ? 3 : 2;  // bits of a functional's index within a pass
     constexpr int V = 4 * NF;
     double* my_fun = sfun + (m * 2 + par) * kNumFunBC * 5;
+    // The partner moves of the chain's lanes, partner distance S/2 first:
+    // xor 16 (an LDS swizzle), then the DPP row mirror (i <-> 15 - i), half
+    // mirror (i <-> 7 - i), quad xor 2 and xor 1. The first FB of them halve
+    // the functionals held (a lane keeps NF/2, then NF/4, ...), the rest add
+    // the four entries left over the remaining lanes. A lane stores its
+    // partial of functional f at slot f ^ fl, with fl made of the lane-bit
+    // functions g = b4, b3, b3^b2, b2^b1, b2^b0 (b = bits of seg) of those
+    // FB halving moves: each halving move flips its own g between partners
+    // and leaves the later ones unchanged, so both partners keep their first
+    // half of slots and send the second, and no select is needed; the lane
+    // then holds functional fl, summed over the chain.
+    auto bit = [&](int b) { return (seg >> b) & 1; };
+    auto gfun = [&](int kind) {
+      return kind == 16 ? bit(4) : kind == 8 ? bit(3) : kind == 4 ? (bit(3) ^ bit(2))
+                                                      : kind == 2 ? (bit(2) ^ bit(1)) : (bit(2) ^ bit(0));
+    };
+    int fl = 0;
+#pragma unroll
+    for (int j = 0; j < FB; ++j) fl = (fl << 1) | gfun(S >> (j + 1));
+    auto mv = [&](auto kind_tag, double x) {
+      constexpr int KD = decltype(kind_tag)::value;
+      if constexpr (KD == 16) return __shfl_xor(x, 16, 64);
+      else if constexpr (KD == 8) return dpp_d<kDppRowMirror>(x);
+      else if constexpr (KD == 4) return dpp_d<kDppRowHalfMirror>(x);
+      else if constexpr (KD == 2) return dpp_d<kDppQuadXor2>(x);
+      else return dpp_d<kDppQuadXor1>(x);
+    };
 #pragma unroll
     for (int f0 = 0; f0 < kNumFunBC; f0 += NF) {
       double v[V];
@@ -1274,58 +1303,35 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
         if (rows_all(q)) {
           const int n = par + 2 * (r0 + q);
 #pragma unroll
-          for (int f = 0; f < NF; ++f) {
-            const double w = sW[(f0 + f) * NUP + n + (n >> 3)];
+          for (int fp = 0; fp < NF; ++fp) {
+            const double w = sW[(f0 + (fp ^ fl)) * NUP + n + (n >> 3)];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) v[f * 4 + k] = fma(w, X[q][k], v[f * 4 + k]);
+            for (int k = 0; k < 4; ++k) v[fp * 4 + k] = fma(w, X[q][k], v[fp * 4 + k]);
           }
+          // one row's weights in flight at a time (registers)
+          __builtin_amdgcn_sched_barrier(0);
         }
-      // one step at partner distance D (its DPP or LDS move): halve the
-      // entries held (h of them kept) or, down to one, add the partner's
-      auto step = [&](auto ctrl_tag, int h, bool upper) {
-        constexpr int CT_ = decltype(ctrl_tag)::value;
-        auto mv = [&](double x) {
-          if constexpr (CT_ < 0) return __shfl_xor(x, 16, 64);
-          else return dpp_d<CT_>(x);
-        };
-        if (h == 0) {
-          v[0] += mv(v[0]);
-          return;
-        }
+      // move J has partner distance S >> (J + 1)
+      auto move = [&](auto j_tag) {
+        constexpr int J = decltype(j_tag)::value;
+        using KT = std::integral_constant<int, (S >> (J + 1))>;
+        if constexpr (J < FB) {
+          constexpr int hh = V >> (J + 1);
 #pragma unroll
-        for (int i = 0; i < V / 2; ++i) {
-          if (i < h) {
-            const double snd = upper ? v[i] : v[h + i];
-            const double kp = upper ? v[h + i] : v[i];
-            v[i] = kp + mv(snd);
-          }
+          for (int i = 0; i < hh; ++i) v[i] += mv(KT{}, v[hh + i]);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] += mv(KT{}, v[k]);
         }
       };
-      using X16 = std::integral_constant<int, -1>;
-      using X8 = std::integral_constant<int, kDppRowMirror>;
-      using X4 = std::integral_constant<int, kDppRowHalfMirror>;
-      using X2 = std::integral_constant<int, kDppQuadXor2>;
-      using X1 = std::integral_constant<int, kDppQuadXor1>;
-      int h = V / 2;
-      if constexpr (S > 16) { step(X16{}, h, (seg & 16) != 0); h >>= 1; }
-      if constexpr (S > 8) { step(X8{}, h, (seg & 8) != 0); h >>= 1; }
-      if constexpr (S > 4) { step(X4{}, h, (seg & 4) != 0); h >>= 1; }
-      step(X2{}, h, (seg & 2) != 0);
-      h >>= 1;
-      step(X1{}, h, (seg & 1) != 0);
-      if constexpr (V >= S) {
-        constexpr int K = V / S;
+      move(std::integral_constant<int, 0>{});
+      move(std::integral_constant<int, 1>{});
+      if constexpr (LOGS > 2) move(std::integral_constant<int, 2>{});
+      if constexpr (LOGS > 3) move(std::integral_constant<int, 3>{});
+      if constexpr (LOGS > 4) move(std::integral_constant<int, 4>{});
+      if ((seg & ((S >> FB) - 1)) == 0) {
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-          const int e = seg * K + i;
-          my_fun[(f0 + (e >> 2)) * 5 + (e & 3)] = v[i];
-        }
-      } else {
-        constexpr int GS = S / V;
-        if (seg % GS == 0) {
-          const int e = seg / GS;
-          my_fun[(f0 + (e >> 2)) * 5 + (e & 3)] = v[0];
-        }
+        for (int k = 0; k < 4; ++k) my_fun[(f0 + fl) * 5 + k] = v[k];
       }
     }
 #pragma unroll
