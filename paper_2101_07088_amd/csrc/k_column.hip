@@ -818,6 +818,16 @@ __device__ __forceinline__ double dpp_d(double v) {
   return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// The same move with 1.0 where there is no source lane (or the row is masked
+// off): the identity of a product, so that a scan step needs no branch.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_one(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0x3FF00000, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // Decimation-in-time FFTs of the MB sequences of both buffers in lockstep
 // (input in bit-reversed order, output natural), with the padded row layout,
 // in passes of three radix-2 stages (two where the stage count requires);
@@ -833,8 +843,14 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
   // later stages are those of the first kind times -i and powers of
   // exp(-i pi / 4). The first pass maps consecutive threads to consecutive
   // groups of one sequence where that keeps its LDS accesses off shared banks.
-  auto pass8 = [&](int lh, bool gfast) {
+  // Element addresses: ix(k0 + e half, s) = base + e stride when the padding
+  // term (k >> PS) is linear in e, i.e. for half >= 2^PS (every pass after the
+  // first, half >= 8 >= 2^PS) and, in the first pass (half = 1, k0 a multiple
+  // of 8), for PS = 0 or PS >= 3.
+  auto pass8 = [&](auto first_tag, int lh, bool gfast) {
+    constexpr bool FIRST = decltype(first_tag)::value;
     constexpr int LG = LOGM - 3;  // groups per sequence: M / 8
+    if constexpr (FIRST) lh = 0;
     const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1, ts3 = ts1 >> 2;
     int s, b;
     if (gfast) {
@@ -846,12 +862,15 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
     }
     const int grp = b >> lh, pos = b & (half - 1);
     const int k0 = (grp << (lh + 3)) + pos;
+    constexpr bool kLin = !FIRST || PS == 0 || PS >= 3;
+    const int base = ix(k0, s), stride = half * MB + (half >> PS);
+    auto at = [&](int e) { return kLin ? base + e * stride : ix(k0 + e * half, s); };
     const C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
     C a[2][8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      a[0][e] = A[ix(k0 + e * half, s)];
-      a[1][e] = B[ix(k0 + e * half, s)];
+      a[0][e] = A[at(e)];
+      a[1][e] = B[at(e)];
     }
     const Rr r2 = (Rr)0.70710678118654752440;
     C w2m, w3e[4];  // w2 times -i; w3 times exp(-i pi e / 4)
@@ -864,7 +883,7 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
     w3e[2].y = -w3.x;
     w3e[3].x = r2 * (w3.y - w3.x);
     w3e[3].y = -r2 * (w3.x + w3.y);
-    if (sizeof(Rr) == 4 && lh == 0) {
+    if (sizeof(Rr) == 4 && FIRST) {
       // first pass: every twiddle is 1, -i or exp(-i pi e / 4) (no products
       // with table values; FP32 only, where the registers allow the second
       // code path)
@@ -927,29 +946,28 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
     }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      A[ix(k0 + e * half, s)] = a[0][e];
-      B[ix(k0 + e * half, s)] = a[1][e];
+      A[at(e)] = a[0][e];
+      B[at(e)] = a[1][e];
     }
     __syncthreads();
   };
   // radix-2^2 pass (stages lh, lh + 1), two groups per thread and buffer
   auto pass4 = [&](int lh) {
     constexpr int BPT4 = M * MB / 4 / NT;
-    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1;
+    const int half = 1 << lh, ts1 = (M >> 1) >> lh, ts2 = ts1 >> 1, st4 = half * MB + (half >> PS);
     C a[2][BPT4][4], w1[BPT4], w2[BPT4];
-    int k0[BPT4], s0[BPT4];
+    int k0[BPT4];
 #pragma unroll
     for (int q = 0; q < BPT4; ++q) {
       const int t = tid + q * NT, s = t & (MB - 1), b = t >> LOGMB;
       const int grp = b >> lh, pos = b & (half - 1);
-      k0[q] = (grp << (lh + 2)) + pos;
-      s0[q] = s;
+      k0[q] = ix((grp << (lh + 2)) + pos, s);  // half >= 8 >= 2^PS: base + e stride
       w1[q] = tw[pos * ts1];
       w2[q] = tw[pos * ts2];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        a[0][q][e] = A[ix(k0[q] + e * half, s)];
-        a[1][q][e] = B[ix(k0[q] + e * half, s)];
+        a[0][q][e] = A[k0[q] + e * st4];
+        a[1][q][e] = B[k0[q] + e * st4];
       }
     }
 #pragma unroll
@@ -967,10 +985,10 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
           u3.x = u3.y;
           u3.y = -re;
         }
-        buf[ix(k0[q], s0[q])] = cadd(b0, u2);
-        buf[ix(k0[q] + 2 * half, s0[q])] = csub(b0, u2);
-        buf[ix(k0[q] + half, s0[q])] = cadd(b1, u3);
-        buf[ix(k0[q] + 3 * half, s0[q])] = csub(b1, u3);
+        buf[k0[q]] = cadd(b0, u2);
+        buf[k0[q] + 2 * st4] = csub(b0, u2);
+        buf[k0[q] + st4] = cadd(b1, u3);
+        buf[k0[q] + 3 * st4] = csub(b1, u3);
       }
     }
     __syncthreads();
@@ -979,8 +997,9 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
   // in loops that are not unrolled: unrolled, their hoisted addresses cost
   // ~40 VGPRs)
   constexpr int n8 = LOGM == 7 ? 1 : LOGM / 3, n4 = (LOGM - 3 * n8) / 2;
+  pass8(std::true_type{}, 0, LOGS >= 4);
 #pragma nounroll
-  for (int p = 0; p < n8; ++p) pass8(3 * p, p == 0 && LOGS >= 4);
+  for (int p = 1; p < n8; ++p) pass8(std::false_type{}, 3 * p, false);
 #pragma nounroll
   for (int p = 0; p < n4; ++p) pass4(3 * n8 + 2 * p);
 }
@@ -1123,18 +1142,30 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     // inclusive scan of the segment maps d_end = P d_in + d over the chain:
     // within rows of 16 lanes by DPP row shifts, then across the two rows
     double Ps = P, Ds[5] = {d[0], d[1], d[2], d[3], d[4]};
+    // With 16 or 32 segments a lane takes a step exactly when the DPP move has
+    // a source lane for it (the rows of 16 lanes are chains or halves of
+    // one): lanes without one receive the identity map (P = 1, d = 0) and
+    // the step needs no branch.
     auto fstep = [&](auto ctrl_tag, int o, bool take, auto rows_tag) {
       constexpr int CT_ = decltype(ctrl_tag)::value, RM = decltype(rows_tag)::value;
-      const double pp = dpp_d<CT_, RM>(Ps);
       double dp[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) dp[k] = dpp_d<CT_, RM>(Ds[k]);
-      if (take) {
+      if constexpr (S >= 16) {
+        const double pp = dpp_one<CT_, RM>(Ps);
 #pragma unroll
         for (int k = 0; k < 5; ++k) Ds[k] = fma(Ps, dp[k], Ds[k]);
         Ps *= pp;
+      } else {
+        const double pp = dpp_d<CT_, RM>(Ps);
+        if (take) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) Ds[k] = fma(Ps, dp[k], Ds[k]);
+          Ps *= pp;
+        }
       }
       (void)o;
+      (void)take;
     };
     using I1 = std::integral_constant<int, kDppRowShr + 1>;
     using I2 = std::integral_constant<int, kDppRowShr + 2>;
@@ -1180,15 +1211,23 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     double Qs = Q, Xs[5] = {x[0], x[1], x[2], x[3], x[4]};
     auto bstep = [&](auto ctrl_tag, bool take) {
       constexpr int CT_ = decltype(ctrl_tag)::value;
-      const double qn = dpp_d<CT_>(Qs);
       double xn[5];
 #pragma unroll
       for (int k = 0; k < 5; ++k) xn[k] = dpp_d<CT_>(Xs[k]);
-      if (take) {
+      if constexpr (S >= 16) {  // as in the forward scan: no branch
+        const double qn = dpp_one<CT_>(Qs);
 #pragma unroll
         for (int k = 0; k < 5; ++k) Xs[k] = fma(Qs, xn[k], Xs[k]);
         Qs *= qn;
+      } else {
+        const double qn = dpp_d<CT_>(Qs);
+        if (take) {
+#pragma unroll
+          for (int k = 0; k < 5; ++k) Xs[k] = fma(Qs, xn[k], Xs[k]);
+          Qs *= qn;
+        }
       }
+      (void)take;
     };
     using J1 = std::integral_constant<int, kDppRowShl + 1>;
     using J2 = std::integral_constant<int, kDppRowShl + 2>;
