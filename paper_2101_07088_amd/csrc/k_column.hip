@@ -1058,26 +1058,35 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
 
   // 1. even extension of the node values in bit-reversed order (slot p takes
   //    node bitrev(p)), all global loads first, then the forward transforms
+  //    Thread tid takes slot rows (tid >> LOGMB) + q NT / MB, q < 8, so its
+  //    nodes are bitrev(tid >> LOGMB) * 8 + bitrev3(q); byte offsets fit 32
+  //    bits (N_z <= 257 nodes of at most 2^20 modes of 16 bytes). A mode
+  //    beyond the last (the last block's tail) loads the last mode's values:
+  //    its chains have no multipliers (zero solution) and it is never stored.
   {
     constexpr int kPer = KE / NT;
+    static_assert(kPer == 8 && (NT >> LOGMB) * kPer == M, "eight slot rows per thread");
+    const int mi_ld = min(m0 + (tid & (MB - 1)), nmodes - 1);
+    const int jb = bitrev(tid >> LOGMB, LOGM - 3) << 3;
+    const char* pi = reinterpret_cast<const char*>(fx_i);
+    const char* po = reinterpret_cast<const char*>(fx_o);
     C va[kPer], vb[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int t = tid + q * NT;
-      const int j = bitrev(t >> LOGMB, LOGM), m = t & (MB - 1), mi = m0 + m;
+      const int j = jb | (((q & 1) << 2) | (q & 2) | (q >> 2));
       const int c = j < N ? j : M - j;
-      va[q].x = 0; va[q].y = 0; vb[q].x = 0; vb[q].y = 0;
-      if (mi < nmodes) {
-        const size_t o = (size_t)c * nmodes + mi;
-        va[q] = fx_i[o];
-        if (in_band(g, c)) vb[q] = fx_o[o];
-      }
+      const unsigned off = (unsigned)(c * nmodes + mi_ld) * (unsigned)sizeof(C);
+      va[q] = *reinterpret_cast<const C*>(pi + off);
+      vb[q].x = 0;
+      vb[q].y = 0;
+      if (in_band(g, c)) vb[q] = *reinterpret_cast<const C*>(po + off);
     }
+    const int p0 = ix(tid >> LOGMB, tid & (MB - 1));
+    constexpr int kRowStep = (NT >> LOGMB) * MB + ((NT >> LOGMB) >> PS);  // ix of NT / MB rows further
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int t = tid + q * NT, p = ix(t >> LOGMB, t & (MB - 1));
-      A[p] = vb[q];
-      B[p] = va[q];
+      A[p0 + q * kRowStep] = vb[q];
+      B[p0 + q * kRowStep] = va[q];
     }
   }
   // 2. the chains. Lane (m, par, seg): rows r0 .. r0 + cnt - 1 of chain par
@@ -1285,18 +1294,14 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
   const double* sW = reinterpret_cast<const double*>(A);
   {
     __syncthreads();  // every lane has read its transform values
+    // thread n copies entry n of every row (one address, constant row offsets)
     double* dW = reinterpret_cast<double*>(A);
-    constexpr int kWq = (kNumFunBC * N + NT - 1) / NT;
-    double wv[kWq];
+    for (int n = tid; n < N; n += NT) {
+      double wv[kNumFunBC];
 #pragma unroll
-    for (int q = 0; q < kWq; ++q) {
-      const int i = tid + q * NT, f = i / N, n = i - f * N;
-      wv[q] = i < kNumFunBC * N ? W[f * NU + n] : 0.0;
-    }
+      for (int f = 0; f < kNumFunBC; ++f) wv[f] = W[f * NU + n];
 #pragma unroll
-    for (int q = 0; q < kWq; ++q) {
-      const int i = tid + q * NT, f = i / N, n = i - f * N;
-      if (i < kNumFunBC * N) dW[f * NUP + n + (n >> 3)] = wv[q];
+      for (int f = 0; f < kNumFunBC; ++f) dW[f * NUP + n + (n >> 3)] = wv[f];
     }
     __syncthreads();
   }
@@ -1565,7 +1570,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     auto sstep = [&](auto ctrl_tag, bool take) {
       constexpr int CT_ = decltype(ctrl_tag)::value;
       const double ur = dpp_d<CT_>(ar), ui = dpp_d<CT_>(ai);
-      if (take) {
+      if (S >= 16 || take) {  // 16 or 32 segments: lanes without a source add 0
         ar += ur;
         ai += ui;
       }
@@ -1640,12 +1645,12 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       ps_x += s_Ai[mm] * z;
       pz_x += s_Ai[mm];
     }
-    const size_t o = (size_t)j * nmodes + mo;
+    const unsigned off = (unsigned)(j * nmodes + mo) * (unsigned)sizeof(C);  // fits 32 bits, as the loads
     C a, b;
     a.x = (R)ps_x; a.y = (R)ps_y;
     b.x = (R)pz_x; b.y = (R)pz_y;
-    psi[o] = a;
-    psiz[o] = b;
+    *reinterpret_cast<C*>(reinterpret_cast<char*>(psi) + off) = a;
+    *reinterpret_cast<C*>(reinterpret_cast<char*>(psiz) + off) = b;
   }
 }
 
