@@ -72,6 +72,34 @@ def test_large_mixed_against_fp64(large):
     assert eF <= 1e-5 and efar <= 1e-5 and ephi <= 1e-5 and eU <= 1e-5
 
 
+def test_large_mixed_every_spread_shape(large):
+    """Every spreading shape the autotuner may choose on this grid (scatter,
+    gather, and the gather form with its sums on the matrix cores), in the
+    mixed path, against the FP64 path at the mixed bar; one plan, so the
+    kernels run after one another on LDS that earlier kernels wrote."""
+    import paper_2101_07088_amd as dp
+    p, pos, q, r64 = large
+    plan = dp.Plan(p, max_n=len(q), precision=dp.DPSE_MIXED)
+    tp = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    tried = []
+    for i in range(16):
+        try:
+            plan.set_tiles([i, -1, -1])
+        except dp.DpseError:
+            continue
+        U, phi, F = plan.solve(tp, tq)
+        assert plan.sync_status() == 0
+        eF = rel_rms(F.cpu().numpy(), r64["F"])
+        print(f"[large] spread shape {i}: mixed vs FP64 relRMS F {eF:.2e}", flush=True)
+        assert eF <= 1e-5, i
+        tried.append(i)
+    assert len(tried) >= 8
+    plan.close()
+    del tp, tq
+    torch.cuda.empty_cache()
+
+
 def test_large_near_field_sampled(large):
     import paper_2101_07088_amd as dp
     p, pos, q, r64 = large
