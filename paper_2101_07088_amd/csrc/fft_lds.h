@@ -21,6 +21,10 @@ __device__ inline C cmul(C a, C b) {
 
 __device__ inline int bitrev(int k, int logL) { return (int)(__brev((unsigned)k) >> (32 - logL)); }
 
+// Twiddle strides ts of the passes below are powers of two (L / (2 half) and
+// its halves), so pos * ts is taken as pos << ctz(ts): a shift by a uniform
+// amount instead of a per-lane 32-bit multiply.
+
 // nseq sequences of length L = 2^logL; element k of sequence s lives at
 // buf[s * ss + k * es]; input in bit-reversed order, output natural order.
 // tw[k] = exp(-2 pi i k / L) for k < L/2 (conjugated when inverse).
@@ -130,8 +134,8 @@ __device__ void fft_lds_r22(C* buf, int logL, int lognseq, int ss, int es, const
       else { b = t & (nb4 - 1); s = t >> lognb4; }
       const int grp = b >> lh, pos = b & (half - 1);
       base[q] = s * ss + ((grp << (lh + 2)) + pos) * es;
-      w1[q] = tw[pos * ts1];
-      w2[q] = tw[pos * ts2];
+      w1[q] = tw[pos << __builtin_ctz(ts1)];
+      w2[q] = tw[pos << __builtin_ctz(ts2)];
 #pragma unroll
       for (int e = 0; e < 4; ++e) a[q][e] = buf[base[q] + e * half * es];
     }
@@ -201,8 +205,8 @@ __device__ void fft_lds_r22_pair(C* buf0, C* buf1, int logL, int lognseq, int ss
       else { b = t & (nb4 - 1); s = t >> lognb4; }
       const int grp = b >> lh, pos = b & (half - 1);
       base[q] = s * ss + ((grp << (lh + 2)) + pos) * es;
-      w1[q] = tw[pos * ts1];
-      w2[q] = tw[pos * ts2];
+      w1[q] = tw[pos << __builtin_ctz(ts1)];
+      w2[q] = tw[pos << __builtin_ctz(ts2)];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         a[0][q][e] = buf0[base[q] + e * half * es];
@@ -299,7 +303,7 @@ __device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid
         v[e] = cadd(v[e], t);
       }
     } else {
-      C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+      C w1 = tw[pos << __builtin_ctz(ts1)], w2 = tw[pos << __builtin_ctz(ts2)], w3 = tw[pos << __builtin_ctz(ts3)];
       if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
       C w2m, w3e[4];
       w2m.x = sg * w2.y;
@@ -343,7 +347,7 @@ __device__ void fft_rows_r8(C* buf, int logN, const C* tw, bool inverse, int tid
       const int t = tid + q * NTHR, b = t & ((1 << lg) - 1), s = t >> lg;
       const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 2)) + pos;
       const int base = rowpad_ix(s, k0, N);
-      C x1 = tw[pos * ts1], x2 = tw[pos * ts2];
+      C x1 = tw[pos << __builtin_ctz(ts1)], x2 = tw[pos << __builtin_ctz(ts2)];
       if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
       C a[4];
 #pragma unroll
@@ -415,7 +419,7 @@ __device__ void fft_cols_r8(C* A, C* B, int logM, int logS, const C* tw, bool in
       b = t >> logS;
     }
     const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 3)) + pos;
-    C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+    C w1 = tw[pos << __builtin_ctz(ts1)], w2 = tw[pos << __builtin_ctz(ts2)], w3 = tw[pos << __builtin_ctz(ts3)];
     if (inverse) { w1.y = -w1.y; w2.y = -w2.y; w3.y = -w3.y; }
     const Rr r2 = (Rr)0.70710678118654752440;
     const Rr sg = inverse ? (Rr)-1 : (Rr)1;
@@ -475,7 +479,7 @@ __device__ void fft_cols_r8(C* A, C* B, int logM, int logS, const C* tw, bool in
     for (int q = 0; q < KE / (4 * NTHR); ++q) {
       const int t = tid + q * NTHR, s = t & (S - 1), b = t >> logS;
       const int grp = b >> lh, pos = b & (half - 1), k0 = (grp << (lh + 2)) + pos;
-      C x1 = tw[pos * ts1], x2 = tw[pos * ts2];
+      C x1 = tw[pos << __builtin_ctz(ts1)], x2 = tw[pos << __builtin_ctz(ts2)];
       if (inverse) { x1.y = -x1.y; x2.y = -x2.y; }
       constexpr int NB = PAIR ? 2 : 1;
 #pragma unroll

@@ -865,7 +865,7 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
     constexpr bool kLin = !FIRST || PS == 0 || PS >= 3;
     const int base = ix(k0, s), stride = half * MB + (half >> PS);
     auto at = [&](int e) { return kLin ? base + e * stride : ix(k0 + e * half, s); };
-    const C w1 = tw[pos * ts1], w2 = tw[pos * ts2], w3 = tw[pos * ts3];
+    const C w1 = tw[pos << __builtin_ctz(ts1)], w2 = tw[pos << __builtin_ctz(ts2)], w3 = tw[pos << __builtin_ctz(ts3)];
     C a[2][8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -962,8 +962,8 @@ __device__ __forceinline__ void fft_scan_pair(C* A, C* B, const C* tw, int tid) 
       const int t = tid + q * NT, s = t & (MB - 1), b = t >> LOGMB;
       const int grp = b >> lh, pos = b & (half - 1);
       k0[q] = ix((grp << (lh + 2)) + pos, s);  // half >= 8 >= 2^PS: base + e stride
-      w1[q] = tw[pos * ts1];
-      w2[q] = tw[pos * ts2];
+      w1[q] = tw[pos << __builtin_ctz(ts1)];
+      w2[q] = tw[pos << __builtin_ctz(ts2)];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         a[0][q][e] = A[k0[q] + e * st4];
@@ -1075,7 +1075,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
     for (int q = 0; q < kPer; ++q) {
       const int j = jb | (((q & 1) << 2) | (q & 2) | (q >> 2));
       const int c = j < N ? j : M - j;
-      const unsigned off = (unsigned)(c * nmodes + mi_ld) * (unsigned)sizeof(C);
+      const unsigned off = (__umul24((unsigned)c, (unsigned)nmodes) + (unsigned)mi_ld) * (unsigned)sizeof(C);
       va[q] = *reinterpret_cast<const C*>(pi + off);
       vb[q].x = 0;
       vb[q].y = 0;
@@ -1645,7 +1645,7 @@ __global__ void __launch_bounds__(kScanNT) k_column_scan(Geom g, const typename 
       ps_x += s_Ai[mm] * z;
       pz_x += s_Ai[mm];
     }
-    const unsigned off = (unsigned)(j * nmodes + mo) * (unsigned)sizeof(C);  // fits 32 bits, as the loads
+    const unsigned off = (__umul24((unsigned)j, (unsigned)nmodes) + (unsigned)mo) * (unsigned)sizeof(C);  // as the loads
     C a, b;
     a.x = (R)ps_x; a.y = (R)ps_y;
     b.x = (R)pz_x; b.y = (R)pz_y;

@@ -61,6 +61,19 @@ __device__ inline T pick3(const T (&a)[K], int s) {
   return s == 0 ? a[0] : (s == 1 ? a[1] : a[2]);
 }
 
+// Element at a 32-bit unsigned byte offset from a block-uniform base (the
+// offsets within a plane or a block's rows stay below 2^32 bytes): the load
+// or store then adds the offset to the scalar base, with no 64-bit address
+// arithmetic per lane.
+template <typename T>
+__device__ __forceinline__ T& at_b(T* base, unsigned byte_off) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ const T& at_b(const T* base, unsigned byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
 // R2C along x of the row ranges of J (rows of length Nx).
 template <typename R>
 __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R> J,
@@ -85,15 +98,16 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     // keeps off shared banks
     constexpr int kQ = kElems / 4 / kThreads;
     const int nq = Nx >> 2;
+    const R* inb = in + r_base * Nx;  // the block's rows: 32-bit offsets from here
     float4 v0[kQ], v1[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       const int gq = threadIdx.x + q * kThreads, s = gq >> (logN - 2), u = gq & (nq - 1);
-      const int64_t r = r_base + 2 * s;
+      const int o = ((2 * s) << logN) + 4 * u;
       v0[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       v1[q] = v0[q];
-      if (2 * s < nr) v0[q] = *reinterpret_cast<const float4*>(in + r * Nx + 4 * u);
-      if (2 * s + 1 < nr) v1[q] = *reinterpret_cast<const float4*>(in + (r + 1) * Nx + 4 * u);
+      if (2 * s < nr) v0[q] = at_b(reinterpret_cast<const float4*>(inb), (unsigned)o * 4u);
+      if (2 * s + 1 < nr) v1[q] = at_b(reinterpret_cast<const float4*>(inb), (unsigned)(o + Nx) * 4u);
     }
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -116,12 +130,13 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     // loads of the thread are issued before the LDS stores
     constexpr int kPer = kElems / kThreads;
     R v0[kPer], v1[kPer];
+    const R* inb = in + r_base * Nx;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int i = threadIdx.x + q * kThreads, s = i >> logN, x = bitrev(i & (Nx - 1), logN);
-      const int64_t r = r_base + 2 * s;
-      v0[q] = 2 * s < nr ? in[r * Nx + x] : (R)0;
-      v1[q] = 2 * s + 1 < nr ? in[(r + 1) * Nx + x] : (R)0;
+      const int o = ((2 * s) << logN) + x;
+      v0[q] = 2 * s < nr ? at_b(inb, (unsigned)o * (unsigned)sizeof(R)) : (R)0;
+      v1[q] = 2 * s + 1 < nr ? at_b(inb, (unsigned)(o + Nx) * (unsigned)sizeof(R)) : (R)0;
     }
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -144,9 +159,10 @@ __global__ void __launch_bounds__(kThreads) k_fft_x_r2c(Geom g, const FftJobs<R>
     a.y = (R)0.5 * (z.y + zc.y) * scale;
     b.x = (R)0.5 * (z.y - zc.y) * scale;
     b.y = (R)-0.5 * (z.x - zc.x) * scale;
-    int rl = 2 * s;
-    if (rl < nr) out[(r_base + rl) * nkx + k] = a;
-    if (rl + 1 < nr) out[(r_base + rl + 1) * nkx + k] = b;
+    const int rl = 2 * s;
+    C* outb = out + r_base * nkx;
+    if (rl < nr) at_b(outb, __umul24((unsigned)rl, (unsigned)nkx * (unsigned)sizeof(C)) + (unsigned)k * (unsigned)sizeof(C)) = a;
+    if (rl + 1 < nr) at_b(outb, __umul24((unsigned)(rl + 1), (unsigned)nkx * (unsigned)sizeof(C)) + (unsigned)k * (unsigned)sizeof(C)) = b;
   }
 }
 
@@ -201,12 +217,17 @@ __global__ void __launch_bounds__(kYThreads) k_fft_y(Geom g, const FftJobs<R> J,
   // on its own, so the reversal costs the loads nothing)
   const YMap<C, kPer> m(threadIdx.x, logN, logKB, ps);
   const bool valid = kb + m.kl < nkx;
-  C* base = data + (size_t)plane * Ny * nkx + kb + m.kl;
-  const C* src = base + (size_t)m.row_in * nkx;
+  // the plane's base (uniform), then 32-bit offsets within the plane
+  C* base = data + (size_t)plane * Ny * nkx;
+  const int col = kb + m.kl;
+  // byte offsets: row stride rs, the thread's first input and output rows
+  const unsigned rs = (unsigned)nkx * (unsigned)sizeof(C), rstep = (unsigned)m.step * rs;
+  const unsigned b_in = (unsigned)col * (unsigned)sizeof(C) + __umul24((unsigned)m.row_in, rs);
+  const unsigned b_out = (unsigned)col * (unsigned)sizeof(C) + __umul24((unsigned)m.row_out, rs);
   C v[kPer];
   if (valid) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) v[q] = src[(size_t)YMap<C, kPer>::rev(q) * nkx];
+    for (int q = 0; q < kPer; ++q) v[q] = at_b(base, b_in + (unsigned)YMap<C, kPer>::rev(q) * rs);
   } else {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) { v[q].x = 0; v[q].y = 0; }
@@ -216,9 +237,8 @@ __global__ void __launch_bounds__(kYThreads) k_fft_y(Geom g, const FftJobs<R> J,
   __syncthreads();
   fft_cols_r8<C, KE, kYThreads, false>(buf, nullptr, logN, logKB, tw, false, threadIdx.x);
   if (valid) {
-    C* dst = base + (size_t)m.row_out * nkx;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) dst[(size_t)q * m.step * nkx] = buf[m.lds0 + q * m.lds_step];
+    for (int q = 0; q < kPer; ++q) at_b(base, b_out + (unsigned)q * rstep) = buf[m.lds0 + q * m.lds_step];
   }
 }
 
@@ -249,12 +269,17 @@ __global__ void __launch_bounds__(kYThreads) k_ifft_y(Geom g, const typename CT<
   // reversal costs the loads nothing)
   const YMap<C, kPer> m(threadIdx.x, logN, logKB, ps);
   const bool valid = kb + m.kl < nkx;
-  const size_t off = (size_t)plane * Ny * nkx + kb + m.kl;
-  const size_t in0 = off + (size_t)m.row_in * nkx, out0 = off + (size_t)m.row_out * nkx;
+  // the plane's offset (uniform), then 32-bit offsets within the plane
+  const size_t poff = (size_t)plane * Ny * nkx;
+  const int col = kb + m.kl;
+  const unsigned rs = (unsigned)nkx * (unsigned)sizeof(C), rstep = (unsigned)m.step * rs;
+  const unsigned b_in = (unsigned)col * (unsigned)sizeof(C) + __umul24((unsigned)m.row_in, rs);
+  const unsigned b_out = (unsigned)col * (unsigned)sizeof(C) + __umul24((unsigned)m.row_out, rs);
   auto load = [&](C (&v)[kPer], const C* __restrict__ src) {
+    const C* sp = src + poff;
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) v[q] = src[in0 + (size_t)YMap<C, kPer>::rev(q) * nkx];
+      for (int q = 0; q < kPer; ++q) v[q] = at_b(sp, b_in + (unsigned)YMap<C, kPer>::rev(q) * rs);
     } else {
 #pragma unroll
       for (int q = 0; q < kPer; ++q) { v[q].x = 0; v[q].y = 0; }
@@ -276,9 +301,10 @@ __global__ void __launch_bounds__(kYThreads) k_ifft_y(Geom g, const typename CT<
     }
   };
   auto store = [&](C* dst) {
+    C* dp = dst + poff;
     if (valid) {
 #pragma unroll
-      for (int q = 0; q < kPer; ++q) dst[out0 + (size_t)q * m.step * nkx] = buf[m.lds0 + q * m.lds_step];
+      for (int q = 0; q < kPer; ++q) at_b(dp, b_out + (unsigned)q * rstep) = buf[m.lds0 + q * m.lds_step];
     }
   };
   C v[kPer];
@@ -315,6 +341,10 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   const int nr = (int)min((int64_t)nrow_blk, nrows - r_base);
   for (int i = threadIdx.x; i < Nx / 2; i += kThreads) tw[i] = twg[i];
   const double kxf = 2.0 * kPi / g.Lx;
+  // the block's rows (uniform bases), then 32-bit offsets
+  const C* p0b = p0 + r_base * nkx;
+  const C* pyb = py + r_base * nkx;
+  const C* pzb = pz + r_base * nkx;
   // the two sequences of row rl at wavenumber k (slot bitrev(k)), formed from
   // the stored half spectrum at kk = min(k, Nx - k) (conjugated for k > Nx/2):
   // z1 = phi_hat + i Ex_hat, z2 = Ey_hat + i Ez_hat, Ex_hat = -i kx phi_hat,
@@ -344,10 +374,10 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
       const int gq = threadIdx.x + q * kThreads, rl = gq >> (logN - 1), kk = gq & (hx - 1);
       la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
       if (rl < nr) {
-        const size_t o = (size_t)(r_base + rl) * nkx + kk;
-        la[q] = p0[o];
-        lb[q] = py[o];
-        lc[q] = pz[o];
+        const unsigned o = __umul24((unsigned)rl, (unsigned)nkx * (unsigned)sizeof(C)) + (unsigned)kk * (unsigned)sizeof(C);
+        la[q] = at_b(p0b, o);
+        lb[q] = at_b(pyb, o);
+        lc[q] = at_b(pzb, o);
       }
     }
 #pragma unroll
@@ -370,10 +400,10 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
       C a, b, c;
       a.x = 0; a.y = 0; b = a; c = a;
       if (rl < nr) {
-        const size_t o = (size_t)(r_base + rl) * nkx + hx;
-        a = p0[o];
-        b = py[o];
-        c = pz[o];
+        const unsigned o = __umul24((unsigned)rl, (unsigned)nkx * (unsigned)sizeof(C)) + (unsigned)hx * (unsigned)sizeof(C);
+        a = at_b(p0b, o);
+        b = at_b(pyb, o);
+        c = at_b(pzb, o);
       }
       C z1, z2;
       seqs(a, b, c, hx, false, z1, z2);
@@ -392,10 +422,10 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
       la[q].x = 0; la[q].y = 0; lb[q] = la[q]; lc[q] = la[q];
       if (rl < nr) {
         const int kk = k <= Nx / 2 ? k : Nx - k;
-        const size_t o = (size_t)(r_base + rl) * nkx + kk;
-        la[q] = p0[o];
-        lb[q] = py[o];
-        lc[q] = pz[o];
+        const unsigned o = __umul24((unsigned)rl, (unsigned)nkx * (unsigned)sizeof(C)) + (unsigned)kk * (unsigned)sizeof(C);
+        la[q] = at_b(p0b, o);
+        lb[q] = at_b(pyb, o);
+        lc[q] = at_b(pzb, o);
       }
     }
 #pragma unroll
@@ -411,13 +441,13 @@ __global__ void __launch_bounds__(kThreads) k_ifft_x_c2r(Geom g, const typename 
   __syncthreads();
   fft_rows_r8<C, kThreads>(buf, logN, tw, true, threadIdx.x);
   using V = typename std::conditional<sizeof(R) == 8, double4, float4>::type;
-  V* out = reinterpret_cast<V*>(u4);
+  V* out = reinterpret_cast<V*>(u4) + r_base * Nx;  // the block's rows: 32-bit offsets from here
   for (int i = threadIdx.x; i < nr * Nx; i += kThreads) {
     const int rl = i >> logN, x = i & (Nx - 1);
     C z1 = buf[rowpad_ix(2 * rl, x, Nx)], z2 = buf[rowpad_ix(2 * rl + 1, x, Nx)];
     V v;
     v.x = z1.x; v.y = z1.y; v.z = z2.x; v.w = z2.y;
-    out[(size_t)(r_base + rl) * Nx + x] = v;
+    at_b(out, (unsigned)i * (unsigned)sizeof(V)) = v;
   }
 }
 
