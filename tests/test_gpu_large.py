@@ -100,6 +100,27 @@ def test_large_mixed_every_spread_shape(large):
     torch.cuda.empty_cache()
 
 
+def test_large_fp64_gather_and_matrix_core_spreading(large):
+    """The FP64 path with the thread-per-column gather spreading and with its
+    matrix-core form, against the default FP64 solve (the same sums in
+    another order: 1e-12)."""
+    import paper_2101_07088_amd as dp
+    p, pos, q, r64 = large
+    plan = dp.Plan(p, max_n=len(q), precision=dp.DPSE_FP64)
+    tp = torch.tensor(pos, dtype=torch.float64, device="cuda")
+    tq = torch.tensor(q, dtype=torch.float64, device="cuda")
+    for i in (6, 12):
+        plan.set_tiles([i, -1, -1])
+        U, phi, F = plan.solve(tp, tq)
+        assert plan.sync_status() == 0
+        eF, ep = rel_rms(F.cpu().numpy(), r64["F"]), rel_rms(phi.cpu().numpy(), r64["phi"])
+        print(f"[large] FP64 spread shape {i}: relRMS F {eF:.2e} phi {ep:.2e} vs the default", flush=True)
+        assert eF <= 1e-12 and ep <= 1e-12, i
+    plan.close()
+    del tp, tq
+    torch.cuda.empty_cache()
+
+
 def test_large_near_field_sampled(large):
     import paper_2101_07088_amd as dp
     p, pos, q, r64 = large
